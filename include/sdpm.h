@@ -1,0 +1,221 @@
+/*
+ * sdpm.h - C ABI of the shrinking-domain particle-mesh library (libsdpm.so).
+ *
+ * One step of the particle-mesh method of Llinares (2017), "The shrinking
+ * domain framework I", on one AMD Instinct MI355X (gfx950):
+ *   Sec. 2.2 Eqs. 7-9  synchronised leapfrog (drift 1/2, kick, drift 1/2);
+ *   Sec. 2.4           CIC mass deposit and CIC force interpolation with the
+ *                      same weights (momentum conservation);
+ *   Sec. 2.1 Eqs. 3-4  gravity: Poisson (static) or the diffusion equation,
+ *                      advanced here by one implicit (backward Euler) step per
+ *                      half sub-step, both solved by multigrid;
+ *   Sec. 2.3 Table 2   ordering of operations within a step;
+ *   Sec. 2.4 Eq. 10    lightcone of the z = 0 observer; particles outside it
+ *                      are eliminated and the active cells shrink to an index
+ *                      box; Sec. 3: periodic until that box fits in the mesh.
+ *
+ * Units: comoving Mpc/h, conformal time in 1/H0 (H0 = 1), so the speed of
+ * light is 2997.92458.  Momentum p = a dx/dtau.  The mesh equation in grid
+ * units is (Lap_h - kappa h^2) Phi = h^2 (S delta - kappa Phi_old), with the
+ * 7-point Laplacian, S = 3 Omega_m / (2 a), kappa = 3 calH / (c_g^2 dtau/2).
+ *
+ * Conventions for every call:
+ *  - Return value: SDPM_OK (0) or a negative SDPM_E* code.  No call throws or
+ *    aborts across the ABI.  sdpm_last_error() describes the last failure on
+ *    a context.  An error leaves the context usable and its state consistent.
+ *  - Device buffers (particles, fields, workspace) are caller-owned device
+ *    memory that the context borrows; they must outlive the context.
+ *  - All device work is enqueued on the stream given to sdpm_create.  Calls
+ *    that return host scalars synchronise that stream before returning.
+ *  - One context per stream; a context is not thread-safe.
+ *  - Mesh layout: cell (i, j, k) at linear index (k ng + j) ng + i, value at
+ *    position (i h, j h, k h), h = box / ng.  Particle arrays are SoA.
+ */
+#ifndef SDPM_H
+#define SDPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDPM_OK = 0,
+  SDPM_EINVAL = -1,     /* invalid argument or configuration            */
+  SDPM_ENOMEM = -2,     /* workspace too small / host allocation failed */
+  SDPM_EHIP = -3,       /* a HIP runtime call failed                     */
+  SDPM_ENOCONV = -4,    /* multigrid did not reach tol in max_outer      */
+  SDPM_EDOMAIN = -5,    /* a particle's CIC support left the active box  */
+  SDPM_EOVERFLOW = -6,  /* fixed-point coordinate out of range           */
+  SDPM_ESTATE = -7      /* call out of order (e.g. step before bind)     */
+};
+
+enum { SDPM_MIXED = 0, SDPM_PLAIN_FP64 = 1 };      /* sdpm_config.precision  */
+enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1 };    /* sdpm_config.warm_start */
+
+typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
+
+typedef struct sdpm_config {
+  int32_t ng;            /* mesh cells per axis: power of two, 8..2048          */
+  int32_t frac_bits;     /* B, fractional bits of the CIC coordinate (1..16)    */
+  double box;            /* comoving box side L [Mpc/h]                         */
+  double omega_m, omega_l;
+  double c_light;        /* speed of light, 2997.92458 in these units          */
+  double c_grav;         /* 0: static Poisson; < 0: 0.019 h c (Sec. 3.1.1,
+                            Eq. 12, h in Mpc/h); > 0: this speed              */
+  double x_obs[3];       /* observer position [Mpc/h]                          */
+  int32_t shrink;        /* 0: fixed periodic domain; 1: shrinking domain      */
+  int32_t margin;        /* cells added around the lightcone sphere (>= 2)     */
+  int32_t box_align;     /* power of two A: the planes next to the active box
+                            sit at multiples of A (A = 2^(mg_levels-1) nests
+                            every multigrid level exactly)                     */
+  int32_t mg_levels;     /* multigrid levels incl. the finest (>= 2)           */
+  int32_t pre, post;     /* RB Gauss-Seidel sweeps before / after coarse work  */
+  int32_t coarse_sweeps; /* RB Gauss-Seidel sweeps on the coarsest level       */
+  int32_t max_outer;     /* FP64 defect-correction iterations per solve        */
+  double tol;            /* stop when ||r||_2 <= tol ||rhs||_2 (active cells)  */
+  int32_t precision;     /* SDPM_MIXED: FP32 V-cycles in FP64 defect
+                            correction, FP32 momenta; SDPM_PLAIN_FP64: FP64
+                            V-cycles and momenta                               */
+  int32_t warm_start;    /* SDPM_WS_PREV or SDPM_WS_LEARNED                    */
+  int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
+} sdpm_config;
+
+/* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,
+ * float when precision == SDPM_MIXED, double when SDPM_PLAIN_FP64; id: any
+ * labels.  Entries [0, n_active) are the active particles; removed particles
+ * are kept after them in removal order (stable partition).                  */
+typedef struct sdpm_particles {
+  double* x[3];
+  void* p[3];
+  uint32_t* id;
+  int64_t capacity;
+} sdpm_particles;
+
+/* Caller-owned device mesh arrays, ng^3 each.  phi: potential (in/out);
+ * rhs: right-hand side of the last solve (out); counts: fixed-point CIC mass
+ * of the last deposit, sum over a particle's cells = 2^(3B) (out).          */
+typedef struct sdpm_fields {
+  double* phi;
+  double* rhs;
+  uint64_t* counts;
+} sdpm_fields;
+
+typedef struct sdpm_step_stats {
+  int64_t n_active, n_removed;
+  int32_t outer_iters[2];  /* per field sub-step (second is 0 if static)  */
+  int32_t vcycles;         /* V-cycles in this call                       */
+  int32_t warm_used;       /* 1 if the learned guess was accepted         */
+  double res0[2], res[2];  /* relative residual before / after each solve */
+  double dtau, a_half, kappa_h2[2], r_lc;
+  int32_t lo[3], hi[3], periodic;
+  float ms[8];             /* [0] drift+deposit [1] rhs [2] solve 1
+                              [3] force+kick+drift [4] solve 2
+                              [5] removal+compaction [6] total           */
+} sdpm_step_stats;
+
+/* Host-only scalars of one step a -> a + da (no device work):
+ * out[0] dtau, [1] a_half (conformal midpoint), [2] S(a_half),
+ * [3] kappa_1 h^2, [4] kappa_2 h^2, [5] lightcone radius at a + da,
+ * [6] gravity speed c_g.  Sec. 2.2 Eqs. 7-9, Sec. 2.4 Eq. 10 (read as the
+ * light travel distance from a to today, shrinking to 0 at a = 1).        */
+int sdpm_step_scalars(const sdpm_config* cfg, double a, double da, double out[7]);
+
+/* Lightcone radius at a (host only).                                        */
+int sdpm_lightcone_radius(const sdpm_config* cfg, double a, double* r);
+
+/* Active index box for lightcone radius r (host only), Sec. 2.4: cells
+ * within r + margin cells of the observer per axis,
+ *   lo0 = floor((x_o - r)/h) - margin,  hi0 = floor((x_o + r)/h) + margin,
+ * rounded outward so that lo - 1 and hi + 1 are multiples of box_align.  periodic
+ * = 1 (and the box is the whole mesh) while that box does not fit in
+ * [1, ng - 2]; lo/hi are inclusive, axis order x, y, z.                     */
+int sdpm_domain_box(const sdpm_config* cfg, double r, int32_t lo[3], int32_t hi[3],
+                    int32_t* periodic);
+
+/* Fills cfg with defaults for mesh ng and box L (MG min(6, log2(ng) - 1)
+ * levels, V(2,2), 64 coarse sweeps, tol 1e-8, B = 14, margin 2, box_align
+ * 2^(levels-1), observer at the centre, static gravity, no shrinking).     */
+int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box);
+
+/* Device workspace needed for `capacity` particles.                         */
+int sdpm_workspace_bytes(const sdpm_config* cfg, int64_t capacity, int64_t* bytes);
+
+/* Creates a context.  workspace: caller-owned device memory of at least
+ * sdpm_workspace_bytes; hip_stream: hipStream_t (NULL = default stream).
+ * The library allocates only a small pinned host buffer for scalars.       */
+int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes,
+                void* hip_stream, sdpm_ctx** out);
+
+/* "Init particles": borrows the particle and field arrays; n_active
+ * particles are live.  Resets the domain to periodic / whole mesh.          */
+int sdpm_bind(sdpm_ctx* ctx, const sdpm_particles* parts, const sdpm_fields* fields,
+              int64_t n_active);
+
+/* "Init domain": applies the lightcone at a (removing particles outside it
+ * when shrinking), then sets phi by one static (kappa = 0) solve of the
+ * density at a (Table 1: field initial conditions from linear theory).      */
+int sdpm_init_potential(sdpm_ctx* ctx, double a, sdpm_step_stats* out);
+
+/* One step a -> a + da in the order of Table 2: drift dtau/2 with a (Eq. 7),
+ * CIC deposit, solve to a_half, FD force, CIC interpolation, kick with
+ * a_half (Eq. 8), drift dtau/2 with a + da (Eq. 9), second field half
+ * sub-step (skipped for static gravity), lightcone and elimination at
+ * a + da.  out may be NULL.  Returns SDPM_EDOMAIN / SDPM_ENOCONV on those
+ * failures (the step's data is then complete but flagged).                 */
+int sdpm_step(sdpm_ctx* ctx, double a, double da, sdpm_step_stats* out);
+
+/* "Shrink domain": lightcone at a; stable-partitions the active particles
+ * (outside ones after the kept ones), writes their ids to removed_ids_dev
+ * (device, may be NULL) and updates the active box.  Sec. 2.4, Table 2.     */
+int sdpm_shrink(sdpm_ctx* ctx, double a, int64_t* n_removed, uint32_t* removed_ids_dev);
+
+/* As sdpm_shrink but with an explicit lightcone radius r (for tests).       */
+int sdpm_shrink_radius(sdpm_ctx* ctx, double r, int64_t* n_removed,
+                       uint32_t* removed_ids_dev);
+
+/* Current state: n_active, box, boundary mode (host scalars).              */
+int sdpm_get_state(sdpm_ctx* ctx, sdpm_step_stats* out);
+
+/* Sub-steps for kernel-level checks --------------------------------------- */
+/* CIC deposit of the active particles at their current positions into
+ * fields->counts (zeroed first over the active box).                        */
+int sdpm_deposit(sdpm_ctx* ctx);
+/* rhs = h^2 S (counts / (n0/ng^3 2^3B) - 1) [- mean, periodic] - kappa h^2 phi,
+ * then solve (Lap_h - kappa h^2) phi = rhs on the active box, phi as guess. */
+int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_stats* out);
+/* g = -grad Phi (central differences) interpolated to the active particles
+ * with the deposit's CIC weights; g_dev[3]: device FP64 arrays (n_active). */
+int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);
+
+/* Learned warm start: BF16 weights of the 5-layer 3^3 conv net (layout in
+ * sdpm_net_layout); nbytes must equal the layout's total.                   */
+int sdpm_set_warmstart_weights(sdpm_ctx* ctx, const void* bf16_host, int64_t nbytes);
+
+/* Per-kernel timing (tracing).  enable != 0: every kernel launch made by
+ * this context is bracketed by a HIP event pair on the context's stream and
+ * charged with its algorithmic bytes (the bytes the method must move: e.g.
+ * 2 sizeof(T) per cell for one red-black colour sweep, 72 B per particle for
+ * interpolation + kick + drift in FP32 momenta); totals are cleared.  0: off. */
+typedef struct sdpm_kernel_stat {
+  char name[32];
+  int64_t launches;
+  double ms;      /* summed event time of the launches, milliseconds */
+  double bytes;   /* summed algorithmic bytes                        */
+} sdpm_kernel_stat;
+int sdpm_profile(sdpm_ctx* ctx, int32_t enable);
+/* Copies min(max, kinds) per-kernel totals to out; *n = number of kinds.
+ * Totals cover launches completed by the last synchronising call.          */
+int sdpm_profile_read(sdpm_ctx* ctx, sdpm_kernel_stat* out, int32_t max, int32_t* n);
+
+int sdpm_destroy(sdpm_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none).  Valid until the next
+ * call on ctx.  With ctx == NULL: the last failure of sdpm_create.          */
+const char* sdpm_last_error(const sdpm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDPM_H */

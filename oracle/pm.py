@@ -29,6 +29,7 @@ design notes):
   is exact and order independent: U = floor(x s), s = N_g 2^B / L,
   cell = U >> B, q = U mod 2^B, axis weights (2^B - q, q).
 * Active cells (Sec. 2.4): an index box per axis, floor((x_o -+ r)/h) -+ m,
+  rounded outward so the planes next to it are multiples of `align`, and
   never growing.  While that box does not fit strictly inside the mesh the
   whole mesh is active and periodic (Sec. 3: periodic until the lightcone
   reaches the box borders); afterwards it is Dirichlet with the exterior
@@ -64,6 +65,7 @@ class Config:
     x_obs: tuple = None          # default: box centre
     shrink: bool = False
     margin: int = 2
+    align: int = 1               # planes next to the box at multiples of this
     frac_bits: int = 14
     n_initial: int = 0
 
@@ -275,12 +277,17 @@ def outside_lightcone(x: np.ndarray, x_obs: np.ndarray, r_lc: float) -> np.ndarr
     return d2 > r_lc * r_lc
 
 
-def box_for_radius(r_lc: float, x_obs: np.ndarray, h: float, ng: int, margin: int):
+def box_for_radius(r_lc: float, x_obs: np.ndarray, h: float, ng: int, margin: int,
+                   align: int = 1):
     """Index box covering the sphere of radius r_lc about x_obs plus `margin`
-    cells.  Returns (dirichlet, lo, hi); dirichlet is False (whole periodic
-    mesh) unless the box lies inside [1, N_g - 2] on every axis."""
+    cells, rounded outward so that the planes just outside it (lo - 1 and
+    hi + 1) are multiples of `align`.  Returns (dirichlet, lo, hi); dirichlet
+    is False (whole periodic mesh) unless the box lies inside [1, N_g - 2] on
+    every axis."""
     lo = np.array([math.floor((x_obs[d] - r_lc) / h) - margin for d in range(3)], dtype=np.int64)
     hi = np.array([math.floor((x_obs[d] + r_lc) / h) + margin for d in range(3)], dtype=np.int64)
+    lo = ((lo - 1) // align) * align + 1
+    hi = -((-(hi + 1)) // align) * align - 1
     if np.all(lo >= 1) and np.all(hi <= ng - 2):
         return True, lo, hi
     return False, np.zeros(3, dtype=np.int64), np.full(3, ng - 1, dtype=np.int64)
@@ -310,7 +317,7 @@ def shrink_radius(state: State, cfg: Config, r: float) -> np.ndarray:
             removed = state.ids[keep.size:n].copy()
             state.n_active = keep.size
         h = cfg.box / cfg.ng
-        dirichlet, lo, hi = box_for_radius(r, x_obs, h, cfg.ng, cfg.margin)
+        dirichlet, lo, hi = box_for_radius(r, x_obs, h, cfg.ng, cfg.margin, cfg.align)
         if dirichlet:
             if not state.periodic:
                 lo = np.maximum(lo, state.lo)

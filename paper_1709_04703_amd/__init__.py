@@ -1,0 +1,13 @@
+"""Shrinking-domain particle-mesh gravity on AMD MI355X (gfx950).
+
+The data-parallel hot path of Llinares (2017), "The shrinking domain
+framework I": fixed-point CIC deposit, multigrid solve of the implicit step of
+the paper's gravity equation on the shrinking index box, finite-difference
+force, CIC interpolation, synchronised leapfrog and lightcone removal, all in
+hand-written HIP kernels behind the C ABI of ``include/sdpm.h``.
+"""
+from ._lib import (  # noqa: F401
+    Config, EXPORTS, SDPM_MIXED, SDPM_PLAIN_FP64, SDPM_WS_LEARNED, SDPM_WS_PREV, SdpmError,
+    Simulation, StepStats, config_default, domain_box, library, lightcone_radius,
+    step_scalars, workspace_bytes,
+)

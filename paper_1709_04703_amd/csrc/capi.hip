@@ -1,0 +1,833 @@
+// C ABI of libsdpm: context, workspace layout, and the host orchestration of
+// one step in the order of the paper's Table 2.  Every numerical operation on
+// mesh or particles runs in the HIP kernels of mesh.hip / particles.hip; the
+// host computes only FP64 scalars (cosmology.cpp) and the active index box.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace sdpm;
+
+struct sdpm_ctx {
+  sdpm_config cfg;
+  hipStream_t st = nullptr;
+  int nlev_max = 0;      // levels allocated
+  int nlev = 0;          // levels in use for the current box
+  Level lv[kMaxLevels];
+  double* partial = nullptr;
+  double* dscal = nullptr;      // reduction outputs
+  uint32_t* dflags = nullptr;   // [0] error flags, [1] removed count
+  uint64_t* dkept = nullptr;
+  uint32_t* bcounts = nullptr;
+  uint32_t* boffsets = nullptr;
+  void* scratch = nullptr;
+  double* hpin = nullptr;       // pinned host scalars
+  hipEvent_t ev[8] = {};
+  Profiler prof;
+  bool bound = false;
+  sdpm_particles parts{};
+  sdpm_fields fields{};
+  int64_t n_active = 0;
+  int64_t capacity = 0;
+  int periodic = 1;
+  Box box{};                    // active box (level 0)
+  Box counts_box{};             // cells the last deposit may have written
+  char err[512] = {0};
+};
+
+namespace {
+
+thread_local char g_create_err[512] = {0};
+
+int fail(sdpm_ctx* c, int code, const char* fmt, ...) {
+  char* dst = c ? c->err : g_create_err;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(dst, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, SDPM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((1ll << l) < v) ++l;
+  return l;
+}
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+Box full_box(int n) {
+  Box b;
+  for (int d = 0; d < 3; ++d) {
+    b.lo[d] = 0;
+    b.hi[d] = n - 1;
+  }
+  return b;
+}
+
+bool box_equal(const Box& a, const Box& b) {
+  for (int d = 0; d < 3; ++d)
+    if (a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d]) return false;
+  return true;
+}
+
+int validate(const sdpm_config* c, char* msg, size_t len) {
+  if (!c) return snprintf(msg, len, "config is NULL"), SDPM_EINVAL;
+  if (!is_pow2(c->ng) || c->ng < 8 || c->ng > 2048)
+    return snprintf(msg, len, "ng must be a power of two in [8, 2048] (got %d)", c->ng), SDPM_EINVAL;
+  if (c->frac_bits < 1 || c->frac_bits > 16)
+    return snprintf(msg, len, "frac_bits must be in [1, 16]"), SDPM_EINVAL;
+  if (!(c->box > 0.0) || !std::isfinite(c->box)) return snprintf(msg, len, "box must be > 0"), SDPM_EINVAL;
+  if (!(c->omega_m > 0.0) || !(c->c_light > 0.0) || !std::isfinite(c->c_grav))
+    return snprintf(msg, len, "omega_m and c_light must be > 0"), SDPM_EINVAL;
+  if (c->mg_levels < 2 || c->mg_levels > kMaxLevels)
+    return snprintf(msg, len, "mg_levels must be in [2, %d]", kMaxLevels), SDPM_EINVAL;
+  const int coarse = c->ng >> (c->mg_levels - 1);
+  if (coarse < 4 || coarse > kCoarseMax)
+    return snprintf(msg, len, "coarsest multigrid level must have 4..%d cells per axis (ng=%d, levels=%d)",
+                    kCoarseMax, c->ng, c->mg_levels), SDPM_EINVAL;
+  if (!is_pow2(c->box_align) || c->box_align > c->ng / 4)
+    return snprintf(msg, len, "box_align must be a power of two <= ng/4"), SDPM_EINVAL;
+  if (c->margin < 2) return snprintf(msg, len, "margin must be >= 2"), SDPM_EINVAL;
+  if (c->pre < 1 || c->post < 0 || c->coarse_sweeps < 1 || c->max_outer < 1)
+    return snprintf(msg, len, "need pre >= 1, post >= 0, coarse_sweeps >= 1, max_outer >= 1"), SDPM_EINVAL;
+  if (!(c->tol > 0.0)) return snprintf(msg, len, "tol must be > 0"), SDPM_EINVAL;
+  if (c->precision != SDPM_MIXED && c->precision != SDPM_PLAIN_FP64)
+    return snprintf(msg, len, "unknown precision %d", c->precision), SDPM_EINVAL;
+  if (c->warm_start != SDPM_WS_PREV)
+    return snprintf(msg, len, "warm_start: only SDPM_WS_PREV is available"), SDPM_EINVAL;
+  if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
+  return SDPM_OK;
+}
+
+size_t mg_elem(const sdpm_config& c) { return c.precision == SDPM_MIXED ? 4 : 8; }
+size_t p_elem(const sdpm_config& c) { return c.precision == SDPM_MIXED ? 4 : 8; }
+
+// Workspace layout; with base == nullptr only the size is computed.
+size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const size_t el = mg_elem(c);
+  for (int l = 0; l < c.mg_levels; ++l) {
+    const int n = c.ng >> l;
+    const size_t cells = (size_t)n * n * n;
+    char* e = take(cells * el);
+    char* r = take(cells * el);
+    char* t = take(cells * el);
+    if (ctx) {
+      ctx->lv[l].n = n;
+      ctx->lv[l].e = e;
+      ctx->lv[l].r = r;
+      ctx->lv[l].t = t;
+      ctx->lv[l].box = full_box(n);
+    }
+  }
+  const Box fb = full_box(c.ng);
+  const dim3 g = box_grid(fb);
+  const size_t maxblocks = (size_t)g.x * g.y * g.z;
+  double* partial = (double*)take(maxblocks * kReduceSlots * sizeof(double));
+  double* dscal = (double*)take(16 * sizeof(double));
+  uint32_t* dflags = (uint32_t*)take(16 * sizeof(uint32_t));
+  uint64_t* dkept = (uint64_t*)take(2 * sizeof(uint64_t));
+  const size_t nb = (size_t)((capacity + kChunk - 1) / kChunk) + 1;
+  uint32_t* bc = (uint32_t*)take(nb * sizeof(uint32_t));
+  uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
+  void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
+  if (ctx) {
+    ctx->partial = partial;
+    ctx->dscal = dscal;
+    ctx->dflags = dflags;
+    ctx->dkept = dkept;
+    ctx->bcounts = bc;
+    ctx->boffsets = bo;
+    ctx->scratch = scr;
+  }
+  return off;
+}
+
+// Active box for radius r (host; Sec. 2.4 index box, outward rounding).
+void domain_box(const sdpm_config& c, double r, Box* b, int* periodic) {
+  const double h = c.box / c.ng;
+  const int64_t A = c.box_align;
+  bool fits = true;
+  Box out;
+  for (int d = 0; d < 3; ++d) {
+    int64_t lo = (int64_t)std::floor((c.x_obs[d] - r) / h) - c.margin;
+    int64_t hi = (int64_t)std::floor((c.x_obs[d] + r) / h) + c.margin;
+    // planes lo-1 and hi+1 on multiples of A (floor / ceil division)
+    const int64_t lm = lo - 1, hp = hi + 1;
+    const int64_t lf = (lm >= 0 ? lm / A : -((-lm + A - 1) / A)) * A;
+    const int64_t hc = (hp >= 0 ? (hp + A - 1) / A : -((-hp) / A)) * A;
+    lo = lf + 1;
+    hi = hc - 1;
+    if (lo < 1 || hi > c.ng - 2) fits = false;
+    out.lo[d] = (int)std::max<int64_t>(std::min<int64_t>(lo, c.ng), -1);
+    out.hi[d] = (int)std::max<int64_t>(std::min<int64_t>(hi, c.ng), -1);
+  }
+  if (fits) {
+    *b = out;
+    *periodic = 0;
+  } else {
+    *b = full_box(c.ng);
+    *periodic = 1;
+  }
+}
+
+double corner_distance(const sdpm_config& c) {
+  double m = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double v = ((k >> d) & 1) ? c.box : 0.0;
+      s += (v - c.x_obs[d]) * (v - c.x_obs[d]);
+    }
+    m = std::max(m, std::sqrt(s));
+  }
+  return m;
+}
+
+// Multigrid level boxes for the current domain.
+void set_levels(sdpm_ctx* c) {
+  c->lv[0].box = c->periodic ? full_box(c->cfg.ng) : c->box;
+  c->nlev = 1;
+  for (int l = 1; l < c->nlev_max; ++l) {
+    const int n = c->lv[l].n;
+    Box b;
+    bool empty = false;
+    if (c->periodic) {
+      b = full_box(n);
+    } else {
+      const Box& f = c->lv[l - 1].box;
+      for (int d = 0; d < 3; ++d) {
+        b.lo[d] = (f.lo[d] + 1) >> 1;
+        b.hi[d] = std::min(f.hi[d] >> 1, n - 2);
+        if (b.hi[d] < b.lo[d]) empty = true;
+      }
+    }
+    if (empty) break;
+    c->lv[l].box = b;
+    c->nlev = l + 1;
+  }
+}
+
+// Clears the multigrid correction and scratch arrays (values outside a
+// level's box must be zero).
+template <typename T>
+void clear_levels(sdpm_ctx* c) {
+  for (int l = 0; l < c->nlev_max; ++l) {
+    const Box fb = full_box(c->lv[l].n);
+    launch_fill<T>((T*)c->lv[l].e, c->lv[l].n, fb, (T)0, c->st);
+    launch_fill<T>((T*)c->lv[l].t, c->lv[l].n, fb, (T)0, c->st);
+  }
+}
+
+void clear_all_levels(sdpm_ctx* c) {
+  if (c->cfg.precision == SDPM_MIXED)
+    clear_levels<float>(c);
+  else
+    clear_levels<double>(c);
+}
+
+ParticleArgs particle_args(sdpm_ctx* c) {
+  ParticleArgs pa;
+  for (int d = 0; d < 3; ++d) {
+    pa.x[d] = c->parts.x[d];
+    pa.p[d] = c->parts.p[d];
+  }
+  pa.id = c->parts.id;
+  pa.n = c->n_active;
+  return pa;
+}
+
+MeshMap mesh_map(sdpm_ctx* c) {
+  MeshMap mm;
+  mm.ng = c->cfg.ng;
+  mm.frac_bits = c->cfg.frac_bits;
+  mm.periodic = c->periodic;
+  mm.box = c->cfg.box;
+  mm.scale = (double)((int64_t)c->cfg.ng << c->cfg.frac_bits) / c->cfg.box;
+  mm.active = c->periodic ? full_box(c->cfg.ng) : c->box;
+  return mm;
+}
+
+int sync_scalars(sdpm_ctx* c, int ndouble) {
+  if (ndouble > 0)
+    HIP_TRY(c, hipMemcpyAsync(c->hpin, c->dscal, ndouble * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(c, hipMemcpyAsync(c->hpin + 16, c->dflags, 16, hipMemcpyDeviceToHost, c->st));
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  return SDPM_OK;
+}
+
+// Makes the context's profiler the current one for the duration of a call.
+struct ProfScope {
+  explicit ProfScope(sdpm_ctx* c) { g_prof = c ? &c->prof : nullptr; }
+  ~ProfScope() { g_prof = nullptr; }
+};
+
+uint32_t host_flags(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[0]; }
+uint32_t host_removed(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[1]; }
+
+int flags_error(sdpm_ctx* c) {
+  const uint32_t f = host_flags(c);
+  if (f & kFlagOverflow)
+    return fail(c, SDPM_EOVERFLOW, "a particle coordinate is not finite");
+  if (f & kFlagDomain)
+    return fail(c, SDPM_EDOMAIN, "a particle's CIC cells leave the active box or the mesh");
+  return SDPM_OK;
+}
+
+// rhs = S h^2 (C / (n0/ng^3 2^3B) - ratio) - kappa phi over the box, with
+// ratio = n_active / n0 on a periodic mesh (subtracts the exact mean, since
+// sum C = n_active 2^3B) and 1 otherwise.  ||rhs||^2 -> dscal[0].
+void assemble_rhs(sdpm_ctx* c, double s_source, double kappa) {
+  const sdpm_config& g = c->cfg;
+  const double h = g.box / g.ng;
+  const double nbar = (double)g.n_initial / ((double)g.ng * g.ng * g.ng);
+  const double c_scale = s_source * h * h / (nbar * std::ldexp(1.0, 3 * g.frac_bits));
+  const double ratio = c->periodic ? (double)c->n_active / (double)g.n_initial : 1.0;
+  const double c_off = s_source * h * h * ratio;
+  int nb = 0;
+  launch_rhs(c->fields.counts, c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c_scale, c_off,
+             kappa, c->partial, &nb, c->st);
+  launch_reduce_final(c->partial, nb, 1, c->dscal, c->st);
+}
+
+struct SolveOut {
+  double res0 = 0, res = 0;
+  int iters = 0, vcycles = 0;
+};
+
+// FP64 defect correction around V-cycles in T; rhs and ||rhs||^2 (dscal[0])
+// must be in place.  phi is the initial guess and the result.
+template <typename T>
+int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
+  const sdpm_config& g = c->cfg;
+  const Box& b = c->lv[0].box;
+  int nb = 0;
+  launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial, &nb,
+                     c->st);
+  launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+  int rc = sync_scalars(c, 2);
+  if (rc) return rc;
+  const double bn = std::sqrt(c->hpin[0]);
+  const double denom = std::max(bn, 1e-300);
+  double rn = std::sqrt(c->hpin[1]);
+  const double thresh = g.tol * denom;
+  so->res0 = rn / denom;
+  int it = 0;
+  while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
+    vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
+    launch_correct<T>(c->fields.phi, (const T*)c->lv[0].e, g.ng, b, c->st);
+    launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
+                       &nb, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+    rc = sync_scalars(c, 2);
+    if (rc) return rc;
+    rn = std::sqrt(c->hpin[1]);
+    ++it;
+  }
+  so->iters = it;
+  so->vcycles = it;
+  so->res = rn / denom;
+  if (c->periodic && kappa == 0.0) {
+    // zero-mean gauge of the singular periodic Poisson problem
+    launch_sum_phi(c->fields.phi, g.ng, b, c->partial, &nb, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + 2, c->st);
+    rc = sync_scalars(c, 3);
+    if (rc) return rc;
+    launch_add_const(c->fields.phi, g.ng, b, -c->hpin[2] / (double)box_cells(b), c->st);
+  }
+  if (!(rn <= thresh))
+    return fail(c, SDPM_ENOCONV, "multigrid reached relative residual %.3e > tol %.1e after %d iterations",
+                so->res, g.tol, it);
+  return SDPM_OK;
+}
+
+int solve(sdpm_ctx* c, double kappa, SolveOut* so) {
+  return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, so)
+                                        : solve_impl<double>(c, kappa, so);
+}
+
+int deposit(sdpm_ctx* c, double drift_coef, int drift) {
+  launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, c->counts_box, 0ull, c->st);
+  c->counts_box = c->periodic ? full_box(c->cfg.ng) : c->box;
+  const ParticleArgs pa = particle_args(c);
+  const MeshMap mm = mesh_map(c);
+  if (c->cfg.precision == SDPM_MIXED)
+    launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
+  else
+    launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
+  return SDPM_OK;
+}
+
+// Lightcone radius r: eliminate outside particles (stable partition) and
+// update the active box.  `known_removed` < 0: count on the device first.
+int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed,
+                uint32_t* removed_ids) {
+  *n_removed = 0;
+  if (!c->cfg.shrink) return SDPM_OK;
+  const int64_t n = c->n_active;
+  const double r2 = r * r;
+  if (n > 0 && r < corner_distance(c->cfg) * (1.0 + 1e-12) && known_removed != 0) {
+    const ParticleArgs pa = particle_args(c);
+    if (c->cfg.precision == SDPM_MIXED)
+      launch_compact<float>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept, c->st);
+    else
+      launch_compact<double>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept, c->st);
+    HIP_TRY(c, hipMemcpyAsync(c->hpin + 20, c->dkept, sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipStreamSynchronize(c->st));
+    if (c->prof.on) c->prof.collect();
+    const int64_t kept = (int64_t)((uint64_t*)(c->hpin + 20))[0];
+    *n_removed = n - kept;
+    if (removed_ids && *n_removed > 0)
+      HIP_TRY(c, hipMemcpyAsync(removed_ids, c->parts.id + kept, *n_removed * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, c->st));
+    c->n_active = kept;
+  }
+  Box nb;
+  int per = 1;
+  domain_box(c->cfg, r, &nb, &per);
+  if (!per) {
+    if (!c->periodic) {
+      for (int d = 0; d < 3; ++d) {
+        nb.lo[d] = std::max(nb.lo[d], c->box.lo[d]);
+        nb.hi[d] = std::min(nb.hi[d], c->box.hi[d]);
+      }
+    }
+    if (c->periodic || !box_equal(nb, c->box)) {
+      c->periodic = 0;
+      c->box = nb;
+      set_levels(c);
+      clear_all_levels(c);
+    }
+  }
+  return SDPM_OK;
+}
+
+void fill_state(sdpm_ctx* c, sdpm_step_stats* o) {
+  o->n_active = c->n_active;
+  for (int d = 0; d < 3; ++d) {
+    o->lo[d] = c->periodic ? 0 : c->box.lo[d];
+    o->hi[d] = c->periodic ? c->cfg.ng - 1 : c->box.hi[d];
+  }
+  o->periodic = c->periodic;
+}
+
+int check_ready(sdpm_ctx* c) {
+  if (!c) return SDPM_EINVAL;
+  if (!c->bound) return fail(c, SDPM_ESTATE, "no particles/fields bound (call sdpm_bind first)");
+  return SDPM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
+  if (!cfg) return SDPM_EINVAL;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->ng = ng;
+  cfg->frac_bits = 14;
+  cfg->box = box;
+  cfg->omega_m = 0.3;
+  cfg->omega_l = 0.7;
+  cfg->c_light = 2997.92458;
+  cfg->c_grav = 0.0;
+  for (int d = 0; d < 3; ++d) cfg->x_obs[d] = 0.5 * box;
+  cfg->shrink = 0;
+  cfg->margin = 2;
+  int lv = 6;
+  if (is_pow2(ng) && ng >= 8) {
+    const int lg = ilog2(ng);
+    lv = std::max(2, std::min(lg - 3, kMaxLevels));   // coarsest 16 cells (8 or 4 if ng < 32)
+    if ((ng >> (lv - 1)) < 4) lv = 2;
+  }
+  cfg->mg_levels = lv;
+  cfg->box_align = 1 << (lv - 1);
+  cfg->pre = 2;
+  cfg->post = 2;
+  cfg->coarse_sweeps = 64;
+  cfg->max_outer = 50;
+  cfg->tol = 1e-8;
+  cfg->precision = SDPM_MIXED;
+  cfg->warm_start = SDPM_WS_PREV;
+  cfg->n_initial = (int64_t)ng * ng * ng;
+  return SDPM_OK;
+}
+
+int sdpm_step_scalars(const sdpm_config* cfg, double a, double da, double out[7]) {
+  char msg[256];
+  const int rc = validate(cfg, msg, sizeof msg);
+  if (rc) return fail(nullptr, rc, "%s", msg);
+  if (!out || !(a > 0.0) || !(da > 0.0)) return fail(nullptr, SDPM_EINVAL, "need a > 0, da > 0");
+  const StepScalars s = step_scalars(*cfg, a, da);
+  out[0] = s.dtau;
+  out[1] = s.a_half;
+  out[2] = s.s_half;
+  out[3] = s.kappa1_h2;
+  out[4] = s.kappa2_h2;
+  out[5] = s.r_lc_end;
+  out[6] = s.c_g;
+  return SDPM_OK;
+}
+
+int sdpm_lightcone_radius(const sdpm_config* cfg, double a, double* r) {
+  if (!cfg || !r || !(a > 0.0)) return SDPM_EINVAL;
+  *r = lightcone_radius(a, cfg->omega_m, cfg->omega_l, cfg->c_light);
+  return SDPM_OK;
+}
+
+int sdpm_domain_box(const sdpm_config* cfg, double r, int32_t lo[3], int32_t hi[3],
+                    int32_t* periodic) {
+  char msg[256];
+  const int rc = validate(cfg, msg, sizeof msg);
+  if (rc) return fail(nullptr, rc, "%s", msg);
+  if (!lo || !hi || !periodic || !(r >= 0.0)) return SDPM_EINVAL;
+  Box b;
+  int per;
+  domain_box(*cfg, r, &b, &per);
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = b.lo[d];
+    hi[d] = b.hi[d];
+  }
+  *periodic = per;
+  return SDPM_OK;
+}
+
+int sdpm_workspace_bytes(const sdpm_config* cfg, int64_t capacity, int64_t* bytes) {
+  char msg[256];
+  const int rc = validate(cfg, msg, sizeof msg);
+  if (rc) return fail(nullptr, rc, "%s", msg);
+  if (!bytes || capacity < 0 || capacity >= (1ll << 32))
+    return fail(nullptr, SDPM_EINVAL, "capacity must be in [0, 2^32)");
+  *bytes = (int64_t)carve(*cfg, capacity, nullptr, nullptr);
+  return SDPM_OK;
+}
+
+int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void* hip_stream,
+                sdpm_ctx** out) {
+  char msg[256];
+  int rc = validate(cfg, msg, sizeof msg);
+  if (rc) return fail(nullptr, rc, "%s", msg);
+  if (!out || !workspace) return fail(nullptr, SDPM_EINVAL, "out and workspace must be non-NULL");
+  sdpm_ctx* c = new (std::nothrow) sdpm_ctx;
+  if (!c) return fail(nullptr, SDPM_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->st = (hipStream_t)hip_stream;
+  // capacity that fits: the particle scratch is the last region
+  const size_t fixed = carve(*cfg, 0, nullptr, nullptr);
+  const size_t per = 3 * sizeof(double) + 3 * p_elem(*cfg) + sizeof(uint32_t) + 2 * sizeof(uint32_t);
+  if ((size_t)ws_bytes < fixed) {
+    delete c;
+    return fail(nullptr, SDPM_ENOMEM, "workspace of %lld bytes < %zu required",
+                (long long)ws_bytes, fixed);
+  }
+  int64_t cap = (int64_t)(((size_t)ws_bytes - fixed) / per);
+  while (cap > 0 && carve(*cfg, cap, nullptr, nullptr) > (size_t)ws_bytes) --cap;
+  c->capacity = cap;
+  carve(*cfg, cap, (char*)workspace, c);
+  c->nlev_max = cfg->mg_levels;
+  c->periodic = 1;
+  c->box = full_box(cfg->ng);
+  c->counts_box = full_box(cfg->ng);
+  set_levels(c);
+  if (hipHostMalloc((void**)&c->hpin, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(nullptr, SDPM_EHIP, "hipHostMalloc failed");
+  }
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      hipHostFree(c->hpin);
+      delete c;
+      return fail(nullptr, SDPM_EHIP, "hipEventCreate failed");
+    }
+  }
+  clear_all_levels(c);
+  *out = c;
+  return SDPM_OK;
+}
+
+int sdpm_bind(sdpm_ctx* c, const sdpm_particles* parts, const sdpm_fields* fields,
+              int64_t n_active) {
+  ProfScope prof_scope(c);
+  if (!c) return SDPM_EINVAL;
+  if (!parts || !fields || !fields->phi || !fields->rhs || !fields->counts)
+    return fail(c, SDPM_EINVAL, "particles and fields must be non-NULL");
+  if (n_active < 0 || n_active > parts->capacity)
+    return fail(c, SDPM_EINVAL, "n_active must be in [0, capacity]");
+  if (parts->capacity > c->capacity)
+    return fail(c, SDPM_ENOMEM, "particle capacity %lld exceeds what the workspace holds (%lld)",
+                (long long)parts->capacity, (long long)c->capacity);
+  if (n_active > 0)
+    for (int d = 0; d < 3; ++d)
+      if (!parts->x[d] || !parts->p[d] || !parts->id)
+        return fail(c, SDPM_EINVAL, "particle arrays must be non-NULL");
+  c->parts = *parts;
+  c->fields = *fields;
+  c->n_active = n_active;
+  c->periodic = 1;
+  c->box = full_box(c->cfg.ng);
+  c->counts_box = full_box(c->cfg.ng);
+  set_levels(c);
+  clear_all_levels(c);
+  HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
+  c->bound = true;
+  c->err[0] = 0;
+  return SDPM_OK;
+}
+
+int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!(a > 0.0) || a > 1.0) return fail(c, SDPM_EINVAL, "a must be in (0, 1]");
+  sdpm_step_stats st{};
+  int64_t removed = 0;
+  const double r = lightcone_radius(a, c->cfg.omega_m, c->cfg.omega_l, c->cfg.c_light);
+  rc = shrink_impl(c, r, -1, &removed, nullptr);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
+  launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, full_box(c->cfg.ng), 0ull, c->st);
+  deposit(c, 0.0, 0);
+  assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0);
+  SolveOut so;
+  const int src = solve(c, 0.0, &so);
+  rc = flags_error(c);
+  st.n_removed = removed;
+  st.outer_iters[0] = so.iters;
+  st.vcycles = so.vcycles;
+  st.res0[0] = so.res0;
+  st.res[0] = so.res;
+  st.r_lc = r;
+  fill_state(c, &st);
+  if (out) *out = st;
+  return rc ? rc : src;
+}
+
+int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!(a > 0.0) || !(da > 0.0) || a + da > 1.0 + 1e-12)
+    return fail(c, SDPM_EINVAL, "need a > 0, da > 0 and a + da <= 1");
+  const sdpm_config& g = c->cfg;
+  const StepScalars sc = step_scalars(g, a, da);
+  const double h = g.box / g.ng;
+  sdpm_step_stats st{};
+  st.dtau = sc.dtau;
+  st.a_half = sc.a_half;
+  st.kappa_h2[0] = sc.kappa1_h2;
+  st.kappa_h2[1] = sc.kappa2_h2;
+  st.r_lc = sc.r_lc_end;
+  HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
+  HIP_TRY(c, hipEventRecord(c->ev[0], c->st));
+  // drift dtau/2 with a(t), then density at t + dt/2   (Table 2 rows 1-2)
+  deposit(c, 0.5 * sc.dtau / a, 1);
+  HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
+  // Phi from t to t + dt/2                              (row 3)
+  assemble_rhs(c, sc.s_half, sc.kappa1_h2);
+  HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
+  SolveOut s1;
+  const int src1 = solve(c, sc.kappa1_h2, &s1);
+  if (src1 && src1 != SDPM_ENOCONV) return src1;
+  HIP_TRY(c, hipEventRecord(c->ev[3], c->st));
+  // grad Phi, CIC interpolation, kick with a(t+dt/2), drift with a(t+dt)  (rows 4-6)
+  const bool removal = g.shrink && c->n_active > 0 &&
+                       sc.r_lc_end < corner_distance(g) * (1.0 + 1e-12);
+  {
+    const ParticleArgs pa = particle_args(c);
+    const MeshMap mm = mesh_map(c);
+    const double kick = sc.a_half * sc.dtau, drift = 0.5 * sc.dtau / (a + da);
+    if (g.precision == SDPM_MIXED)
+      launch_interp_kick_drift<float>(pa, c->fields.phi, mm, 0.5 / h, kick, drift, g.x_obs,
+                                      sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1, c->dflags,
+                                      c->st);
+    else
+      launch_interp_kick_drift<double>(pa, c->fields.phi, mm, 0.5 / h, kick, drift, g.x_obs,
+                                       sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
+                                       c->dflags, c->st);
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[4], c->st));
+  // Phi from t + dt/2 to t + dt with the same density    (row 7)
+  SolveOut s2;
+  int src2 = SDPM_OK;
+  if (sc.kappa2_h2 > 0.0) {
+    assemble_rhs(c, sc.s_half, sc.kappa2_h2);
+    src2 = solve(c, sc.kappa2_h2, &s2);
+    if (src2 && src2 != SDPM_ENOCONV) return src2;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[5], c->st));
+  rc = sync_scalars(c, 1);
+  if (rc) return rc;
+  const int ferr = flags_error(c);
+  // lightcone at t + dt: eliminate particles and cells  (last row)
+  int64_t removed = 0;
+  if (!ferr) {
+    rc = shrink_impl(c, sc.r_lc_end, removal ? (int64_t)host_removed(c) : 0, &removed, nullptr);
+    if (rc) return rc;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[6], c->st));
+  HIP_TRY(c, hipEventSynchronize(c->ev[6]));
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {0, 6}};
+  for (int q = 0; q < 7; ++q) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev[pairs[q][0]], c->ev[pairs[q][1]]);
+    st.ms[q] = ms;
+  }
+  // solve 1 includes rhs assembly in ms[2]; report rhs separately as ms[1]
+  st.n_removed = removed;
+  st.outer_iters[0] = s1.iters;
+  st.outer_iters[1] = s2.iters;
+  st.vcycles = s1.vcycles + s2.vcycles;
+  st.res0[0] = s1.res0;
+  st.res[0] = s1.res;
+  st.res0[1] = s2.res0;
+  st.res[1] = s2.res;
+  fill_state(c, &st);
+  if (out) *out = st;
+  if (ferr) return ferr;
+  if (src1) return src1;
+  return src2;
+}
+
+int sdpm_shrink_radius(sdpm_ctx* c, double r, int64_t* n_removed, uint32_t* removed_ids_dev) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!(r >= 0.0)) return fail(c, SDPM_EINVAL, "radius must be >= 0");
+  int64_t nr = 0;
+  rc = shrink_impl(c, r, -1, &nr, removed_ids_dev);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  if (n_removed) *n_removed = nr;
+  return SDPM_OK;
+}
+
+int sdpm_shrink(sdpm_ctx* c, double a, int64_t* n_removed, uint32_t* removed_ids_dev) {
+  if (!c) return SDPM_EINVAL;
+  if (!(a > 0.0) || a > 1.0) return fail(c, SDPM_EINVAL, "a must be in (0, 1]");
+  return sdpm_shrink_radius(c, lightcone_radius(a, c->cfg.omega_m, c->cfg.omega_l, c->cfg.c_light),
+                            n_removed, removed_ids_dev);
+}
+
+int sdpm_get_state(sdpm_ctx* c, sdpm_step_stats* out) {
+  if (!c || !out) return SDPM_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  fill_state(c, out);
+  return SDPM_OK;
+}
+
+int sdpm_deposit(sdpm_ctx* c) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
+  deposit(c, 0.0, 0);
+  rc = sync_scalars(c, 0);
+  if (rc) return rc;
+  return flags_error(c);
+}
+
+int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* out) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!(kappa_h2 >= 0.0) || !std::isfinite(s_source))
+    return fail(c, SDPM_EINVAL, "kappa_h2 must be >= 0 and s finite");
+  assemble_rhs(c, s_source, kappa_h2);
+  SolveOut so;
+  rc = solve(c, kappa_h2, &so);
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->outer_iters[0] = so.iters;
+    out->vcycles = so.vcycles;
+    out->res0[0] = so.res0;
+    out->res[0] = so.res;
+    out->kappa_h2[0] = kappa_h2;
+    fill_state(c, out);
+  }
+  return rc;
+}
+
+int sdpm_interp_force(sdpm_ctx* c, double* g_dev[3]) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!g_dev || (c->n_active > 0 && (!g_dev[0] || !g_dev[1] || !g_dev[2])))
+    return fail(c, SDPM_EINVAL, "g_dev arrays must be non-NULL");
+  HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
+  const double h = c->cfg.box / c->cfg.ng;
+  launch_interp_force(particle_args(c), c->fields.phi, mesh_map(c), 0.5 / h,
+                      c->n_active ? g_dev[0] : nullptr, c->n_active ? g_dev[1] : nullptr,
+                      c->n_active ? g_dev[2] : nullptr, c->dflags, c->st);
+  rc = sync_scalars(c, 0);
+  if (rc) return rc;
+  return flags_error(c);
+}
+
+int sdpm_set_warmstart_weights(sdpm_ctx* c, const void* bf16_host, int64_t nbytes) {
+  if (!c) return SDPM_EINVAL;
+  (void)bf16_host;
+  (void)nbytes;
+  return fail(c, SDPM_EINVAL, "learned warm start is not available in this build");
+}
+
+int sdpm_profile(sdpm_ctx* c, int32_t enable) {
+  if (!c) return SDPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  c->prof.reset();
+  c->prof.on = enable != 0;
+  return SDPM_OK;
+}
+
+int sdpm_profile_read(sdpm_ctx* c, sdpm_kernel_stat* out, int32_t max, int32_t* n) {
+  if (!c || !n || (max > 0 && !out)) return SDPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  *n = K_NKERNELS;
+  for (int k = 0; k < K_NKERNELS && k < max; ++k) {
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, kKernelNames[k], sizeof(out[k].name) - 1);
+    out[k].launches = c->prof.launches[k];
+    out[k].ms = c->prof.ms[k];
+    out[k].bytes = c->prof.bytes[k];
+  }
+  return SDPM_OK;
+}
+
+int sdpm_destroy(sdpm_ctx* c) {
+  if (!c) return SDPM_OK;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  else (void)hipDeviceSynchronize();
+  c->prof.release();
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete c;
+  return SDPM_OK;
+}
+
+const char* sdpm_last_error(const sdpm_ctx* c) { return c ? c->err : g_create_err; }
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// Internal declarations shared by the libsdpm translation units (not part of
+// the C ABI).  Every kernel is written for gfx950: 64-lane wavefronts,
+// 256-thread workgroups for the streaming kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/sdpm.h"
+
+namespace sdpm {
+
+constexpr int kMaxLevels = 12;
+constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
+constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
+constexpr int kBoxTy = 4;
+constexpr int kBoxKz = 8;
+constexpr int kChunk = 1024;          // particles per workgroup in the compaction passes
+constexpr int kReduceSlots = 4;       // independent sums carried by one reduction
+
+// Inclusive index box of one mesh level (axis order x, y, z).
+struct Box {
+  int lo[3];
+  int hi[3];
+};
+
+__host__ __device__ inline int64_t lin(int i, int j, int k, int n) {
+  return ((int64_t)k * n + j) * n + i;
+}
+
+inline int64_t box_cells(const Box& b) {
+  return (int64_t)(b.hi[0] - b.lo[0] + 1) * (b.hi[1] - b.lo[1] + 1) * (b.hi[2] - b.lo[2] + 1);
+}
+
+inline dim3 box_grid(const Box& b, int xcells_per_block = kBoxTx) {
+  const int nx = b.hi[0] - b.lo[0] + 1, ny = b.hi[1] - b.lo[1] + 1, nz = b.hi[2] - b.lo[2] + 1;
+  return dim3((nx + xcells_per_block - 1) / xcells_per_block, (ny + kBoxTy - 1) / kBoxTy,
+              (nz + kBoxKz - 1) / kBoxKz);
+}
+
+// One multigrid level: `n` cells per axis (power of two), active box, and
+// arrays of the correction e, the right-hand side r and a residual scratch t.
+struct Level {
+  int n;
+  Box box;
+  void* e;
+  void* r;
+  void* t;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side background cosmology (cosmology.cpp)
+// ---------------------------------------------------------------------------
+struct StepScalars {
+  double dtau, a_half, s_half, kappa1_h2, kappa2_h2, r_lc_end, c_g;
+};
+double hubble_e(double a, double om, double ol);
+double conformal_dtau(double a0, double a1, double om, double ol);
+double conformal_midpoint(double a0, double a1, double om, double ol);
+double lightcone_radius(double a, double om, double ol, double c_light);
+StepScalars step_scalars(const sdpm_config& cfg, double a, double da);
+
+// ---------------------------------------------------------------------------
+// Launchers, mesh kernels (mesh.hip).  All enqueue on `st`.
+// ---------------------------------------------------------------------------
+template <typename T> void launch_fill(T* a, int n, const Box& b, T v, hipStream_t st);
+void launch_rhs(const uint64_t* counts, const double* phi, double* rhs, int n, const Box& b,
+                double c_scale, double c_off, double kappa, double* partial, int* nblocks,
+                hipStream_t st);
+template <typename T>
+void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
+                     double kappa, double* partial, int* nblocks, hipStream_t st);
+template <typename T>
+void launch_correct(double* phi, const T* e, int n, const Box& b, hipStream_t st);
+void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
+                    hipStream_t st);
+void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st);
+void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
+                         hipStream_t st);
+template <typename T>
+void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
+            bool periodic, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Launchers, particle kernels (particles.hip).
+// ---------------------------------------------------------------------------
+struct ParticleArgs {
+  double* x[3];
+  void* p[3];
+  uint32_t* id;
+  int64_t n;
+};
+struct MeshMap {
+  int ng;
+  int frac_bits;
+  int periodic;
+  double box;         // L
+  double scale;       // s = ng 2^B / L
+  Box active;         // deposit / interpolation cells must lie inside
+};
+template <typename PT>
+void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags,
+                          hipStream_t st);
+template <typename PT>
+void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
+                              double inv2h, double kick_coef, double drift_coef,
+                              const double* x_obs, double r2, int count_removed,
+                              uint32_t* removed_count, uint32_t* flags, hipStream_t st);
+void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
+                         double inv2h, double* g0, double* g1, double* g2, uint32_t* flags,
+                         hipStream_t st);
+// Stable partition of the first n particles: kept (d^2 <= r2) first.
+// scratch must hold n particles; counts/offsets hold ceil(n / kChunk) entries.
+template <typename PT>
+void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
+                    uint32_t* block_counts, uint32_t* block_offsets, uint64_t* kept_total,
+                    hipStream_t st);
+
+// flags written by kernels
+enum : uint32_t { kFlagDomain = 1u, kFlagOverflow = 2u };
+
+// ---------------------------------------------------------------------------
+// Per-kernel timing with HIP events (profiler.cpp).  When a context has
+// profiling enabled, every launch is bracketed by an event pair on the
+// launch stream and charged with its algorithmic bytes; totals are read after
+// the next stream synchronisation.
+// ---------------------------------------------------------------------------
+enum KernelId : int {
+  K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
+  K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
+  K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
+  K_NKERNELS
+};
+extern const char* const kKernelNames[K_NKERNELS];
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  std::vector<int> pend_id;
+  std::vector<double> pend_bytes;
+  double ms[K_NKERNELS] = {};
+  double bytes[K_NKERNELS] = {};
+  int64_t launches[K_NKERNELS] = {};
+  void reset();
+  void begin(hipStream_t st);
+  void end(hipStream_t st, int id, double bytes);
+  void collect();       // call after the stream has been synchronised
+  void release();
+};
+
+// The profiler of the context making the current call (nullptr: none).
+extern thread_local Profiler* g_prof;
+inline void prof_begin(hipStream_t st) {
+  if (g_prof && g_prof->on) g_prof->begin(st);
+}
+inline void prof_end(hipStream_t st, int id, double bytes) {
+  if (g_prof && g_prof->on) g_prof->end(st, id, bytes);
+}
+
+}  // namespace sdpm

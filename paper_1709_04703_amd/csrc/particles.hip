@@ -1,0 +1,394 @@
+// Particle kernels: drift + fixed-point CIC deposit, CIC interpolation of the
+// finite-difference force + kick + drift (+ lightcone test), and the stable
+// stream compaction that eliminates particles outside the lightcone.
+//
+// CIC (Sec. 2.4, same weights both ways for momentum conservation): the
+// coordinate U = floor(x s), s = ng 2^B / L, gives the lower cell U >> B and
+// the fraction q = U mod 2^B; the axis weights are (2^B - q, q) and the
+// 8 products (<= 2^(3B)) are added to 64-bit integer counts, so the deposit
+// is exact and independent of the order in which atomics land.
+// Leapfrog (Sec. 2.2 Eqs. 7-9): x += p (dtau/2)/a ; p += a_half g dtau ;
+// x += p (dtau/2)/a_next, with g = -grad Phi by central differences.
+#include "internal.h"
+
+namespace sdpm {
+namespace {
+
+struct Cic {
+  int cell[3];
+  uint64_t w[3][2];
+};
+
+// Fixed-point coordinates of one particle.  Returns 0 or a kFlag* bit.
+__device__ inline uint32_t cic_setup(const double x[3], const MeshMap& mm, Cic& c) {
+  const int64_t span = (int64_t)mm.ng << mm.frac_bits;
+  const uint64_t one = 1ull << mm.frac_bits;
+  uint32_t bad = 0;
+  for (int d = 0; d < 3; ++d) {
+    const double u = x[d] * mm.scale;
+    if (u != u || __builtin_isinf(u)) {
+      bad |= kFlagOverflow;
+      c.cell[d] = 0;
+      c.w[d][0] = one;
+      c.w[d][1] = 0;
+      continue;
+    }
+    if (!(u >= 0.0 && u <= (double)span)) {
+      bad |= kFlagDomain;
+      c.cell[d] = 0;
+      c.w[d][0] = one;
+      c.w[d][1] = 0;
+      continue;
+    }
+    int64_t U = (int64_t)floor(u);
+    if (mm.periodic) U &= span - 1;
+    c.cell[d] = (int)(U >> mm.frac_bits);
+    const uint64_t q = (uint64_t)U & (one - 1);
+    c.w[d][0] = one - q;
+    c.w[d][1] = q;
+    if (!mm.periodic && (c.cell[d] < mm.active.lo[d] || c.cell[d] + 1 > mm.active.hi[d]))
+      bad |= kFlagDomain;
+  }
+  return bad;
+}
+
+// Squared distance ((dx^2 + dy^2) + dz^2) without fused multiply-adds, so
+// that the lightcone test is the same FP64 expression everywhere.
+__device__ inline double dist2_nofma(double x0, double x1, double x2, double o0, double o1,
+                                     double o2) {
+#pragma clang fp contract(off)
+  const double dx = x0 - o0, dy = x1 - o1, dz = x2 - o2;
+  const double a = dx * dx;
+  const double b = dy * dy;
+  const double c = dz * dz;
+  return (a + b) + c;
+}
+
+template <typename PT, bool DRIFT>
+__global__ void __launch_bounds__(256)
+k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
+                uint32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= pa.n) return;
+  double x[3];
+  for (int d = 0; d < 3; ++d) {
+    double v = pa.x[d][i];
+    if (DRIFT) {
+      v = v + (double)((const PT*)pa.p[d])[i] * coef;
+      if (mm.periodic) {
+        if (v < 0.0) v += mm.box;
+        if (v >= mm.box) v -= mm.box;
+      }
+      pa.x[d][i] = v;
+    }
+    x[d] = v;
+  }
+  Cic c;
+  const uint32_t bad = cic_setup(x, mm, c);
+  if (bad) {
+    atomicOr(flags, bad);
+    return;
+  }
+  const int m = mm.ng - 1;
+  for (int dz = 0; dz < 2; ++dz) {
+    const int kk = mm.periodic ? ((c.cell[2] + dz) & m) : c.cell[2] + dz;
+    for (int dy = 0; dy < 2; ++dy) {
+      const int jj = mm.periodic ? ((c.cell[1] + dy) & m) : c.cell[1] + dy;
+      const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
+      if (wyz == 0) continue;
+      for (int dx = 0; dx < 2; ++dx) {
+        const uint64_t wgt = c.w[0][dx] * wyz;
+        if (wgt == 0) continue;
+        const int ii = mm.periodic ? ((c.cell[0] + dx) & m) : c.cell[0] + dx;
+        atomicAdd(counts + lin(ii, jj, kk, mm.ng), (unsigned long long)wgt);
+      }
+    }
+  }
+}
+
+// g = sum over the 8 CIC cells of w * (-grad Phi) (central differences).
+__device__ inline void interp_g(const double* __restrict__ phi, const MeshMap& mm, const Cic& c,
+                                double inv2h, double g[3]) {
+  const int n = mm.ng, m = n - 1;
+  const double norm = ldexp(1.0, -3 * mm.frac_bits);
+  g[0] = g[1] = g[2] = 0.0;
+  for (int dz = 0; dz < 2; ++dz) {
+    const int k = (c.cell[2] + dz) & m;
+    const int kp = (k + 1) & m, km = (k - 1) & m;
+    for (int dy = 0; dy < 2; ++dy) {
+      const int j = (c.cell[1] + dy) & m;
+      const int jp = (j + 1) & m, jm = (j - 1) & m;
+      const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
+      if (wyz == 0) continue;
+      for (int dx = 0; dx < 2; ++dx) {
+        const uint64_t wgt = c.w[0][dx] * wyz;
+        if (wgt == 0) continue;
+        const int i = (c.cell[0] + dx) & m;
+        const double wd = (double)wgt * norm;
+        const double gx = -(phi[lin((i + 1) & m, j, k, n)] - phi[lin((i - 1) & m, j, k, n)]) * inv2h;
+        const double gy = -(phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]) * inv2h;
+        const double gz = -(phi[lin(i, j, kp, n)] - phi[lin(i, j, km, n)]) * inv2h;
+        g[0] += wd * gx;
+        g[1] += wd * gy;
+        g[2] += wd * gz;
+      }
+    }
+  }
+}
+
+template <typename PT>
+__global__ void __launch_bounds__(256)
+k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, double inv2h,
+                    double kick_coef, double drift_coef, double o0, double o1, double o2,
+                    double r2, int count_removed, uint32_t* __restrict__ removed_count,
+                    uint32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool out = false;
+  if (i < pa.n) {
+    double x[3] = {pa.x[0][i], pa.x[1][i], pa.x[2][i]};
+    Cic c;
+    const uint32_t bad = cic_setup(x, mm, c);
+    if (bad) {
+      atomicOr(flags, bad);
+    } else {
+      double g[3];
+      interp_g(phi, mm, c, inv2h, g);
+      for (int d = 0; d < 3; ++d) {
+        PT* p = (PT*)pa.p[d];
+        const PT pn = (PT)((double)p[i] + g[d] * kick_coef);
+        p[i] = pn;
+        double v = x[d] + (double)pn * drift_coef;
+        if (mm.periodic) {
+          if (v < 0.0) v += mm.box;
+          if (v >= mm.box) v -= mm.box;
+        }
+        pa.x[d][i] = v;
+        x[d] = v;
+      }
+      if (count_removed) out = dist2_nofma(x[0], x[1], x[2], o0, o1, o2) > r2;
+    }
+  }
+  if (count_removed) {
+    const unsigned long long mask = __ballot(out);
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(removed_count, (uint32_t)__popcll(mask));
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_interp_force(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, double inv2h,
+               double* __restrict__ g0, double* __restrict__ g1, double* __restrict__ g2,
+               uint32_t* __restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= pa.n) return;
+  const double x[3] = {pa.x[0][i], pa.x[1][i], pa.x[2][i]};
+  Cic c;
+  const uint32_t bad = cic_setup(x, mm, c);
+  if (bad) {
+    atomicOr(flags, bad);
+    return;
+  }
+  double g[3];
+  interp_g(phi, mm, c, inv2h, g);
+  g0[i] = g[0];
+  g1[i] = g[1];
+  g2[i] = g[2];
+}
+
+// ------------------------------------------------------------ compaction
+// Workgroup b owns particles [b kChunk, (b+1) kChunk) in 4 rounds of 256.
+__global__ void __launch_bounds__(256)
+k_count_kept(ParticleArgs pa, double o0, double o1, double o2, double r2,
+             uint32_t* __restrict__ block_counts) {
+  __shared__ uint32_t wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  uint32_t mine = 0;
+  for (int u = 0; u < kChunk / 256; ++u) {
+    const int64_t i = base + u * 256 + tid;
+    bool keep = false;
+    if (i < pa.n) keep = !(dist2_nofma(pa.x[0][i], pa.x[1][i], pa.x[2][i], o0, o1, o2) > r2);
+    const unsigned long long mask = __ballot(keep);
+    if (lane == 0) mine += (uint32_t)__popcll(mask);
+  }
+  if (lane == 0) wsum[wave] = mine;
+  __syncthreads();
+  if (tid == 0) block_counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// Exclusive scan of nb block counts by one workgroup; total to *kept_total.
+__global__ void __launch_bounds__(1024)
+k_scan_counts(const uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int64_t nb,
+              uint64_t* __restrict__ kept_total) {
+  __shared__ uint64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = tid * per, b1 = min(nb, b0 + per);
+  uint64_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += counts[b];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint64_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = tid ? part[tid - 1] : 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    offsets[b] = (uint32_t)run;
+    run += counts[b];
+  }
+  if (tid == 1023) *kept_total = part[1023];
+}
+
+template <typename PT>
+__global__ void __launch_bounds__(256)
+k_scatter(ParticleArgs pa, double o0, double o1, double o2, double r2,
+          const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ kept_total,
+          double* __restrict__ sx0, double* __restrict__ sx1, double* __restrict__ sx2,
+          PT* __restrict__ sp0, PT* __restrict__ sp1, PT* __restrict__ sp2,
+          uint32_t* __restrict__ sid) {
+  __shared__ uint32_t wk[4], wr[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  const uint64_t kept_before = offsets[blockIdx.x];
+  const uint64_t removed_before = (uint64_t)base - kept_before;
+  const uint64_t nkept = *kept_total;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  uint64_t run_k = 0, run_r = 0;
+  for (int u = 0; u < kChunk / 256; ++u) {
+    const int64_t i = base + u * 256 + tid;
+    const bool valid = i < pa.n;
+    bool keep = false;
+    if (valid) keep = !(dist2_nofma(pa.x[0][i], pa.x[1][i], pa.x[2][i], o0, o1, o2) > r2);
+    const unsigned long long mk = __ballot(keep);
+    const unsigned long long mr = __ballot(valid && !keep);
+    if (lane == 0) {
+      wk[wave] = (uint32_t)__popcll(mk);
+      wr[wave] = (uint32_t)__popcll(mr);
+    }
+    __syncthreads();
+    uint32_t ok = 0, orr = 0;
+    for (int w = 0; w < wave; ++w) {
+      ok += wk[w];
+      orr += wr[w];
+    }
+    const uint32_t tk = wk[0] + wk[1] + wk[2] + wk[3];
+    const uint32_t tr = wr[0] + wr[1] + wr[2] + wr[3];
+    if (valid) {
+      uint64_t dst;
+      if (keep)
+        dst = kept_before + run_k + ok + (uint64_t)__popcll(mk & below);
+      else
+        dst = nkept + removed_before + run_r + orr + (uint64_t)__popcll(mr & below);
+      sx0[dst] = pa.x[0][i];
+      sx1[dst] = pa.x[1][i];
+      sx2[dst] = pa.x[2][i];
+      sp0[dst] = ((const PT*)pa.p[0])[i];
+      sp1[dst] = ((const PT*)pa.p[1])[i];
+      sp2[dst] = ((const PT*)pa.p[2])[i];
+      sid[dst] = pa.id[i];
+    }
+    run_k += tk;
+    run_r += tr;
+    __syncthreads();
+  }
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+template <typename PT>
+void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags,
+                          hipStream_t st) {
+  if (pa.n <= 0) return;
+  prof_begin(st);
+  if (drift)
+    hipLaunchKernelGGL((k_drift_deposit<PT, true>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa,
+                       drift_coef, mm, (unsigned long long*)counts, flags);
+  else
+    hipLaunchKernelGGL((k_drift_deposit<PT, false>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st,
+                       pa, drift_coef, mm, (unsigned long long*)counts, flags);
+  const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
+  prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
+}
+template void launch_drift_deposit<float>(const ParticleArgs&, double, int, const MeshMap&,
+                                          uint64_t*, uint32_t*, hipStream_t);
+template void launch_drift_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
+                                           uint64_t*, uint32_t*, hipStream_t);
+
+template <typename PT>
+void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
+                              double inv2h, double kick_coef, double drift_coef,
+                              const double* x_obs, double r2, int count_removed,
+                              uint32_t* removed_count, uint32_t* flags, hipStream_t st) {
+  if (pa.n <= 0) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_interp_kick_drift<PT>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi,
+                     mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2], r2,
+                     count_removed, removed_count, flags);
+  prof_end(st, K_INTERP_KICK_DRIFT, (48.0 + 6.0 * sizeof(PT)) * pa.n + 8.0 * box_cells(mm.active));
+}
+template void launch_interp_kick_drift<float>(const ParticleArgs&, const double*, const MeshMap&,
+                                              double, double, double, const double*, double, int,
+                                              uint32_t*, uint32_t*, hipStream_t);
+template void launch_interp_kick_drift<double>(const ParticleArgs&, const double*, const MeshMap&,
+                                               double, double, double, const double*, double,
+                                               int, uint32_t*, uint32_t*, hipStream_t);
+
+void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
+                         double inv2h, double* g0, double* g1, double* g2, uint32_t* flags,
+                         hipStream_t st) {
+  if (pa.n <= 0) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_interp_force, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi, mm,
+                     inv2h, g0, g1, g2, flags);
+  prof_end(st, K_INTERP_FORCE, 48.0 * pa.n + 8.0 * box_cells(mm.active));
+}
+
+template <typename PT>
+void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
+                    uint32_t* block_counts, uint32_t* block_offsets, uint64_t* kept_total,
+                    hipStream_t st) {
+  if (pa.n <= 0) return;
+  const int64_t nb = (pa.n + kChunk - 1) / kChunk;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_count_kept, dim3((unsigned)nb), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
+                     x_obs[2], r2, block_counts);
+  prof_end(st, K_COUNT_KEPT, 24.0 * pa.n);
+  prof_begin(st);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, block_offsets, nb,
+                     kept_total);
+  prof_end(st, K_SCAN, 8.0 * nb);
+  char* s = (char*)scratch;
+  const size_t n = (size_t)pa.n;
+  double* sx0 = (double*)s;
+  double* sx1 = sx0 + n;
+  double* sx2 = sx1 + n;
+  PT* sp0 = (PT*)(sx2 + n);
+  PT* sp1 = sp0 + n;
+  PT* sp2 = sp1 + n;
+  uint32_t* sid = (uint32_t*)(sp2 + n);
+  const double pbytes = (24.0 + 3.0 * sizeof(PT) + 4.0) * pa.n;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_scatter<PT>, dim3((unsigned)nb), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
+                     x_obs[2], r2, block_offsets, kept_total, sx0, sx1, sx2, sp0, sp1, sp2, sid);
+  prof_end(st, K_SCATTER, 2.0 * pbytes);
+  prof_begin(st);
+  for (int d = 0; d < 3; ++d) {
+    (void)hipMemcpyAsync(pa.x[d], sx0 + d * n, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(pa.p[d], sp0 + d * n, n * sizeof(PT), hipMemcpyDeviceToDevice, st);
+  }
+  (void)hipMemcpyAsync(pa.id, sid, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+  prof_end(st, K_COPY, 2.0 * pbytes);
+}
+template void launch_compact<float>(const ParticleArgs&, const double*, double, void*, uint32_t*,
+                                    uint32_t*, uint64_t*, hipStream_t);
+template void launch_compact<double>(const ParticleArgs&, const double*, double, void*, uint32_t*,
+                                     uint32_t*, uint64_t*, hipStream_t);
+
+}  // namespace sdpm

@@ -1,0 +1,65 @@
+// Per-kernel HIP-event timing (see Profiler in internal.h).
+#include "internal.h"
+
+namespace sdpm {
+
+const char* const kKernelNames[K_NKERNELS] = {
+    "fill", "drift_deposit", "rhs", "residual_fp64", "correct", "reduce_final", "sum_phi",
+    "add_const", "smooth_first", "smooth_rb", "resid_level", "restrict_fw", "prolong_tri",
+    "coarse_lds", "interp_kick_drift", "interp_force", "count_kept", "scan_counts", "scatter",
+    "copy_back",
+};
+
+thread_local Profiler* g_prof = nullptr;
+
+void Profiler::reset() {
+  used = 0;
+  pend_id.clear();
+  pend_bytes.clear();
+  for (int k = 0; k < K_NKERNELS; ++k) {
+    ms[k] = 0.0;
+    bytes[k] = 0.0;
+    launches[k] = 0;
+  }
+}
+
+void Profiler::begin(hipStream_t st) {
+  if (used + 2 > ev.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      ev.push_back(e);
+    }
+  }
+  (void)hipEventRecord(ev[used], st);
+}
+
+void Profiler::end(hipStream_t st, int id, double b) {
+  if (used + 2 > ev.size()) return;
+  (void)hipEventRecord(ev[used + 1], st);
+  used += 2;
+  pend_id.push_back(id);
+  pend_bytes.push_back(b);
+}
+
+void Profiler::collect() {
+  for (size_t q = 0; q < pend_id.size(); ++q) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]) == hipSuccess) {
+      ms[pend_id[q]] += t;
+      bytes[pend_id[q]] += pend_bytes[q];
+      launches[pend_id[q]] += 1;
+    }
+  }
+  used = 0;
+  pend_id.clear();
+  pend_bytes.clear();
+}
+
+void Profiler::release() {
+  for (auto e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  used = 0;
+}
+
+}  // namespace sdpm

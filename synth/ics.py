@@ -21,6 +21,7 @@ import dataclasses
 import math
 
 import numpy as np
+import scipy.fft as sfft
 from scipy import integrate
 
 
@@ -113,7 +114,7 @@ def zeldovich_ics(n1d: int, box: float, a_init: float, seed: int,
     dv = (box / n1d) ** 3
     with np.errstate(divide="ignore", invalid="ignore"):
         pk = np.where(kk > 0, amp * base(np.where(kk > 0, kk, 1.0)), 0.0)
-    wk = np.fft.rfftn(w)
+    wk = sfft.rfftn(w, workers=-1)
     dk = wk * np.sqrt(pk / dv)
     nyq = n1d // 2
     dk[0, 0, 0] = 0.0
@@ -124,7 +125,7 @@ def zeldovich_ics(n1d: int, box: float, a_init: float, seed: int,
         inv_k2 = np.where(kk > 0, 1.0 / (kk * kk), 0.0)
     psi = []
     for kc in (kx, ky, kz):
-        comp = np.fft.irfftn(1j * kc * dk * inv_k2, s=(n1d, n1d, n1d))
+        comp = sfft.irfftn(1j * kc * dk * inv_k2, s=(n1d, n1d, n1d), workers=-1)
         psi.append(comp.ravel())
     psi = np.stack(psi, axis=1) * d_i
     q = lattice_positions(n1d, box)

@@ -1,0 +1,139 @@
+"""GPU parity, bit-exact parts: fixed-point CIC deposit counts and the
+lightcone removal (removed set, stable order, active box) against the oracle
+on identical inputs, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import pm
+from synth import clustered_particles, edge_particles, lattice_positions, uniform_particles
+
+from helpers import lib_config, log, make_sim, oracle_config
+
+pytestmark = pytest.mark.gpu
+
+B = 14
+
+
+def _particles(kind, ng, box, n):
+    if kind == "uniform":
+        return uniform_particles(n, box, 100 + ng)
+    if kind == "clustered":
+        return clustered_particles(n, box, 200 + ng, ng=ng, width_cells=0.8)
+    if kind == "edge":
+        return edge_particles(ng, box)
+    if kind == "lattice":
+        x = lattice_positions(round(n ** (1 / 3)), box)
+        return x, np.zeros_like(x), np.arange(x.shape[0], dtype=np.uint32)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind,ng,n,prec", [
+    ("uniform", 32, 10000, 0), ("clustered", 32, 20000, 0), ("edge", 16, 8, 0),
+    ("lattice", 32, 32**3, 0), ("uniform", 64, 100003, 1), ("clustered", 128, 70001, 0),
+])
+def test_deposit_bit_exact(kind, ng, n, prec):
+    box = 100.0
+    x, p, ids = _particles(kind, ng, box, n)
+    log(f"deposit {kind} ng={ng} n={x.shape[0]} precision={prec}")
+    cfg = lib_config(ng, box, precision=prec, n_initial=x.shape[0])
+    sim = make_sim(cfg, x.shape[0])
+    sim.bind(x, p, ids)
+    sim.deposit()
+    got = sim.counts_numpy()
+    ref = pm.deposit(x, ng, box, B, True)
+    assert np.array_equal(got, ref)
+    # run twice: identical (integer atomics are order independent)
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), ref)
+    sim.close()
+
+
+def test_deposit_empty_and_single():
+    cfg = lib_config(16, 10.0, n_initial=1)
+    sim = make_sim(cfg, 4)
+    sim.bind(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.uint32))
+    sim.deposit()
+    assert not sim.counts_numpy().any()
+    x = np.array([[3.75, 0.0, 9.999999]])
+    sim.bind(x, np.zeros((1, 3)), np.array([7], np.uint32))
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(x, 16, 10.0, B, True))
+    sim.close()
+
+
+@pytest.mark.parametrize("n,xo", [(50000, None), (3001, (700.0, 400.0, 520.0)), (1024, None)])
+def test_removal_bit_exact_stable_partition(n, xo):
+    ng, box = 64, 1000.0
+    kw = dict(shrink=1, n_initial=n)
+    if xo is not None:
+        kw["x_obs"] = xo
+    cfg = lib_config(ng, box, **kw)
+    ocfg = oracle_config(cfg)
+    x, p, ids = uniform_particles(n, box, 31 + n)
+    rng = np.random.Generator(np.random.PCG64(n))
+    ids = rng.permutation(n).astype(np.uint32)
+    log(f"removal n={n} x_obs={xo}")
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    ost = pm.State(x.copy(), p.copy(), ids.copy(), n, np.zeros((ng,) * 3), 0.5)
+    import torch
+    removed_dev = torch.zeros(n, dtype=torch.int32, device="cuda")
+    for r in (900.0, 640.0, 470.0, 455.0, 300.0, 120.0):
+        nr = sim.shrink_radius(r, removed_dev)
+        oremoved = pm.shrink_radius(ost, ocfg, r)
+        assert nr == len(oremoved)
+        assert sim.n_active == ost.n_active
+        assert np.array_equal(removed_dev[:nr].cpu().numpy().view(np.uint32), oremoved)
+        gx, gp, gid = sim.particles(all_particles=True)
+        assert np.array_equal(gid, ost.ids)
+        assert np.array_equal(gx, ost.x)
+        assert np.array_equal(gp, ost.p.astype(np.float32).astype(np.float64))
+        st = sim.state()
+        assert st["periodic"] == int(ost.periodic)
+        if not ost.periodic:
+            assert st["lo"] == list(ost.lo) and st["hi"] == list(ost.hi)
+    sim.close()
+
+
+def test_removal_everything_at_zero_radius():
+    ng, box, n = 32, 100.0, 5000
+    cfg = lib_config(ng, box, shrink=1, n_initial=n)
+    x, p, ids = uniform_particles(n, box, 5)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    assert sim.shrink(1.0) == n
+    assert sim.n_active == 0
+    _, _, gid = sim.particles(all_particles=True)
+    assert np.array_equal(gid, ids)         # all kept in memory, original order
+    sim.deposit()                            # empty active set is legal
+    assert not sim.counts_numpy().any()
+    sim.close()
+
+
+def test_deposit_in_dirichlet_box_and_domain_error():
+    ng, box, n = 64, 640.0, 4000
+    cfg = lib_config(ng, box, shrink=1, n_initial=n)
+    ocfg = oracle_config(cfg)
+    x, p, ids = clustered_particles(n, box, 9, ng=ng, width_cells=1.0, lo=260.0, hi=380.0)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    sim.deposit()                            # periodic: whole mesh written
+    sim.shrink_radius(150.0)
+    st = sim.state()
+    assert st["periodic"] == 0
+    ost = pm.State(x.copy(), p.copy(), ids.copy(), n, np.zeros((ng,) * 3), 0.5)
+    pm.shrink_radius(ost, ocfg, 150.0)
+    sim.deposit()
+    ref = pm.deposit(ost.x[:ost.n_active], ng, box, B, False)
+    assert np.array_equal(sim.counts_numpy(), ref)
+    # a particle whose CIC cells leave the active box is reported
+    import paper_1709_04703_amd as P
+    sim.close()
+    sim2 = make_sim(cfg, n)
+    k = ost.n_active
+    sim2.bind(ost.x[:k], ost.p[:k], ost.ids[:k])
+    sim2.shrink_radius(150.0)
+    sim2.x[0, 0] = 5.0
+    with pytest.raises(P.SdpmError, match="EDOMAIN"):
+        sim2.deposit()
+    sim2.close()

@@ -1,0 +1,156 @@
+"""GPU parity of whole steps (Table 2 order) against the oracle: one step
+from an identical state, a short periodic Poisson run, and a shrinking run
+with the diffusion-equation gravity, lightcone removal and the switch to the
+frozen-exterior box; plus the degenerate cases (no particles, a = 1)."""
+import numpy as np
+import pytest
+
+from oracle import cosmology as oc
+from oracle import pm
+from synth import uniform_particles, zeldovich_ics
+
+from helpers import lib_config, log, make_sim, oracle_config, periodic_delta, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+def _by_id(x, ids):
+    order = np.argsort(ids)
+    return x[order]
+
+
+@pytest.mark.parametrize("prec,c_grav", [(1, 0.0), (0, 0.0), (0, -1.0), (1, -1.0)])
+def test_one_step_from_identical_state(prec, c_grav):
+    ng, box, a0, da = 32, 100.0, 0.02, 0.049
+    x, p, ids = zeldovich_ics(ng, box, a0, 1709, "powerlaw-2")
+    tol = 1e-10
+    cfg = lib_config(ng, box, precision=prec, c_grav=c_grav, tol=tol, n_initial=ng**3)
+    ocfg = oracle_config(cfg)
+    log(f"one step precision={prec} c_grav={c_grav}")
+    sim = make_sim(cfg, ng**3)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    assert rel_rms(sim.phi_numpy(), ost.phi) <= 1e-7
+    # same starting potential on both sides
+    sim.phi.copy_(__import__("torch").as_tensor(ost.phi))
+    pin = p.astype(np.float32).astype(np.float64) if prec == 0 else p
+    ost.p = pin.copy()
+    st = sim.step(a0, da)
+    diag = {}
+    ost = pm.step(ost, ocfg, da, diag)
+    gx, gp, gid = sim.particles()
+    dx = periodic_delta(_by_id(gx, gid), _by_id(ost.x, ost.ids), box)
+    log(f"  iters={st['outer_iters']} res={st['res']} max|dx|={np.abs(dx).max():.2e} "
+        f"p err={rel_rms(_by_id(gp, gid), _by_id(ost.p, ost.ids)):.2e} "
+        f"phi err={rel_rms(sim.phi_numpy(), ost.phi):.2e}")
+    assert np.abs(dx).max() <= 1e-9 * box
+    p_tol = 1e-7 if prec == 0 else 1e-8
+    assert rel_rms(_by_id(gp, gid), _by_id(ost.p, ost.ids)) <= p_tol
+    assert rel_rms(sim.phi_numpy(), ost.phi) <= 1e-7
+    assert st["dtau"] == pytest.approx(diag["dtau"], rel=1e-12)
+    assert st["kappa_h2"][0] == pytest.approx(diag["kappa1_h2"], rel=1e-12)
+    sim.close()
+
+
+def test_periodic_poisson_run_20_steps():
+    # the 32^3, 100 Mpc/h, P ~ k^-2 configuration: a = 0.02 -> 1 in 20 steps
+    ng, box, a0 = 32, 100.0, 0.02
+    nsteps = 20
+    x, p, ids = zeldovich_ics(ng, box, a0, 1709, "powerlaw-2")
+    cfg = lib_config(ng, box, precision=1, tol=1e-10, n_initial=ng**3)
+    ocfg = oracle_config(cfg)
+    sim = make_sim(cfg, ng**3)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    edges = np.linspace(a0, 1.0, nsteps + 1)
+    errs = []
+    for n in range(nsteps):
+        st = sim.step(edges[n], edges[n + 1] - edges[n])
+        ost = pm.step(ost, ocfg, edges[n + 1] - edges[n])
+        gx, gp, gid = sim.particles()
+        dx = periodic_delta(_by_id(gx, gid), _by_id(ost.x, ost.ids), box)
+        errs.append(np.sqrt(np.mean(dx**2)) / (box / ng))
+        assert st["res"][0] <= 1e-10
+    log(f"  position rms error / cell per step: {np.array2string(np.array(errs), precision=2)}")
+    assert errs[0] < 1e-9
+    assert errs[-1] < 1e-3
+    gx, gp, gid = sim.particles()
+    assert rel_rms(_by_id(gp, gid), _by_id(ost.p, ost.ids)) < 1e-3
+    sim.close()
+
+
+def test_shrinking_run_against_oracle():
+    # 64^3 particles, 2000 Mpc/h, z = 49 -> 0 in 32 steps, gravity with the
+    # paper's reduced speed, mixed precision
+    ng, box, nsteps = 64, 2000.0, 32
+    a0 = 1.0 / 50.0
+    x, p, ids = zeldovich_ics(ng, box, a0, 4703)
+    cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3)
+    ocfg = oracle_config(cfg)
+    sim = make_sim(cfg, ng**3)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    edges = np.linspace(a0, 1.0, nsteps + 1)
+    xo = np.full(3, box / 2)
+    switched = False
+    for n in range(nsteps):
+        a, da = edges[n], edges[n + 1] - edges[n]
+        n_before = sim.n_active
+        st = sim.step(a, da)
+        ost = pm.step(ost, ocfg, da)
+        r = oc.lightcone_radius(a + da, 0.3, 0.7)
+        gx_all, _, gid_all = sim.particles(all_particles=True)
+        k = sim.n_active
+        # the removal decision is the FP64 predicate on the library's positions
+        assert not pm.outside_lightcone(gx_all[:k], xo, st["r_lc"]).any()
+        assert pm.outside_lightcone(gx_all[k:n_before], xo, st["r_lc"]).all()
+        assert st["r_lc"] == pytest.approx(r, rel=1e-12)
+        assert abs(k - ost.n_active) <= max(2, 1e-4 * ng**3), (n, k, ost.n_active)
+        assert st["periodic"] == int(ost.periodic)
+        if not ost.periodic:
+            switched = True
+            assert st["lo"] == list(ost.lo) and st["hi"] == list(ost.hi)
+        assert max(st["res"]) <= cfg.tol
+        if k and ost.n_active:
+            common = np.intersect1d(gid_all[:k], ost.ids[:ost.n_active])
+            gsel = np.isin(gid_all[:k], common)
+            osel = np.isin(ost.ids[:ost.n_active], common)
+            gx = _by_id(gx_all[:k][gsel], gid_all[:k][gsel])
+            ox = _by_id(ost.x[:ost.n_active][osel], ost.ids[:ost.n_active][osel])
+            err = np.abs(periodic_delta(gx, ox, box)).max() / (box / ng)
+            assert err < 1e-3, (n, err)
+        log(f"  step {n} a={a + da:.3f} active={k} oracle={ost.n_active} periodic={st['periodic']} "
+            f"iters={st['outer_iters']} kappa={st['kappa_h2'][0]:.3f}")
+    assert switched
+    assert sim.n_active == 0 and ost.n_active == 0          # r_lc(1) = 0
+    sim.close()
+
+
+def test_empty_particle_set_steps():
+    ng, box = 16, 100.0
+    cfg = lib_config(ng, box, c_grav=-1.0, n_initial=10)
+    sim = make_sim(cfg, 10)
+    sim.bind(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.uint32))
+    sim.init_potential(0.1)
+    st = sim.step(0.1, 0.1)
+    assert st["n_active"] == 0
+    sim.close()
+
+
+def test_step_argument_errors():
+    import paper_1709_04703_amd as P
+
+    cfg = lib_config(16, 100.0, n_initial=100)
+    sim = make_sim(cfg, 100)
+    with pytest.raises(P.SdpmError, match="ESTATE"):
+        sim.step(0.5, 0.1)
+    x, p, ids = uniform_particles(100, 100.0, 1)
+    sim.bind(x, p * 0, ids)
+    with pytest.raises(P.SdpmError, match="EINVAL"):
+        sim.step(0.95, 0.1)
+    with pytest.raises(P.SdpmError, match="EINVAL"):
+        sim.step(0.5, -0.1)
+    sim.close()

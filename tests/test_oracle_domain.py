@@ -59,6 +59,13 @@ def test_box_rule_and_switch():
     assert not dirichlet and list(lo) == [0, 0, 0] and list(hi) == [63, 63, 63]
     dirichlet, lo, hi = pm.box_for_radius(200.0, xo, h, ng, 2)
     assert dirichlet and list(lo) == [10, 10, 10] and list(hi) == [54, 54, 54]
+    # outward rounding: planes next to the box on multiples of 8
+    dirichlet, lo, hi = pm.box_for_radius(200.0, xo, h, ng, 2, 8)
+    assert dirichlet and list(lo) == [9, 9, 9] and list(hi) == [55, 55, 55]
+    dirichlet, lo, hi = pm.box_for_radius(211.0, xo, h, ng, 2, 8)
+    assert dirichlet and list(lo) == [1, 1, 1] and list(hi) == [55, 55, 55]
+    dirichlet, lo, hi = pm.box_for_radius(231.0, xo, h, ng, 2, 8)
+    assert not dirichlet
     # a box that never grows
     cfg = pm.Config(ng=ng, box=box, shrink=True, n_initial=1)
     st = pm.State(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0, np.uint32), 0,
