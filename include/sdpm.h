@@ -72,7 +72,7 @@ typedef struct sdpm_config {
                             every multigrid level exactly)                     */
   int32_t mg_levels;     /* multigrid levels incl. the finest (>= 2)           */
   int32_t pre, post;     /* RB Gauss-Seidel sweeps before / after coarse work  */
-  int32_t coarse_sweeps; /* RB Gauss-Seidel sweeps on the coarsest level       */
+  int32_t coarse_sweeps; /* max RB Gauss-Seidel sweeps on the coarsest level   */
   int32_t max_outer;     /* FP64 defect-correction iterations per solve        */
   double tol;            /* stop when ||r||_2 <= tol ||rhs||_2 (active cells)  */
   int32_t precision;     /* SDPM_MIXED: FP32 V-cycles in FP64 defect
@@ -144,7 +144,7 @@ int sdpm_workspace_bytes(const sdpm_config* cfg, int64_t capacity, int64_t* byte
 
 /* Creates a context.  workspace: caller-owned device memory of at least
  * sdpm_workspace_bytes; hip_stream: hipStream_t (NULL = default stream).
- * The library allocates only a small pinned host buffer for scalars.       */
+ * The library allocates only a small host buffer for scalars.              */
 int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes,
                 void* hip_stream, sdpm_ctx** out);
 

@@ -101,6 +101,10 @@ def library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1709_04703_amd.build`")
+    # torch ships its own HIP runtime (same soname as ROCm's); loading it
+    # first makes libsdpm bind to that one runtime instead of a second copy.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER

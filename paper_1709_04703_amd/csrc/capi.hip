@@ -25,7 +25,7 @@ struct sdpm_ctx {
   uint32_t* bcounts = nullptr;
   uint32_t* boffsets = nullptr;
   void* scratch = nullptr;
-  double* hpin = nullptr;       // pinned host scalars
+  double* hpin = nullptr;       // host copies of device scalars
   hipEvent_t ev[8] = {};
   Profiler prof;
   bool bound = false;
@@ -531,16 +531,24 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
   if (!c) return fail(nullptr, SDPM_ENOMEM, "host allocation failed");
   c->cfg = *cfg;
   c->st = (hipStream_t)hip_stream;
-  // capacity that fits: the particle scratch is the last region
+  // largest particle capacity whose layout fits the workspace
   const size_t fixed = carve(*cfg, 0, nullptr, nullptr);
-  const size_t per = 3 * sizeof(double) + 3 * p_elem(*cfg) + sizeof(uint32_t) + 2 * sizeof(uint32_t);
   if ((size_t)ws_bytes < fixed) {
     delete c;
     return fail(nullptr, SDPM_ENOMEM, "workspace of %lld bytes < %zu required",
                 (long long)ws_bytes, fixed);
   }
-  int64_t cap = (int64_t)(((size_t)ws_bytes - fixed) / per);
-  while (cap > 0 && carve(*cfg, cap, nullptr, nullptr) > (size_t)ws_bytes) --cap;
+  const size_t per = 3 * sizeof(double) + 3 * p_elem(*cfg) + sizeof(uint32_t);
+  int64_t lo = 0, hi = (int64_t)(((size_t)ws_bytes - fixed) / per) + 1;
+  hi = std::min<int64_t>(hi, (1ll << 32) - 1);
+  while (lo < hi) {  // invariant: carve(lo) fits
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (carve(*cfg, mid, nullptr, nullptr) <= (size_t)ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t cap = lo;
   c->capacity = cap;
   carve(*cfg, cap, (char*)workspace, c);
   c->nlev_max = cfg->mg_levels;
@@ -548,13 +556,14 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
   c->box = full_box(cfg->ng);
   c->counts_box = full_box(cfg->ng);
   set_levels(c);
-  if (hipHostMalloc((void**)&c->hpin, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  c->hpin = new (std::nothrow) double[64]();
+  if (!c->hpin) {
     delete c;
-    return fail(nullptr, SDPM_EHIP, "hipHostMalloc failed");
+    return fail(nullptr, SDPM_ENOMEM, "host allocation failed");
   }
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
-      hipHostFree(c->hpin);
+      delete[] c->hpin;
       delete c;
       return fail(nullptr, SDPM_EHIP, "hipEventCreate failed");
     }
@@ -823,7 +832,7 @@ int sdpm_destroy(sdpm_ctx* c) {
   c->prof.release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
-  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete[] c->hpin;
   delete c;
   return SDPM_OK;
 }

@@ -10,6 +10,9 @@
 // periodic levels cover the whole mesh and wrap indices with n - 1 masks
 // (n is a power of two).  In Dirichlet mode every box satisfies 1 <= lo and
 // hi <= n - 2, so the same masked indexing never wraps there.
+#include <algorithm>
+#include <cmath>
+
 #include "internal.h"
 
 namespace sdpm {
@@ -286,9 +289,13 @@ k_prolong(const T* __restrict__ ec, T* __restrict__ ef, int nc, int nf, Box bf) 
 
 // Coarsest level: one workgroup; e lives in LDS on a box-local array of at
 // most kCoarseMax^3 entries: the whole (periodic) level, or the box plus a
-// one-cell ring of zeros (Dirichlet).  `sweeps` red-black sweeps; with
-// project != 0 (periodic, kappa = 0) the mean of r is removed first and the
-// mean of e afterwards.  The host checks that the local array fits.
+// one-cell ring of zeros (Dirichlet).  Each thread owns up to kCoarseMax^3 /
+// 1024 cells whose LDS offsets and right-hand sides stay in registers for all
+// `sweeps` red-black sweeps.  With project != 0 (periodic, kappa = 0) the
+// mean of r is removed first and the mean of e afterwards.  The host checks
+// that the local array fits.
+constexpr int kCoarsePer = kCoarseMax * kCoarseMax * kCoarseMax / 1024;
+
 template <typename T>
 __global__ void __launch_bounds__(1024)
 k_coarse(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T inv_diag,
@@ -302,39 +309,58 @@ k_coarse(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T in
   const int lx = nx + 2 * off, ly = ny + 2 * off, lz = nz + 2 * off;
   const int m = n - 1;
   for (int c = tid; c < lx * ly * lz; c += 1024) es[c] = 0;
-  double rmean = 0.0;
-  if (project) {
-    double acc = 0.0;
-    for (int q = tid; q < nbox; q += 1024) {
-      const int i = b.lo[0] + q % nx, j = b.lo[1] + (q / nx) % ny, k = b.lo[2] + q / (nx * ny);
-      acc += (double)r[lin(i, j, k, n)];
+  // owned cells: local offset of the cell and of its 6 neighbours, colour, rhs
+  int own[kCoarsePer], nbr[kCoarsePer][6], col[kCoarsePer];
+  T rr[kCoarsePer];
+  int64_t gidx[kCoarsePer];
+  int nown = 0;
+  double racc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCoarsePer; ++u) {
+    const int q = tid + 1024 * u;
+    if (q >= nbox) break;
+    nown = u + 1;
+    const int qa = q % nx, qb = (q / nx) % ny, qc = q / (nx * ny);
+    const int a0 = qa + off, b0 = qb + off, c0 = qc + off;
+    int am, ap, bm, bp, cm, cp;
+    if (periodic) {
+      am = (a0 - 1) & m; ap = (a0 + 1) & m;
+      bm = (b0 - 1) & m; bp = (b0 + 1) & m;
+      cm = (c0 - 1) & m; cp = (c0 + 1) & m;
+    } else {
+      am = a0 - 1; ap = a0 + 1; bm = b0 - 1; bp = b0 + 1; cm = c0 - 1; cp = c0 + 1;
     }
-    const double s = block_sum<1024>(acc, sh);
+    own[u] = (c0 * ly + b0) * lx + a0;
+    nbr[u][0] = (c0 * ly + b0) * lx + am;
+    nbr[u][1] = (c0 * ly + b0) * lx + ap;
+    nbr[u][2] = (c0 * ly + bm) * lx + a0;
+    nbr[u][3] = (c0 * ly + bp) * lx + a0;
+    nbr[u][4] = (cm * ly + b0) * lx + a0;
+    nbr[u][5] = (cp * ly + b0) * lx + a0;
+    const int i = b.lo[0] + qa, j = b.lo[1] + qb, k = b.lo[2] + qc;
+    col[u] = (i + j + k) & 1;
+    gidx[u] = lin(i, j, k, n);
+    rr[u] = r[gidx[u]];
+    racc += (double)rr[u];
+  }
+  if (project) {
+    const double s = block_sum<1024>(racc, sh);
     if (tid == 0) sh[8] = s / nbox;
     __syncthreads();
-    rmean = sh[8];
+    const T rm = (T)sh[8];
+#pragma unroll
+    for (int u = 0; u < kCoarsePer; ++u)
+      if (u < nown) rr[u] -= rm;
   }
   __syncthreads();
-  const T rm = (T)rmean;
   for (int sw = 0; sw < sweeps; ++sw) {
     for (int color = 0; color < 2; ++color) {
-      for (int q = tid; q < nbox; q += 1024) {
-        const int qa = q % nx, qb = (q / nx) % ny, qc = q / (nx * ny);
-        const int i = b.lo[0] + qa, j = b.lo[1] + qb, k = b.lo[2] + qc;
-        if (((i + j + k) & 1) != color) continue;
-        const int a0 = qa + off, b0 = qb + off, c0 = qc + off;
-        int am, ap, bm, bp, cm, cp;
-        if (periodic) {
-          am = (a0 - 1) & m; ap = (a0 + 1) & m;
-          bm = (b0 - 1) & m; bp = (b0 + 1) & m;
-          cm = (c0 - 1) & m; cp = (c0 + 1) & m;
-        } else {
-          am = a0 - 1; ap = a0 + 1; bm = b0 - 1; bp = b0 + 1; cm = c0 - 1; cp = c0 + 1;
-        }
-        const T nb = es[(c0 * ly + b0) * lx + am] + es[(c0 * ly + b0) * lx + ap] +
-                     es[(c0 * ly + bm) * lx + a0] + es[(c0 * ly + bp) * lx + a0] +
-                     es[(cm * ly + b0) * lx + a0] + es[(cp * ly + b0) * lx + a0];
-        es[(c0 * ly + b0) * lx + a0] = (nb - scale * (r[lin(i, j, k, n)] - rm)) * inv_diag;
+#pragma unroll
+      for (int u = 0; u < kCoarsePer; ++u) {
+        if (u >= nown || col[u] != color) continue;
+        const T nb = es[nbr[u][0]] + es[nbr[u][1]] + es[nbr[u][2]] + es[nbr[u][3]] +
+                     es[nbr[u][4]] + es[nbr[u][5]];
+        es[own[u]] = (nb - scale * rr[u]) * inv_diag;
       }
       __syncthreads();
     }
@@ -342,20 +368,17 @@ k_coarse(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T in
   T emean = 0;
   if (project) {
     double acc = 0.0;
-    for (int q = tid; q < nbox; q += 1024) {
-      const int qa = q % nx, qb = (q / nx) % ny, qc = q / (nx * ny);
-      acc += (double)es[((qc + off) * ly + qb + off) * lx + qa + off];
-    }
+#pragma unroll
+    for (int u = 0; u < kCoarsePer; ++u)
+      if (u < nown) acc += (double)es[own[u]];
     const double s = block_sum<1024>(acc, sh);
     if (tid == 0) sh[8] = s / nbox;
     __syncthreads();
     emean = (T)sh[8];
   }
-  for (int q = tid; q < nbox; q += 1024) {
-    const int qa = q % nx, qb = (q / nx) % ny, qc = q / (nx * ny);
-    e[lin(b.lo[0] + qa, b.lo[1] + qb, b.lo[2] + qc, n)] =
-        es[((qc + off) * ly + qb + off) * lx + qa + off] - emean;
-  }
+#pragma unroll
+  for (int u = 0; u < kCoarsePer; ++u)
+    if (u < nown) e[gidx[u]] = es[own[u]] - emean;
 }
 
 }  // namespace
@@ -474,10 +497,23 @@ void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coar
                                : ((int64_t)(nx + 2) * (ny + 2) * (nz + 2) <=
                                   (int64_t)kCoarseMax * kCoarseMax * kCoarseMax);
     const T scale = (T)sc, inv_diag = (T)(1.0 / (6.0 + sc * kappa));
+    // sweeps for a 1e-3 reduction of the slowest mode: Jacobi factor
+    // rho = 6 cos(theta) / (6 + 4^l kappa h^2), red-black GS factor rho^2,
+    // theta = 2 pi / n (periodic) or pi / (extent + 1) (Dirichlet)
+    int sweeps = coarse_sweeps;
+    {
+      const int ext = std::max(nx, std::max(ny, nz));
+      const double th = periodic ? 2.0 * M_PI / L.n : M_PI / (ext + 1);
+      const double rho = 6.0 * std::cos(th) / (6.0 + sc * kappa);
+      if (rho > 0.0 && rho < 1.0) {
+        const int need = (int)std::ceil(std::log(1e-3) / (2.0 * std::log(rho)));
+        sweeps = std::max(1, std::min(coarse_sweeps, need));
+      }
+    }
     if (fits) {
       prof_begin(st);
       hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), 0, st, (T*)L.e, (const T*)L.r, L.n,
-                         L.box, scale, inv_diag, coarse_sweeps,
+                         L.box, scale, inv_diag, sweeps,
                          (periodic && kappa == 0.0) ? 1 : 0, periodic ? 1 : 0);
       prof_end(st, K_COARSE, 2 * es * (double)box_cells(L.box));
     } else {
@@ -488,7 +524,7 @@ void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coar
       hipLaunchKernelGGL(k_smooth_first<T>, g, blk, 0, st, (T*)L.e, (const T*)L.r, L.n, L.box,
                          scale, inv_diag);
       prof_end(st, K_SMOOTH_FIRST, 2 * es * cells);
-      for (int s = 0; s < 2 * coarse_sweeps - 1; ++s) {
+      for (int s = 0; s < 2 * sweeps - 1; ++s) {
         prof_begin(st);
         hipLaunchKernelGGL(k_smooth<T>, gc, blk, 0, st, (T*)L.e, (const T*)L.r, L.n, L.box,
                            (s + 1) & 1, scale, inv_diag);
