@@ -38,7 +38,8 @@ def run_mode(P, torch, ics, args, precision, profile):
     x, p, ids = ics
     ng, box = args.ng, args.box
     n = x.shape[0]
-    cfg = P.config_default(ng, box, c_grav=-1.0, shrink=1, precision=precision, n_initial=n)
+    cfg = P.config_default(ng, box, c_grav=-1.0, shrink=1, precision=precision, n_initial=n,
+                           sort_every=args.sort_every)
     sim = P.Simulation(cfg, n)
     sim.bind(x, p, ids)
     a0 = 1.0 / (1.0 + args.z_init)
@@ -128,6 +129,7 @@ def main():
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
     ap.add_argument("--modes", default="mixed,plain")
+    ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     args = ap.parse_args()

@@ -80,6 +80,8 @@ typedef struct sdpm_config {
                             V-cycles and momenta                               */
   int32_t warm_start;    /* SDPM_WS_PREV or SDPM_WS_LEARNED                    */
   int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
+  int32_t sort_every;    /* Morton re-sort before every k-th step (0: never)   */
+  int32_t sort_shift;    /* sort key: cells grouped in blocks of 2^shift       */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,
@@ -185,6 +187,10 @@ int sdpm_deposit(sdpm_ctx* ctx);
 /* rhs = h^2 S (counts / (n0/ng^3 2^3B) - 1) [- mean, periodic] - kappa h^2 phi,
  * then solve (Lap_h - kappa h^2) phi = rhs on the active box, phi as guess. */
 int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_stats* out);
+/* Morton re-sort of the active particles (all SoA arrays permuted together
+ * by the Morton code of their cell, stable LSD radix sort).  Results of the
+ * step do not depend on particle order; the sort improves locality.       */
+int sdpm_sort(sdpm_ctx* ctx);
 /* g = -grad Phi (central differences) interpolated to the active particles
  * with the deposit's CIC weights; g_dev[3]: device FP64 arrays (n_active). */
 int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);

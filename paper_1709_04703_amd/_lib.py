@@ -31,7 +31,7 @@ EXPORTS = [
     "sdpm_step_scalars", "sdpm_lightcone_radius", "sdpm_domain_box", "sdpm_config_default",
     "sdpm_workspace_bytes", "sdpm_create", "sdpm_bind", "sdpm_init_potential", "sdpm_step",
     "sdpm_shrink", "sdpm_shrink_radius", "sdpm_get_state", "sdpm_deposit", "sdpm_solve",
-    "sdpm_interp_force", "sdpm_set_warmstart_weights", "sdpm_profile", "sdpm_profile_read",
+    "sdpm_interp_force", "sdpm_sort", "sdpm_set_warmstart_weights", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error",
 ]
 
@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("coarse_sweeps", ctypes.c_int32), ("max_outer", ctypes.c_int32),
         ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
         ("warm_start", ctypes.c_int32), ("n_initial", ctypes.c_int64),
+        ("sort_every", ctypes.c_int32), ("sort_shift", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -124,6 +125,7 @@ def library() -> ctypes.CDLL:
         "sdpm_deposit": [vp],
         "sdpm_solve": [vp, dbl, dbl, P(StepStats)],
         "sdpm_interp_force": [vp, P(vp)],
+        "sdpm_sort": [vp],
         "sdpm_set_warmstart_weights": [vp, vp, i64],
         "sdpm_profile": [vp, i32],
         "sdpm_profile_read": [vp, P(KernelStat), i32, P(i32)],
@@ -315,6 +317,9 @@ class Simulation:
         st = StepStats()
         self._check(self.lib.sdpm_solve(self.ctx, kappa_h2, s_source, ctypes.byref(st)))
         return st.as_dict()
+
+    def sort(self):
+        self._check(self.lib.sdpm_sort(self.ctx))
 
     def interp_force(self):
         n = self.n_active

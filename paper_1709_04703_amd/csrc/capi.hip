@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 
 #include "internal.h"
 
@@ -25,6 +26,8 @@ struct sdpm_ctx {
   uint32_t* bcounts = nullptr;
   uint32_t* boffsets = nullptr;
   void* scratch = nullptr;
+  void* sort_scratch = nullptr;
+  int64_t steps_done = 0;
   double* hpin = nullptr;       // host copies of device scalars
   hipEvent_t ev[8] = {};
   Profiler prof;
@@ -108,6 +111,8 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->warm_start != SDPM_WS_PREV)
     return snprintf(msg, len, "warm_start: only SDPM_WS_PREV is available"), SDPM_EINVAL;
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
+  if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
+    return snprintf(msg, len, "sort_every and sort_shift must be >= 0, ng >> sort_shift >= 1"), SDPM_EINVAL;
   return SDPM_OK;
 }
 
@@ -148,7 +153,9 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   uint32_t* bc = (uint32_t*)take(nb * sizeof(uint32_t));
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
   void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
+  void* sscr = c.sort_every > 0 ? take(sort_scratch_bytes(capacity)) : nullptr;
   if (ctx) {
+    ctx->sort_scratch = sscr;
     ctx->partial = partial;
     ctx->dscal = dscal;
     ctx->dflags = dflags;
@@ -332,8 +339,9 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
   so->res0 = rn / denom;
   int it = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
-    vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
-    launch_correct<T>(c->fields.phi, (const T*)c->lv[0].e, g.ng, b, c->st);
+    const T* e0 =
+        vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
+    launch_correct<T>(c->fields.phi, e0, g.ng, b, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
@@ -420,6 +428,17 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
   return SDPM_OK;
 }
 
+void sort_particles(sdpm_ctx* c) {
+  if (!c->sort_scratch || c->n_active <= 1) return;
+  const ParticleArgs pa = particle_args(c);
+  if (c->cfg.precision == SDPM_MIXED)
+    launch_morton_sort<float>(pa, c->cfg.ng, c->cfg.box, c->cfg.sort_shift, c->sort_scratch,
+                              c->scratch, c->st);
+  else
+    launch_morton_sort<double>(pa, c->cfg.ng, c->cfg.box, c->cfg.sort_shift, c->sort_scratch,
+                               c->scratch, c->st);
+}
+
 void fill_state(sdpm_ctx* c, sdpm_step_stats* o) {
   o->n_active = c->n_active;
   for (int d = 0; d < 3; ++d) {
@@ -469,6 +488,8 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->precision = SDPM_MIXED;
   cfg->warm_start = SDPM_WS_PREV;
   cfg->n_initial = (int64_t)ng * ng * ng;
+  cfg->sort_every = 0;
+  cfg->sort_shift = 0;
   return SDPM_OK;
 }
 
@@ -598,6 +619,7 @@ int sdpm_bind(sdpm_ctx* c, const sdpm_particles* parts, const sdpm_fields* field
   clear_all_levels(c);
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   c->bound = true;
+  c->steps_done = 0;
   c->err[0] = 0;
   return SDPM_OK;
 }
@@ -647,6 +669,8 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   st.r_lc = sc.r_lc_end;
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   HIP_TRY(c, hipEventRecord(c->ev[0], c->st));
+  if (g.sort_every > 0 && c->steps_done % g.sort_every == 0) sort_particles(c);
+  ++c->steps_done;
   // drift dtau/2 with a(t), then density at t + dt/2   (Table 2 rows 1-2)
   deposit(c, 0.5 * sc.dtau / a, 1);
   HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
@@ -776,6 +800,18 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
     fill_state(c, out);
   }
   return rc;
+}
+
+int sdpm_sort(sdpm_ctx* c) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!c->sort_scratch)
+    return fail(c, SDPM_ESTATE, "the context was created with sort_every = 0 (no sort workspace)");
+  sort_particles(c);
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  return SDPM_OK;
 }
 
 int sdpm_interp_force(sdpm_ctx* c, double* g_dev[3]) {

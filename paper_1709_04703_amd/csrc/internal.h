@@ -34,10 +34,19 @@ inline int64_t box_cells(const Box& b) {
   return (int64_t)(b.hi[0] - b.lo[0] + 1) * (b.hi[1] - b.lo[1] + 1) * (b.hi[2] - b.lo[2] + 1);
 }
 
-inline dim3 box_grid(const Box& b, int xcells_per_block = kBoxTx) {
+// 1-D grid of box tiles (kBoxTx cells in x, kBoxTy rows, kBoxKz planes);
+// kernels recover the tile with an XCD-aware remap of blockIdx.x.
+inline dim3 box_grid(const Box& b) {
   const int nx = b.hi[0] - b.lo[0] + 1, ny = b.hi[1] - b.lo[1] + 1, nz = b.hi[2] - b.lo[2] + 1;
-  return dim3((nx + xcells_per_block - 1) / xcells_per_block, (ny + kBoxTy - 1) / kBoxTy,
-              (nz + kBoxKz - 1) / kBoxKz);
+  return dim3((unsigned)(((nx + kBoxTx - 1) / kBoxTx) * ((ny + kBoxTy - 1) / kBoxTy) *
+                         ((nz + kBoxKz - 1) / kBoxKz)));
+}
+// Same for kernels whose threads map to half-row (colour-split) indices.
+inline dim3 half_grid(const Box& b) {
+  const int hx = (b.hi[0] >> 1) - (b.lo[0] >> 1) + 1, ny = b.hi[1] - b.lo[1] + 1,
+            nz = b.hi[2] - b.lo[2] + 1;
+  return dim3((unsigned)(((hx + kBoxTx - 1) / kBoxTx) * ((ny + kBoxTy - 1) / kBoxTy) *
+                         ((nz + kBoxKz - 1) / kBoxKz)));
 }
 
 // One multigrid level: `n` cells per axis (power of two), active box, and
@@ -45,9 +54,9 @@ inline dim3 box_grid(const Box& b, int xcells_per_block = kBoxTx) {
 struct Level {
   int n;
   Box box;
-  void* e;
-  void* r;
-  void* t;
+  void* e;    // correction     } all three stored split by colour:
+  void* r;    // right-hand side } red cells ((i+j+k) even) first, then black,
+  void* t;    // residual        } each in row order with x index i >> 1
 };
 
 // ---------------------------------------------------------------------------
@@ -74,14 +83,16 @@ void launch_residual(const double* phi, const double* rhs, T* r_out, int n, cons
                      double kappa, double* partial, int* nblocks, hipStream_t st);
 template <typename T>
 void launch_correct(double* phi, const T* e, int n, const Box& b, hipStream_t st);
+
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st);
 void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st);
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
                          hipStream_t st);
+// One V-cycle for A_0 e = r_0; returns the level-0 buffer holding e.
 template <typename T>
-void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
-            bool periodic, hipStream_t st);
+const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
+                bool periodic, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Launchers, particle kernels (particles.hip).
@@ -119,6 +130,13 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
                     uint32_t* block_counts, uint32_t* block_offsets, uint64_t* kept_total,
                     hipStream_t st);
 
+// Morton re-sort (sort.hip): sort_scratch holds sort_scratch_bytes(capacity),
+// particle_scratch one particle set.
+size_t sort_scratch_bytes(int64_t capacity);
+template <typename PT>
+void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, void* sort_scratch,
+                        void* particle_scratch, hipStream_t st);
+
 // flags written by kernels
 enum : uint32_t { kFlagDomain = 1u, kFlagOverflow = 2u };
 
@@ -132,6 +150,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
+  K_SORT, K_GATHER,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

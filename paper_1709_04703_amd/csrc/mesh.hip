@@ -12,6 +12,7 @@
 // hi <= n - 2, so the same masked indexing never wraps there.
 #include <algorithm>
 #include <cmath>
+#include <utility>
 
 #include "internal.h"
 
@@ -39,17 +40,57 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
+// Multigrid arrays (e, r, t of every level) are stored split by colour:
+// the n^3/2 red cells ((i+j+k) even) first, then the black ones, each in
+// row order with x index i >> 1.  A colour sweep then streams contiguous,
+// fully used cache lines.
+__host__ __device__ inline int64_t half_cells(int n) { return (int64_t)n * n * (n >> 1); }
+__host__ __device__ inline int64_t sidx(int i, int j, int k, int n) {
+  return (int64_t)((i + j + k) & 1) * half_cells(n) + ((int64_t)k * n + j) * (n >> 1) + (i >> 1);
+}
+
 __device__ inline int block_linear() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+// Workgroup -> tile mapping.  Box kernels launch a 1-D grid of gx*gy*gz
+// workgroups.  The hardware hands consecutive workgroup ids to the 8 XCDs in
+// turn; the ids are remapped so that each XCD receives one contiguous run of
+// tiles (x fastest, then y, then z), and neighbouring tiles - which read each
+// other's halo planes - share that XCD's L2.
+struct Tile {
+  int bx, by, bz;
+};
+__device__ inline Tile tile_of(int gx, int gy) {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  const int l = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  Tile t;
+  t.bx = l % gx;
+  const int q = l / gx;
+  t.by = q % gy;
+  t.bz = q / gy;
+  return t;
+}
+// tiles of kBoxTx cells (or half-row entries) in x, kBoxTy rows, kBoxKz planes
+__device__ inline Tile tile_box(const Box& b) {
+  return tile_of((b.hi[0] - b.lo[0] + kBoxTx) / kBoxTx, (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
+}
+__device__ inline Tile tile_half(const Box& b) {
+  return tile_of(((b.hi[0] >> 1) - (b.lo[0] >> 1) + kBoxTx) / kBoxTx,
+                 (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
 }
 
 // ------------------------------------------------------------------ fills
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill(T* __restrict__ a, int n, Box b, T v) {
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) a[lin(i, j, k, n)] = v;
 }
@@ -61,11 +102,12 @@ k_rhs(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
       double* __restrict__ rhs, int n, Box b, double c_scale, double c_off, double kappa,
       double* __restrict__ partial) {
   __shared__ double sh[4];
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   double acc = 0.0;
   if (i <= b.hi[0] && j <= b.hi[1]) {
-    const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
     const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
     for (int k = k0; k <= k1; ++k) {
       const int64_t c = lin(i, j, k, n);
@@ -78,29 +120,34 @@ k_rhs(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
-// r = rhs - (Lap_h phi - kappa phi) in FP64, stored as T; partial sum of r^2.
+// r = rhs - (Lap_h phi - kappa phi) in FP64, stored as T (colour-split).
+// Each thread walks kBoxKz planes and carries phi at k-1 and k in registers.
+// Partial sum of r^2 per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_residual(const double* __restrict__ phi, const double* __restrict__ rhs,
-           T* __restrict__ rout, int n, Box b, double kappa, double* __restrict__ partial) {
+k_residual(const double* __restrict__ phi, const double* __restrict__ rhs, T* __restrict__ rout,
+           int n, Box b, double kappa, double* __restrict__ partial) {
   __shared__ double sh[4];
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   const int m = n - 1;
   double acc = 0.0;
   if (i <= b.hi[0] && j <= b.hi[1]) {
-    const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
     const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
     const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
+    double below = phi[lin(i, j, (k0 - 1) & m, n)], ctr = phi[lin(i, j, k0, n)];
     for (int k = k0; k <= k1; ++k) {
-      const int kp = (k + 1) & m, km = (k - 1) & m;
+      const double above = phi[lin(i, j, (k + 1) & m, n)];
       const int64_t c = lin(i, j, k, n);
-      const double ctr = phi[c];
       const double nb = phi[lin(ip, j, k, n)] + phi[lin(im, j, k, n)] + phi[lin(i, jp, k, n)] +
-                        phi[lin(i, jm, k, n)] + phi[lin(i, j, kp, n)] + phi[lin(i, j, km, n)];
+                        phi[lin(i, jm, k, n)] + above + below;
       const double res = rhs[c] - (nb - 6.0 * ctr - kappa * ctr);
-      rout[c] = (T)res;
+      rout[sidx(i, j, k, n)] = (T)res;
       acc += res * res;
+      below = ctr;
+      ctr = above;
     }
   }
   const double s = block_sum<256>(acc, sh);
@@ -110,25 +157,27 @@ k_residual(const double* __restrict__ phi, const double* __restrict__ rhs,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_correct(double* __restrict__ phi, const T* __restrict__ e, int n, Box b) {
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) {
     const int64_t c = lin(i, j, k, n);
-    phi[c] += (double)e[c];
+    phi[c] += (double)e[sidx(i, j, k, n)];
   }
 }
 
 __global__ void __launch_bounds__(256)
 k_sum_phi(const double* __restrict__ phi, int n, Box b, double* __restrict__ partial) {
   __shared__ double sh[4];
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   double acc = 0.0;
   if (i <= b.hi[0] && j <= b.hi[1]) {
-    const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
     const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
     for (int k = k0; k <= k1; ++k) acc += phi[lin(i, j, k, n)];
   }
@@ -137,10 +186,11 @@ k_sum_phi(const double* __restrict__ phi, int n, Box b, double* __restrict__ par
 }
 
 __global__ void __launch_bounds__(256) k_add_const(double* __restrict__ phi, int n, Box b, double v) {
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) phi[lin(i, j, k, n)] += v;
 }
@@ -159,131 +209,136 @@ k_reduce_final(const double* __restrict__ partial, int nblocks, int nslots,
 }
 
 // -------------------------------------------------------- multigrid (T)
-// Zero initial guess: one red half-sweep is e = -4^l r / diag on red cells,
-// and black cells start at 0.
-template <typename T>
+// One colour of red-black Gauss-Seidel on the split layout.  Threads map to
+// (h, j, k) with h the half-row index; the cell of `color` in that pair is
+// i = 2h + ((color + j + k) & 1).  Its six neighbours have the other colour:
+// x-neighbours at half-row indices ((i -+ 1) & m) >> 1, y/z neighbours at h.
+// FIRST: zero initial guess (neighbours are zero; red only).
+template <typename T, bool FIRST>
 __global__ void __launch_bounds__(256)
-k_smooth_first(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T inv_diag) {
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
-  if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  for (int k = k0; k <= k1; ++k) {
-    const int64_t c = lin(i, j, k, n);
-    e[c] = ((i + j + k) & 1) == 0 ? -scale * r[c] * inv_diag : (T)0;
-  }
-}
-
-// One colour of red-black Gauss-Seidel: cells with (i+j+k)&1 == color.
-// A workgroup row of 64 threads covers 128 cells in x.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_smooth(T* __restrict__ e, const T* __restrict__ r, int n, Box b, int color, T scale,
-         T inv_diag) {
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+k_smooth_color(T* __restrict__ e, const T* __restrict__ r, int n, Box b, int color, T scale,
+               T inv_diag) {
+  const Tile tl = tile_half(b);
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (j > b.hi[1]) return;
-  const int t = blockIdx.x * kBoxTx + threadIdx.x;
-  const int m = n - 1;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+  const int h = (b.lo[0] >> 1) + tl.bx * kBoxTx + threadIdx.x;
+  const int m = n - 1, hn = n >> 1;
+  const int64_t hc = half_cells(n);
+  const int64_t own = (int64_t)color * hc, oth = (int64_t)(color ^ 1) * hc;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   const int jp = (j + 1) & m, jm = (j - 1) & m;
   for (int k = k0; k <= k1; ++k) {
-    const int par = (b.lo[0] + j + k) & 1;
-    const int i = b.lo[0] + (par ^ color) + 2 * t;
-    if (i > b.hi[0]) continue;
-    const int kp = (k + 1) & m, km = (k - 1) & m;
-    const int64_t c = lin(i, j, k, n);
-    const T nb = e[lin((i + 1) & m, j, k, n)] + e[lin((i - 1) & m, j, k, n)] + e[lin(i, jp, k, n)] +
-                 e[lin(i, jm, k, n)] + e[lin(i, j, kp, n)] + e[lin(i, j, km, n)];
-    e[c] = (nb - scale * r[c]) * inv_diag;
+    const int i = 2 * h + ((color + j + k) & 1);
+    if (i < b.lo[0] || i > b.hi[0]) continue;
+    const int64_t row = ((int64_t)k * n + j) * hn;
+    const int64_t c = own + row + h;
+    if (FIRST) {
+      e[c] = -scale * r[c] * inv_diag;
+    } else {
+      const int kp = (k + 1) & m, km = (k - 1) & m;
+      const T nb = e[oth + row + (((i - 1) & m) >> 1)] + e[oth + row + (((i + 1) & m) >> 1)] +
+                   e[oth + ((int64_t)k * n + jm) * hn + h] + e[oth + ((int64_t)k * n + jp) * hn + h] +
+                   e[oth + ((int64_t)km * n + j) * hn + h] + e[oth + ((int64_t)kp * n + j) * hn + h];
+      e[c] = (nb - scale * r[c]) * inv_diag;
+    }
   }
 }
 
-// t = r - A_l e on the box.
+// t = r - A_l e on the red cells of the box.  After a sweep that ends with
+// the black colour the black residual is zero (each black equation was just
+// solved exactly), so t keeps zeros there (t is cleared with the levels).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_resid_level(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__ tout, int n,
-              Box b, T inv_scale, T kappa) {
-  const int i = b.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
-  if (i > b.hi[0] || j > b.hi[1]) return;
-  const int m = n - 1;
-  const int k0 = b.lo[2] + blockIdx.z * kBoxKz;
+k_resid_red(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__ tout, int n, Box b,
+            T inv_scale, T kappa) {
+  const Tile tl = tile_half(b);
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (j > b.hi[1]) return;
+  const int h = (b.lo[0] >> 1) + tl.bx * kBoxTx + threadIdx.x;
+  const int m = n - 1, hn = n >> 1;
+  const int64_t oth = half_cells(n);
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
+  const int jp = (j + 1) & m, jm = (j - 1) & m;
   for (int k = k0; k <= k1; ++k) {
+    const int i = 2 * h + ((j + k) & 1);
+    if (i < b.lo[0] || i > b.hi[0]) continue;
     const int kp = (k + 1) & m, km = (k - 1) & m;
-    const int64_t c = lin(i, j, k, n);
+    const int64_t row = ((int64_t)k * n + j) * hn;
+    const int64_t c = row + h;
     const T ctr = e[c];
-    const T nb = e[lin(ip, j, k, n)] + e[lin(im, j, k, n)] + e[lin(i, jp, k, n)] +
-                 e[lin(i, jm, k, n)] + e[lin(i, j, kp, n)] + e[lin(i, j, km, n)];
+    const T nb = e[oth + row + (((i - 1) & m) >> 1)] + e[oth + row + (((i + 1) & m) >> 1)] +
+                 e[oth + ((int64_t)k * n + jm) * hn + h] + e[oth + ((int64_t)k * n + jp) * hn + h] +
+                 e[oth + ((int64_t)km * n + j) * hn + h] + e[oth + ((int64_t)kp * n + j) * hn + h];
     tout[c] = r[c] - (nb - (T)6 * ctr) * inv_scale + kappa * ctr;
   }
 }
 
 // Full weighting: r_c(I) = sum_{o in {-1,0,1}^3} w(o) t_f(2I + o),
-// w = (1/4, 1/2, 1/4) per axis.  t_f is zero outside the fine box.
+// w = (1/4, 1/2, 1/4) per axis.  Only red fine cells (o_x + o_y + o_z even)
+// carry a residual.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_restrict(const T* __restrict__ tf, T* __restrict__ rc, int nf, int nc, Box bc) {
-  const int I = bc.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int J = bc.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
+  const Tile tl = tile_box(bc);
+  const int I = bc.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int J = bc.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (I > bc.hi[0] || J > bc.hi[1]) return;
   const int m = nf - 1;
-  const int K0 = bc.lo[2] + blockIdx.z * kBoxKz;
+  const int K0 = bc.lo[2] + tl.bz * kBoxKz;
   const int K1 = min(K0 + kBoxKz - 1, bc.hi[2]);
-  const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
+  const int hn = nf >> 1;
   for (int K = K0; K <= K1; ++K) {
-    T acc = 0;
-    for (int oz = -1; oz <= 1; ++oz) {
-      const int kf = (2 * K + oz) & m;
-      T az = 0;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int jf = (2 * J + oy) & m;
-        const int64_t row = lin(0, jf, kf, nf);
-        const T ax = w[0] * tf[row + ((2 * I - 1) & m)] + w[1] * tf[row + 2 * I] +
-                     w[2] * tf[row + ((2 * I + 1) & m)];
-        az += w[oy + 1] * ax;
-      }
-      acc += w[oz + 1] * az;
-    }
-    rc[lin(I, J, K, nc)] = acc;
+    // red fine cells of the 3x3x3 stencil, grouped by weight
+    const int i = 2 * I, j = 2 * J, k = 2 * K;
+    const int im = (i - 1) & m, ip = (i + 1) & m, jm = (j - 1) & m, jp = (j + 1) & m;
+    const int km = (k - 1) & m, kp = (k + 1) & m;
+    auto R = [&](int x, int y, int z) -> T { return tf[((int64_t)z * nf + y) * hn + (x >> 1)]; };
+    const T centre = R(i, j, k);
+    const T edges = R(im, jm, k) + R(ip, jm, k) + R(im, jp, k) + R(ip, jp, k) +
+                    R(im, j, km) + R(ip, j, km) + R(im, j, kp) + R(ip, j, kp) +
+                    R(i, jm, km) + R(i, jp, km) + R(i, jm, kp) + R(i, jp, kp);
+    rc[sidx(I, J, K, nc)] = (T)0.125 * centre + (T)0.03125 * edges;
   }
 }
 
-// Trilinear prolongation and correction: e_f += P e_c on the fine box.
-// Coarse values outside the coarse box are zero.
+// Prolongation and correction of the black cells only: the next sweep starts
+// with the red colour, whose update reads only black neighbours and
+// overwrites the red values, so red cells need no correction.  Threads map
+// to (h, j, k) like the smoother; with all_cells each thread also corrects
+// the red cell of its pair.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_prolong(const T* __restrict__ ec, T* __restrict__ ef, int nc, int nf, Box bf) {
-  const int i = bf.lo[0] + blockIdx.x * kBoxTx + threadIdx.x;
-  const int j = bf.lo[1] + blockIdx.y * kBoxTy + threadIdx.y;
-  if (i > bf.hi[0] || j > bf.hi[1]) return;
+__device__ inline T prolong_at(const T* __restrict__ ec, int nc, int i, int j, int k) {
   const int mc = nc - 1;
-  const int k0 = bf.lo[2] + blockIdx.z * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, bf.hi[2]);
   const int i0 = i >> 1, i1 = ((i >> 1) + (i & 1)) & mc;
   const int j0 = j >> 1, j1 = ((j >> 1) + (j & 1)) & mc;
-  const T wi = (i & 1) ? (T)0.5 : (T)1, wj = (j & 1) ? (T)0.5 : (T)1;
+  const int c0 = k >> 1, c1 = ((k >> 1) + (k & 1)) & mc;
+  // trilinear: each axis averages (0, 1), which coincide on even indices
+  const T a = ec[sidx(i0, j0, c0, nc)] + ec[sidx(i1, j0, c0, nc)] + ec[sidx(i0, j1, c0, nc)] +
+              ec[sidx(i1, j1, c0, nc)] + ec[sidx(i0, j0, c1, nc)] + ec[sidx(i1, j0, c1, nc)] +
+              ec[sidx(i0, j1, c1, nc)] + ec[sidx(i1, j1, c1, nc)];
+  return (T)0.125 * a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_prolong(const T* __restrict__ ec, T* __restrict__ ef, int nc, int nf, Box bf, int all_cells) {
+  const Tile tl = tile_half(bf);
+  const int j = bf.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (j > bf.hi[1]) return;
+  const int h = (bf.lo[0] >> 1) + tl.bx * kBoxTx + threadIdx.x;
+  const int hn = nf >> 1;
+  const int64_t hc = half_cells(nf);
+  const int k0 = bf.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, bf.hi[2]);
   for (int k = k0; k <= k1; ++k) {
-    const int k0c = k >> 1, k1c = ((k >> 1) + (k & 1)) & mc;
-    const T wk = (k & 1) ? (T)0.5 : (T)1;
-    T v;
-    if (!(i & 1) && !(j & 1) && !(k & 1)) {
-      v = ec[lin(i0, j0, k0c, nc)];
-    } else {
-      // an odd index averages its two coarse neighbours (weight 1/2 each),
-      // an even index takes its coincident coarse value (weight 1)
-      v = 0;
-      const int is[2] = {i0, i1}, js[2] = {j0, j1}, ks[2] = {k0c, k1c};
-      const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-      for (int c = 0; c < nk; ++c)
-        for (int bb = 0; bb < nj; ++bb)
-          for (int a = 0; a < ni; ++a) v += ec[lin(is[a], js[bb], ks[c], nc)];
-      v *= wi * wj * wk;
+    const int64_t row = ((int64_t)k * nf + j) * hn + h;
+    for (int color = all_cells ? 0 : 1; color < 2; ++color) {
+      const int i = 2 * h + ((color + j + k) & 1);
+      if (i < bf.lo[0] || i > bf.hi[0]) continue;
+      ef[color * hc + row] += prolong_at(ec, nc, i, j, k);
     }
-    ef[lin(i, j, k, nf)] += v;
   }
 }
 
@@ -339,7 +394,7 @@ k_coarse(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T in
     nbr[u][5] = (cp * ly + b0) * lx + a0;
     const int i = b.lo[0] + qa, j = b.lo[1] + qb, k = b.lo[2] + qc;
     col[u] = (i + j + k) & 1;
-    gidx[u] = lin(i, j, k, n);
+    gidx[u] = sidx(i, j, k, n);
     rr[u] = r[gidx[u]];
     racc += (double)rr[u];
   }
@@ -411,8 +466,8 @@ void launch_residual(const double* phi, const double* rhs, T* r_out, int n, cons
   const dim3 g = box_grid(b);
   *nblocks = (int)(g.x * g.y * g.z);
   prof_begin(st);
-  hipLaunchKernelGGL(k_residual<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, rhs, r_out, n, b,
-                     kappa, partial);
+  hipLaunchKernelGGL(k_residual<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, rhs, r_out, n, b, kappa,
+                     partial);
   prof_end(st, K_RESIDUAL, (16.0 + sizeof(T)) * box_cells(b));
 }
 template void launch_residual<float>(const double*, const double*, float*, int, const Box&,
@@ -452,8 +507,26 @@ void launch_reduce_final(const double* partial, int nblocks, int nslots, double*
 }
 
 template <typename T>
-void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
-            bool periodic, hipStream_t st) {
+static void smooth_color(T* e, const T* r, const Level& L, int color, bool first, T scale,
+                         T inv_diag, hipStream_t st) {
+  const Box& b = L.box;
+  const dim3 g = half_grid(b);
+  prof_begin(st);
+  if (first)
+    hipLaunchKernelGGL((k_smooth_color<T, true>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
+                       color, scale, inv_diag);
+  else
+    hipLaunchKernelGGL((k_smooth_color<T, false>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
+                       color, scale, inv_diag);
+  // first (red, zero guess): r + e of the colour; otherwise e of the other
+  // colour + r and e of this colour: half the cells each
+  const double cells = (double)box_cells(b);
+  prof_end(st, first ? K_SMOOTH_FIRST : K_SMOOTH, (first ? 1.0 : 1.5) * sizeof(T) * cells);
+}
+
+template <typename T>
+const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
+                bool periodic, hipStream_t st) {
   const dim3 blk(kBoxTx, kBoxTy);
   const double es = sizeof(T);
   for (int l = 0; l < nlev - 1; ++l) {
@@ -461,31 +534,24 @@ void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coar
     const double cells = (double)box_cells(L.box);
     const T scale = (T)std::ldexp(1.0, 2 * l);
     const T inv_diag = (T)(1.0 / (6.0 + std::ldexp(1.0, 2 * l) * kappa));
-    const dim3 g = box_grid(L.box), gc = box_grid(L.box, 2 * kBoxTx);
     T* e = (T*)L.e;
     const T* r = (const T*)L.r;
     for (int s = 0; s < pre; ++s) {
-      prof_begin(st);
-      if (s == 0) {
-        hipLaunchKernelGGL(k_smooth_first<T>, g, blk, 0, st, e, r, L.n, L.box, scale, inv_diag);
-        prof_end(st, K_SMOOTH_FIRST, 2 * es * cells);
-      } else {
-        hipLaunchKernelGGL(k_smooth<T>, gc, blk, 0, st, e, r, L.n, L.box, 0, scale, inv_diag);
-        prof_end(st, K_SMOOTH, 2 * es * cells);
-      }
-      prof_begin(st);
-      hipLaunchKernelGGL(k_smooth<T>, gc, blk, 0, st, e, r, L.n, L.box, 1, scale, inv_diag);
-      prof_end(st, K_SMOOTH, 2 * es * cells);
+      smooth_color<T>(e, r, L, 0, s == 0, scale, inv_diag, st);
+      smooth_color<T>(e, r, L, 1, false, scale, inv_diag, st);
     }
-    prof_begin(st);
-    hipLaunchKernelGGL(k_resid_level<T>, g, blk, 0, st, e, r, (T*)L.t, L.n, L.box,
-                       (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa);
-    prof_end(st, K_RESID_LEVEL, 3 * es * cells);
+    {
+      const dim3 g = half_grid(L.box);
+      prof_begin(st);
+      hipLaunchKernelGGL(k_resid_red<T>, g, blk, 0, st, e, r, (T*)L.t, L.n, L.box,
+                         (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa);
+      prof_end(st, K_RESID_LEVEL, 2.0 * es * cells);
+    }
     const Level& C = lv[l + 1];
     prof_begin(st);
     hipLaunchKernelGGL(k_restrict<T>, box_grid(C.box), blk, 0, st, (const T*)L.t, (T*)C.r, L.n,
                        C.n, C.box);
-    prof_end(st, K_RESTRICT, es * (cells + (double)box_cells(C.box)));
+    prof_end(st, K_RESTRICT, es * (cells / 2 + (double)box_cells(C.box)));
   }
   {
     const int l = nlev - 1;
@@ -518,17 +584,9 @@ void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coar
       prof_end(st, K_COARSE, 2 * es * (double)box_cells(L.box));
     } else {
       // large degenerate Dirichlet box: sweeps through global memory
-      const dim3 g = box_grid(L.box), gc = box_grid(L.box, 2 * kBoxTx);
-      const double cells = (double)box_cells(L.box);
-      prof_begin(st);
-      hipLaunchKernelGGL(k_smooth_first<T>, g, blk, 0, st, (T*)L.e, (const T*)L.r, L.n, L.box,
-                         scale, inv_diag);
-      prof_end(st, K_SMOOTH_FIRST, 2 * es * cells);
-      for (int s = 0; s < 2 * sweeps - 1; ++s) {
-        prof_begin(st);
-        hipLaunchKernelGGL(k_smooth<T>, gc, blk, 0, st, (T*)L.e, (const T*)L.r, L.n, L.box,
-                           (s + 1) & 1, scale, inv_diag);
-        prof_end(st, K_SMOOTH, 2 * es * cells);
+      for (int s = 0; s < sweeps; ++s) {
+        smooth_color<T>((T*)L.e, (const T*)L.r, L, 0, s == 0, scale, inv_diag, st);
+        smooth_color<T>((T*)L.e, (const T*)L.r, L, 1, false, scale, inv_diag, st);
       }
     }
   }
@@ -539,21 +597,17 @@ void vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coar
     const T scale = (T)std::ldexp(1.0, 2 * l);
     const T inv_diag = (T)(1.0 / (6.0 + std::ldexp(1.0, 2 * l) * kappa));
     prof_begin(st);
-    hipLaunchKernelGGL(k_prolong<T>, box_grid(L.box), blk, 0, st, (const T*)C.e, (T*)L.e, C.n,
-                       L.n, L.box);
-    prof_end(st, K_PROLONG, es * (2 * cells + (double)box_cells(C.box)));
-    const dim3 gc = box_grid(L.box, 2 * kBoxTx);
+    hipLaunchKernelGGL(k_prolong<T>, half_grid(L.box), blk, 0, st, (const T*)C.e, (T*)L.e, C.n,
+                       L.n, L.box, post > 0 ? 0 : 1);
+    prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
     for (int s = 0; s < post; ++s) {
-      for (int color = 0; color < 2; ++color) {
-        prof_begin(st);
-        hipLaunchKernelGGL(k_smooth<T>, gc, blk, 0, st, (T*)L.e, (const T*)L.r, L.n, L.box, color,
-                           scale, inv_diag);
-        prof_end(st, K_SMOOTH, 2 * es * cells);
-      }
+      smooth_color<T>((T*)L.e, (const T*)L.r, L, 0, false, scale, inv_diag, st);
+      smooth_color<T>((T*)L.e, (const T*)L.r, L, 1, false, scale, inv_diag, st);
     }
   }
+  return (const T*)lv[0].e;
 }
-template void vcycle<float>(const Level*, int, double, int, int, int, bool, hipStream_t);
-template void vcycle<double>(const Level*, int, double, int, int, int, bool, hipStream_t);
+template const float* vcycle<float>(const Level*, int, double, int, int, int, bool, hipStream_t);
+template const double* vcycle<double>(const Level*, int, double, int, int, int, bool, hipStream_t);
 
 }  // namespace sdpm

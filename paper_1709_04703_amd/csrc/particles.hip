@@ -64,43 +64,130 @@ __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0,
   return (a + b) + c;
 }
 
+// Drift + deposit, 1024 particles per workgroup.  When the CIC cells of the
+// workgroup's particles fit a box of at most kDepLds cells (always for
+// spatially sorted particles, and for lattice order too) the weights are
+// summed with 64-bit LDS atomics and each touched cell is flushed with one
+// global atomic; otherwise every corner goes straight to global atomics.
+// Integer sums: the result is the same either way and in any order.
+constexpr int kDepPer = 4;
+constexpr int kDepLds = 4096;
+
+__device__ inline int wave_min(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_down(v, off, 64));
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_down(v, off, 64));
+  return v;
+}
+
 template <typename PT, bool DRIFT>
 __global__ void __launch_bounds__(256)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= pa.n) return;
-  double x[3];
-  for (int d = 0; d < 3; ++d) {
-    double v = pa.x[d][i];
-    if (DRIFT) {
-      v = v + (double)((const PT*)pa.p[d])[i] * coef;
-      if (mm.periodic) {
-        if (v < 0.0) v += mm.box;
-        if (v >= mm.box) v -= mm.box;
+  __shared__ unsigned long long acc[kDepLds];
+  __shared__ int blo[3], bhi[3];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * (256 * kDepPer);
+  if (tid < 3) {
+    blo[tid] = 0x7fffffff;
+    bhi[tid] = -0x7fffffff;
+  }
+  Cic c[kDepPer];
+  bool ok[kDepPer];
+  int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+  uint32_t bad_all = 0;
+#pragma unroll
+  for (int u = 0; u < kDepPer; ++u) {
+    const int64_t i = base + u * 256 + tid;
+    ok[u] = false;
+    if (i >= pa.n) continue;
+    double x[3];
+    for (int d = 0; d < 3; ++d) {
+      double v = pa.x[d][i];
+      if (DRIFT) {
+        v = v + (double)((const PT*)pa.p[d])[i] * coef;
+        if (mm.periodic) {
+          if (v < 0.0) v += mm.box;
+          if (v >= mm.box) v -= mm.box;
+        }
+        pa.x[d][i] = v;
       }
-      pa.x[d][i] = v;
+      x[d] = v;
     }
-    x[d] = v;
+    const uint32_t bad = cic_setup(x, mm, c[u]);
+    if (bad) {
+      bad_all |= bad;
+      continue;
+    }
+    ok[u] = true;
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = min(mn[d], c[u].cell[d]);
+      mx[d] = max(mx[d], c[u].cell[d]);
+    }
   }
-  Cic c;
-  const uint32_t bad = cic_setup(x, mm, c);
-  if (bad) {
-    atomicOr(flags, bad);
-    return;
+  if (bad_all) atomicOr(flags, bad_all);
+  __syncthreads();
+  for (int d = 0; d < 3; ++d) {
+    const int a = wave_min(mn[d]), b = wave_max(mx[d]);
+    if ((tid & 63) == 0) {
+      atomicMin(&blo[d], a);
+      atomicMax(&bhi[d], b);
+    }
   }
+  __syncthreads();
+  const int lx = bhi[0] - blo[0] + 2, ly = bhi[1] - blo[1] + 2, lz = bhi[2] - blo[2] + 2;
+  if (lx <= 1) return;                                   // no valid particle in the workgroup
   const int m = mm.ng - 1;
-  for (int dz = 0; dz < 2; ++dz) {
-    const int kk = mm.periodic ? ((c.cell[2] + dz) & m) : c.cell[2] + dz;
-    for (int dy = 0; dy < 2; ++dy) {
-      const int jj = mm.periodic ? ((c.cell[1] + dy) & m) : c.cell[1] + dy;
-      const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
-      if (wyz == 0) continue;
-      for (int dx = 0; dx < 2; ++dx) {
-        const uint64_t wgt = c.w[0][dx] * wyz;
-        if (wgt == 0) continue;
-        const int ii = mm.periodic ? ((c.cell[0] + dx) & m) : c.cell[0] + dx;
-        atomicAdd(counts + lin(ii, jj, kk, mm.ng), (unsigned long long)wgt);
+  const bool use_lds = (int64_t)lx * ly * lz <= kDepLds;
+  if (use_lds) {
+    const int vol = lx * ly * lz;
+    for (int q = tid; q < vol; q += 256) acc[q] = 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kDepPer; ++u) {
+      if (!ok[u]) continue;
+      const int ax = c[u].cell[0] - blo[0], ay = c[u].cell[1] - blo[1], az = c[u].cell[2] - blo[2];
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy) {
+          const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
+          if (wyz == 0) continue;
+          for (int dx = 0; dx < 2; ++dx) {
+            const uint64_t wgt = c[u].w[0][dx] * wyz;
+            if (wgt) atomicAdd(&acc[((az + dz) * ly + ay + dy) * lx + ax + dx], (unsigned long long)wgt);
+          }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < vol; q += 256) {
+      const unsigned long long v = acc[q];
+      if (!v) continue;
+      int gx = blo[0] + q % lx, gy = blo[1] + (q / lx) % ly, gz = blo[2] + q / (lx * ly);
+      if (mm.periodic) {
+        gx &= m;
+        gy &= m;
+        gz &= m;
+      }
+      atomicAdd(counts + lin(gx, gy, gz, mm.ng), v);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kDepPer; ++u) {
+      if (!ok[u]) continue;
+      for (int dz = 0; dz < 2; ++dz) {
+        const int kk = mm.periodic ? ((c[u].cell[2] + dz) & m) : c[u].cell[2] + dz;
+        for (int dy = 0; dy < 2; ++dy) {
+          const int jj = mm.periodic ? ((c[u].cell[1] + dy) & m) : c[u].cell[1] + dy;
+          const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
+          if (wyz == 0) continue;
+          for (int dx = 0; dx < 2; ++dx) {
+            const uint64_t wgt = c[u].w[0][dx] * wyz;
+            if (wgt == 0) continue;
+            const int ii = mm.periodic ? ((c[u].cell[0] + dx) & m) : c[u].cell[0] + dx;
+            atomicAdd(counts + lin(ii, jj, kk, mm.ng), (unsigned long long)wgt);
+          }
+        }
       }
     }
   }
@@ -307,12 +394,13 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
                           hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st);
+  const dim3 g(grid_for(pa.n, 256 * kDepPer));
   if (drift)
-    hipLaunchKernelGGL((k_drift_deposit<PT, true>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa,
-                       drift_coef, mm, (unsigned long long*)counts, flags);
+    hipLaunchKernelGGL((k_drift_deposit<PT, true>), g, dim3(256), 0, st, pa, drift_coef, mm,
+                       (unsigned long long*)counts, flags);
   else
-    hipLaunchKernelGGL((k_drift_deposit<PT, false>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st,
-                       pa, drift_coef, mm, (unsigned long long*)counts, flags);
+    hipLaunchKernelGGL((k_drift_deposit<PT, false>), g, dim3(256), 0, st, pa, drift_coef, mm,
+                       (unsigned long long*)counts, flags);
   const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
   prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
 }

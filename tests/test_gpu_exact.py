@@ -137,3 +137,78 @@ def test_deposit_in_dirichlet_box_and_domain_error():
     with pytest.raises(P.SdpmError, match="EDOMAIN"):
         sim2.deposit()
     sim2.close()
+
+
+def _morton_key(x, ng, box):
+    """Independent Morton code of each particle's cell (bit loop)."""
+    c = np.clip(np.floor(x * (ng / box)), 0, ng - 1).astype(np.int64)
+    key = np.zeros(x.shape[0], dtype=np.int64)
+    for b in range(11):
+        for d in range(3):
+            key |= ((c[:, d] >> b) & 1) << (3 * b + d)
+    return key
+
+
+@pytest.mark.parametrize("ng,n,prec", [(64, 100003, 0), (32, 5000, 1)])
+def test_morton_sort_permutes_and_orders(ng, n, prec):
+    box = 500.0
+    cfg = lib_config(ng, box, precision=prec, sort_every=1, n_initial=n)
+    x, p, ids = uniform_particles(n, box, 77)
+    log(f"morton sort ng={ng} n={n}")
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    sim.sort()
+    gx, gp, gid = sim.particles()
+    key = _morton_key(gx, ng, box)
+    assert np.all(np.diff(key) >= 0)
+    order = np.argsort(gid)
+    assert np.array_equal(gid[order], ids)
+    assert np.array_equal(gx[order], x)
+    pin = p.astype(np.float32).astype(np.float64) if prec == 0 else p
+    assert np.array_equal(gp[order], pin)
+    # stability: equal keys keep their previous relative order (ids increase)
+    same = np.diff(key) == 0
+    assert np.all(np.diff(gid.astype(np.int64))[same] > 0)
+    # the deposit of the sorted set (LDS-privatised path) is still exact
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(x, ng, box, B, True))
+    sim.close()
+
+
+def test_sorted_and_unsorted_steps_are_identical():
+    from synth import zeldovich_ics
+    ng, box, a0, da = 32, 200.0, 0.05, 0.02
+    x, p, ids = zeldovich_ics(ng, box, a0, 99, "eh")
+    out = []
+    for sort_every in (0, 1):
+        cfg = lib_config(ng, box, c_grav=-1.0, sort_every=sort_every, n_initial=ng**3)
+        sim = make_sim(cfg, ng**3)
+        sim.bind(x, p, ids)
+        sim.init_potential(a0)
+        sim.step(a0, da)
+        sim.step(a0 + da, da)
+        gx, gp, gid = sim.particles()
+        o = np.argsort(gid)
+        out.append((gx[o], gp[o], sim.phi_numpy().copy(), sim.counts_numpy().copy()))
+        sim.close()
+    for u, v in zip(out[0], out[1]):
+        assert np.array_equal(u, v)
+
+
+def test_step_run_twice_bit_identical():
+    from synth import zeldovich_ics
+    ng, box, a0, da = 32, 2000.0, 0.02, 0.01
+    x, p, ids = zeldovich_ics(ng, box, a0, 5, "eh")
+    res = []
+    for _ in range(2):
+        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3)
+        sim = make_sim(cfg, ng**3)
+        sim.bind(x, p, ids)
+        sim.init_potential(a0)
+        for s in range(3):
+            sim.step(a0 + s * da, da)
+        gx, gp, gid = sim.particles(all_particles=True)
+        res.append((gx, gp, gid, sim.phi_numpy().copy()))
+        sim.close()
+    for u, v in zip(res[0], res[1]):
+        assert np.array_equal(u, v)

@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(P):
 
 
 def test_struct_sizes_match_header_layout(P):
-    assert ctypes.sizeof(P.Config) == 128
+    assert ctypes.sizeof(P.Config) == 136
     assert ctypes.sizeof(P.StepStats) == 8 * 2 + 4 * 4 + 8 * 4 + 8 * 5 + 4 * 7 + 4 * 8 + 4
 
 
