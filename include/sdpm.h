@@ -115,6 +115,9 @@ typedef struct sdpm_step_stats {
   float ms[8];             /* [0] drift+deposit [1] rhs [2] solve 1
                               [3] force+kick+drift [4] solve 2
                               [5] removal+compaction [6] total           */
+  double res_guess[2];     /* relative residual of the accepted initial
+                              guess (equal to res0 when the learned guess
+                              was not used)                              */
 } sdpm_step_stats;
 
 /* Host-only scalars of one step a -> a + da (no device work):
@@ -195,9 +198,66 @@ int sdpm_sort(sdpm_ctx* ctx);
  * with the deposit's CIC weights; g_dev[3]: device FP64 arrays (n_active). */
 int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);
 
-/* Learned warm start: BF16 weights of the 5-layer 3^3 conv net (layout in
- * sdpm_net_layout); nbytes must equal the layout's total.                   */
-int sdpm_set_warmstart_weights(sdpm_ctx* ctx, const void* bf16_host, int64_t nbytes);
+/* Learned warm start ------------------------------------------------------
+ * Not in the paper: a learned initial guess for the multigrid solve of each
+ * implicit gravity sub-step.  A 5-layer 3x3x3 convolution net, 16 channels,
+ * ReLU between layers, periodic padding on the ng^3 mesh, BF16 weights and
+ * activations with FP32 accumulation on the matrix cores.  Input channels:
+ * the residual of the previous potential r0 = rhs - A phi_old (the density
+ * source minus the Laplacian of phi_old) scaled by 1/rms(r0), and phi_old
+ * scaled by 1/rms(phi_old).  Output: the change of the potential in units of
+ * 1/rms(r0).  The guess replaces phi_old only if its residual is smaller;
+ * the solve always continues to tol, so plain multigrid decides the result and
+ * the fallback.
+ * Parameters: SDPM_NET_PARAMS FP32 values, per layer l = 0..4 the weights
+ * W[t][ci][co] (27 x 16 x 16, tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) reading
+ * the input at (i+dx, j+dy, k+dz)) then the bias b[co] (16); input channels
+ * ci >= 2 of layer 0 and output channels co >= 1 of layer 4 are unused.
+ * Activations: ng^3 x 16 BF16 (uint16), channels fastest, voxel (i,j,k) at
+ * (k ng + j) ng + i.  Device pointers; work is enqueued on `stream`.        */
+#define SDPM_NET_PARAMS (5 * (27 * 16 * 16 + 16))
+enum { SDPM_CONV_RELU = 1, SDPM_CONV_OUT_FP32_CH0 = 2, SDPM_CONV_BACKWARD_DATA = 4,
+       SDPM_CONV_MASK = 8 };
+/* Loads FP32 parameters (host memory, n_params == SDPM_NET_PARAMS) into a
+ * context created with warm_start = SDPM_WS_LEARNED.                       */
+int sdpm_set_warmstart_weights(sdpm_ctx* ctx, const float* params_host, int64_t n_params);
+/* One convolution layer (flags: SDPM_CONV_*):
+ *   out[v][co] = bias[co] + sum_t sum_ci in[v + off_t][ci] W[t][ci][co],
+ * then ReLU; with BACKWARD_DATA the adjoint (mirrored taps, W transposed,
+ * no bias): out[u][ci] = sum_t sum_co in[u - off_t][co] W[t][ci][co], then
+ * times [mask > 0] with MASK (mask: BF16 activations).  out: BF16 ng^3 x 16,
+ * or FP32 ng^3 (channel 0) with OUT_FP32_CH0.  n: power of two >= 16.      */
+int sdpm_conv3d(int32_t n, const void* in_bf16, const float* w, const float* bias, int32_t flags,
+                const void* mask_bf16, void* out, void* stream);
+/* Weight and bias gradients of sum(out * g) for out = conv(in):
+ * dw[t][ci][co] = sum_v in[v + off_t][ci] g[v][co], db[co] = sum_v g[v][co];
+ * summed in a fixed order (deterministic).  scratch: sdpm_net_scratch_bytes. */
+int sdpm_conv3d_wgrad(int32_t n, const void* in_bf16, const void* g_bf16, float* dw, float* db,
+                      void* scratch, int64_t scratch_bytes, void* stream);
+/* Device scratch needed by sdpm_conv3d_wgrad and sdpm_net_train_step.      */
+int sdpm_net_scratch_bytes(int32_t n, int64_t* bytes);
+/* act0[v] = (r[v] s_r, phi[v] s_phi, 0, ..., 0) in BF16; r, phi FP32 ng^3. */
+int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi, void* act0,
+                  void* stream);
+/* Net forward: out (FP32 ng^3) = channel 0 of layer 5; act_a / act_b: two
+ * BF16 ng^3 x 16 buffers for the hidden layers.                            */
+int sdpm_net_forward(int32_t n, const float* params, const void* act0, void* act_a, void* act_b,
+                     float* out, void* stream);
+/* One training step on one sample: forward, loss = mean((out - target_scale
+ * target)^2)
+ * written to *loss_dev (device FP32), backward through all layers, Adam
+ * (beta 0.9 / 0.999, step counted from 1) on params with moments m1, m2.   */
+int sdpm_net_train_step(int32_t n, float* params, float* m1, float* m2, int32_t step, float lr,
+                        const void* act0, const float* target, float target_scale, void* scratch,
+                        int64_t scratch_bytes, float* loss_dev, void* stream);
+/* Records every multigrid solve of ctx (up to max_solves) into buf (device,
+ * FP32, 3 ng^3 per solve: r0 with zeros outside the active box, phi_old,
+ * and the converged change phi - phi_old), the training pairs of the net.  */
+int sdpm_record(sdpm_ctx* ctx, float* buf_dev, int64_t max_solves);
+/* Solves recorded so far, and per solve (up to max) kappa h^2, rms(r0) over
+ * the active box and rms(phi_old) over the mesh.                           */
+int sdpm_record_info(sdpm_ctx* ctx, int64_t* count, double* kappa_h2, double* rms_r,
+                     double* rms_phi, int64_t max);
 
 /* Per-kernel timing (tracing).  enable != 0: every kernel launch made by
  * this context is bracketed by a HIP event pair on the context's stream and

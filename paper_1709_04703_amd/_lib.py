@@ -31,9 +31,13 @@ EXPORTS = [
     "sdpm_step_scalars", "sdpm_lightcone_radius", "sdpm_domain_box", "sdpm_config_default",
     "sdpm_workspace_bytes", "sdpm_create", "sdpm_bind", "sdpm_init_potential", "sdpm_step",
     "sdpm_shrink", "sdpm_shrink_radius", "sdpm_get_state", "sdpm_deposit", "sdpm_solve",
-    "sdpm_interp_force", "sdpm_sort", "sdpm_set_warmstart_weights", "sdpm_profile", "sdpm_profile_read",
+    "sdpm_interp_force", "sdpm_sort", "sdpm_set_warmstart_weights", "sdpm_conv3d",
+    "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
+    "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error",
 ]
+NET_PARAMS = 5 * (27 * 16 * 16 + 16)
+CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
 
 
 class Config(ctypes.Structure):
@@ -75,7 +79,7 @@ class StepStats(ctypes.Structure):
         ("res", ctypes.c_double * 2), ("dtau", ctypes.c_double), ("a_half", ctypes.c_double),
         ("kappa_h2", ctypes.c_double * 2), ("r_lc", ctypes.c_double),
         ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3), ("periodic", ctypes.c_int32),
-        ("ms", ctypes.c_float * 8),
+        ("ms", ctypes.c_float * 8), ("res_guess", ctypes.c_double * 2),
     ]
 
     def as_dict(self) -> dict:
@@ -127,6 +131,15 @@ def library() -> ctypes.CDLL:
         "sdpm_interp_force": [vp, P(vp)],
         "sdpm_sort": [vp],
         "sdpm_set_warmstart_weights": [vp, vp, i64],
+        "sdpm_conv3d": [i32, vp, vp, vp, i32, vp, vp, vp],
+        "sdpm_conv3d_wgrad": [i32, vp, vp, vp, vp, vp, i64, vp],
+        "sdpm_net_scratch_bytes": [i32, P(i64)],
+        "sdpm_net_prep": [i32, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp],
+        "sdpm_net_forward": [i32, vp, vp, vp, vp, vp, vp],
+        "sdpm_net_train_step": [i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, ctypes.c_float, vp,
+                                i64, vp, vp],
+        "sdpm_record": [vp, vp, i64],
+        "sdpm_record_info": [vp, P(i64), P(dbl), P(dbl), P(dbl), i64],
         "sdpm_profile": [vp, i32],
         "sdpm_profile_read": [vp, P(KernelStat), i32, P(i32)],
         "sdpm_destroy": [vp],
@@ -190,6 +203,49 @@ def workspace_bytes(cfg: Config, capacity: int) -> int:
     b = ctypes.c_int64()
     check(library().sdpm_workspace_bytes(ctypes.byref(cfg), capacity, ctypes.byref(b)))
     return b.value
+
+
+# ------------------------------------------------------- learned warm start
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def conv3d(n, inp, w, bias, flags, mask, out):
+    """One convolution layer (see sdpm_conv3d); torch device tensors."""
+    check(library().sdpm_conv3d(n, _ptr(inp), _ptr(w), _ptr(bias), flags, _ptr(mask), _ptr(out),
+                                _stream()))
+
+
+def net_scratch_bytes(n: int) -> int:
+    b = ctypes.c_int64()
+    check(library().sdpm_net_scratch_bytes(n, ctypes.byref(b)))
+    return b.value
+
+
+def conv3d_wgrad(n, inp, g, dw, db, scratch):
+    check(library().sdpm_conv3d_wgrad(n, _ptr(inp), _ptr(g), _ptr(dw), _ptr(db), _ptr(scratch),
+                                      scratch.numel() * scratch.element_size(), _stream()))
+
+
+def net_prep(n, r, phi, s_r, s_phi, act0):
+    check(library().sdpm_net_prep(n, _ptr(r), _ptr(phi), s_r, s_phi, _ptr(act0), _stream()))
+
+
+def net_forward(n, params, act0, act_a, act_b, out):
+    check(library().sdpm_net_forward(n, _ptr(params), _ptr(act0), _ptr(act_a), _ptr(act_b),
+                                     _ptr(out), _stream()))
+
+
+def net_train_step(n, params, m1, m2, step, lr, act0, target, target_scale, scratch, loss):
+    check(library().sdpm_net_train_step(n, _ptr(params), _ptr(m1), _ptr(m2), step, lr, _ptr(act0),
+                                        _ptr(target), target_scale, _ptr(scratch),
+                                        scratch.numel() * scratch.element_size(), _ptr(loss),
+                                        _stream()))
 
 
 # ----------------------------------------------------------------- context
@@ -327,6 +383,27 @@ class Simulation:
         arr = (ctypes.c_void_p * 3)(*(g[d].data_ptr() for d in range(3)))
         self._check(self.lib.sdpm_interp_force(self.ctx, arr))
         return g[:, :n]
+
+    # -- learned warm start and solve recording
+    def set_warmstart_weights(self, params):
+        arr = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        self._check(self.lib.sdpm_set_warmstart_weights(
+            self.ctx, arr.ctypes.data_as(ctypes.c_void_p), arr.size))
+
+    def record(self, buf, max_solves: int):
+        """Record up to max_solves solves into buf (torch float32 device
+        tensor of at least max_solves * 3 * ng^3 entries)."""
+        self._record_buf = buf
+        self._check(self.lib.sdpm_record(self.ctx, _ptr(buf), max_solves))
+
+    def record_info(self):
+        cnt = ctypes.c_int64()
+        self._check(self.lib.sdpm_record_info(self.ctx, ctypes.byref(cnt), None, None, None, 0))
+        k = max(cnt.value, 1)
+        kap, rr, rp = (ctypes.c_double * k)(), (ctypes.c_double * k)(), (ctypes.c_double * k)()
+        self._check(self.lib.sdpm_record_info(self.ctx, ctypes.byref(cnt), kap, rr, rp, k))
+        n = cnt.value
+        return n, np.array(kap[:n]), np.array(rr[:n]), np.array(rp[:n])
 
     # -- tracing
     def profile(self, enable: bool = True):

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 #include <utility>
 
 #include "internal.h"
@@ -27,6 +28,19 @@ struct sdpm_ctx {
   uint32_t* boffsets = nullptr;
   void* scratch = nullptr;
   void* sort_scratch = nullptr;
+  // learned warm start
+  float* net_params = nullptr;
+  uint16_t* net_act0 = nullptr;
+  uint16_t* net_a = nullptr;
+  uint16_t* net_b = nullptr;
+  float* net_out = nullptr;
+  void* r_alt = nullptr;
+  bool net_ready = false;
+  int warm_used = 0;
+  // solve recording
+  float* rec_buf = nullptr;
+  int64_t rec_max = 0, rec_count = 0;
+  std::vector<double> rec_kappa, rec_rms_r, rec_rms_phi;
   int64_t steps_done = 0;
   double* hpin = nullptr;       // host copies of device scalars
   hipEvent_t ev[8] = {};
@@ -108,8 +122,10 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (!(c->tol > 0.0)) return snprintf(msg, len, "tol must be > 0"), SDPM_EINVAL;
   if (c->precision != SDPM_MIXED && c->precision != SDPM_PLAIN_FP64)
     return snprintf(msg, len, "unknown precision %d", c->precision), SDPM_EINVAL;
-  if (c->warm_start != SDPM_WS_PREV)
-    return snprintf(msg, len, "warm_start: only SDPM_WS_PREV is available"), SDPM_EINVAL;
+  if (c->warm_start != SDPM_WS_PREV && c->warm_start != SDPM_WS_LEARNED)
+    return snprintf(msg, len, "unknown warm_start %d", c->warm_start), SDPM_EINVAL;
+  if (c->warm_start == SDPM_WS_LEARNED && !net_size_ok(c->ng))
+    return snprintf(msg, len, "the learned warm start needs ng >= 16"), SDPM_EINVAL;
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
   if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
     return snprintf(msg, len, "sort_every and sort_shift must be >= 0, ng >> sort_shift >= 1"), SDPM_EINVAL;
@@ -154,6 +170,23 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
   void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
   void* sscr = c.sort_every > 0 ? take(sort_scratch_bytes(capacity)) : nullptr;
+  if (c.warm_start == SDPM_WS_LEARNED) {
+    const size_t V = (size_t)c.ng * c.ng * c.ng;
+    float* prm = (float*)take(kNetParams * sizeof(float));
+    uint16_t* a0 = (uint16_t*)take(V * 16 * sizeof(uint16_t));
+    uint16_t* aa = (uint16_t*)take(V * 16 * sizeof(uint16_t));
+    uint16_t* ab = (uint16_t*)take(V * 16 * sizeof(uint16_t));
+    float* out = (float*)take(V * sizeof(float));
+    void* ralt = take(V * mg_elem(c));
+    if (ctx) {
+      ctx->net_params = prm;
+      ctx->net_act0 = a0;
+      ctx->net_a = aa;
+      ctx->net_b = ab;
+      ctx->net_out = out;
+      ctx->r_alt = ralt;
+    }
+  }
   if (ctx) {
     ctx->sort_scratch = sscr;
     ctx->partial = partial;
@@ -316,8 +349,8 @@ void assemble_rhs(sdpm_ctx* c, double s_source, double kappa) {
 }
 
 struct SolveOut {
-  double res0 = 0, res = 0;
-  int iters = 0, vcycles = 0;
+  double res0 = 0, res = 0, res_guess = 0;
+  int iters = 0, vcycles = 0, warm = 0;
 };
 
 // FP64 defect correction around V-cycles in T; rhs and ||rhs||^2 (dscal[0])
@@ -337,11 +370,53 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
   double rn = std::sqrt(c->hpin[1]);
   const double thresh = g.tol * denom;
   so->res0 = rn / denom;
+  so->warm = 0;
+  const double cells = (double)box_cells(b);
+  const bool recording = c->rec_buf && c->rec_count < c->rec_max;
+  float* rec = recording ? c->rec_buf + (size_t)c->rec_count * 3 * (size_t)g.ng * g.ng * g.ng : nullptr;
+  double rms_phi = 0.0;
+  if ((c->net_ready && rn > thresh) || recording) {
+    launch_sum_sq(c->fields.phi, g.ng, full_box(g.ng), c->partial, &nb, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + 3, c->st);
+    rc = sync_scalars(c, 4);
+    if (rc) return rc;
+    rms_phi = std::sqrt(c->hpin[3] / ((double)g.ng * g.ng * g.ng));
+  }
+  if (recording) {
+    launch_record_start<T>((const T*)c->lv[0].r, c->fields.phi, g.ng, b, rec, c->st);
+    c->rec_kappa.push_back(kappa);
+    c->rec_rms_r.push_back(rn / std::sqrt(cells));
+    c->rec_rms_phi.push_back(rms_phi);
+    ++c->rec_count;
+  }
+  if (c->net_ready && rn > thresh && rn > 0.0 && rms_phi > 0.0) {
+    // learned initial guess, kept only if it lowers the residual
+    const double rms_r = rn / std::sqrt(cells);
+    const Box* pb = c->periodic ? nullptr : &b;
+    launch_net_prep<T, double, true>(g.ng, (const T*)c->lv[0].r, c->fields.phi,
+                                     (float)(1.0 / rms_r), (float)(1.0 / rms_phi), pb, c->net_act0,
+                                     c->st);
+    net_forward(g.ng, c->net_params, c->net_act0, c->net_a, c->net_b, c->net_out, c->st);
+    launch_residual_guess<T>(c->fields.phi, c->net_out, rms_r, c->fields.rhs, (T*)c->r_alt, g.ng, b,
+                             kappa, c->partial, &nb, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+    rc = sync_scalars(c, 2);
+    if (rc) return rc;
+    const double rg = std::sqrt(c->hpin[1]);
+    if (std::isfinite(rg) && rg < rn) {
+      launch_apply_guess(c->fields.phi, c->net_out, rms_r, g.ng, b, c->st);
+      std::swap(c->lv[0].r, c->r_alt);
+      rn = rg;
+      so->warm = 1;
+    }
+  }
+  so->res_guess = rn / denom;
   int it = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
     const T* e0 =
         vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
     launch_correct<T>(c->fields.phi, e0, g.ng, b, c->st);
+    if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
@@ -731,10 +806,13 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   st.outer_iters[0] = s1.iters;
   st.outer_iters[1] = s2.iters;
   st.vcycles = s1.vcycles + s2.vcycles;
+  st.warm_used = s1.warm + s2.warm;
   st.res0[0] = s1.res0;
   st.res[0] = s1.res;
   st.res0[1] = s2.res0;
   st.res[1] = s2.res;
+  st.res_guess[0] = s1.res_guess;
+  st.res_guess[1] = s2.res_guess;
   fill_state(c, &st);
   if (out) *out = st;
   if (ferr) return ferr;
@@ -794,8 +872,10 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
     std::memset(out, 0, sizeof(*out));
     out->outer_iters[0] = so.iters;
     out->vcycles = so.vcycles;
+    out->warm_used = so.warm;
     out->res0[0] = so.res0;
     out->res[0] = so.res;
+    out->res_guess[0] = so.res_guess;
     out->kappa_h2[0] = kappa_h2;
     fill_state(c, out);
   }
@@ -830,11 +910,103 @@ int sdpm_interp_force(sdpm_ctx* c, double* g_dev[3]) {
   return flags_error(c);
 }
 
-int sdpm_set_warmstart_weights(sdpm_ctx* c, const void* bf16_host, int64_t nbytes) {
+int sdpm_set_warmstart_weights(sdpm_ctx* c, const float* params_host, int64_t n_params) {
   if (!c) return SDPM_EINVAL;
-  (void)bf16_host;
-  (void)nbytes;
-  return fail(c, SDPM_EINVAL, "learned warm start is not available in this build");
+  if (!c->net_params)
+    return fail(c, SDPM_ESTATE, "the context was created without warm_start = SDPM_WS_LEARNED");
+  if (!params_host || n_params != kNetParams)
+    return fail(c, SDPM_EINVAL, "expected %d parameters", kNetParams);
+  HIP_TRY(c, hipMemcpyAsync(c->net_params, params_host, kNetParams * sizeof(float),
+                            hipMemcpyHostToDevice, c->st));
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  c->net_ready = true;
+  return SDPM_OK;
+}
+
+int sdpm_record(sdpm_ctx* c, float* buf_dev, int64_t max_solves) {
+  if (!c) return SDPM_EINVAL;
+  if (max_solves < 0 || (max_solves > 0 && !buf_dev)) return fail(c, SDPM_EINVAL, "bad record buffer");
+  if (c->net_ready) return fail(c, SDPM_ESTATE, "recording needs the plain warm start");
+  c->rec_buf = max_solves ? buf_dev : nullptr;
+  c->rec_max = max_solves;
+  c->rec_count = 0;
+  c->rec_kappa.clear();
+  c->rec_rms_r.clear();
+  c->rec_rms_phi.clear();
+  return SDPM_OK;
+}
+
+int sdpm_record_info(sdpm_ctx* c, int64_t* count, double* kappa_h2, double* rms_r,
+                     double* rms_phi, int64_t max) {
+  if (!c || !count) return SDPM_EINVAL;
+  *count = c->rec_count;
+  for (int64_t q = 0; q < c->rec_count && q < max; ++q) {
+    if (kappa_h2) kappa_h2[q] = c->rec_kappa[q];
+    if (rms_r) rms_r[q] = c->rec_rms_r[q];
+    if (rms_phi) rms_phi[q] = c->rec_rms_phi[q];
+  }
+  return SDPM_OK;
+}
+
+int sdpm_conv3d(int32_t n, const void* in_bf16, const float* w, const float* bias, int32_t flags,
+                const void* mask_bf16, void* out, void* stream) {
+  if (!net_size_ok(n) || !in_bf16 || !w || !out)
+    return fail(nullptr, SDPM_EINVAL, "conv3d: n must be a power of two >= 16, pointers non-NULL");
+  if (flags != 0 && flags != SDPM_CONV_RELU && flags != SDPM_CONV_OUT_FP32_CH0 &&
+      flags != SDPM_CONV_BACKWARD_DATA &&
+      flags != (SDPM_CONV_BACKWARD_DATA | SDPM_CONV_MASK))
+    return fail(nullptr, SDPM_EINVAL, "conv3d: unsupported flag combination %d", flags);
+  if ((flags & SDPM_CONV_MASK) && !mask_bf16) return fail(nullptr, SDPM_EINVAL, "conv3d: mask is NULL");
+  launch_conv(n, (const uint16_t*)in_bf16, w, bias, flags, (const uint16_t*)mask_bf16, out,
+              (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "conv3d launch failed");
+}
+
+int sdpm_net_scratch_bytes(int32_t n, int64_t* bytes) {
+  if (!net_size_ok(n) || !bytes) return fail(nullptr, SDPM_EINVAL, "n must be a power of two >= 16");
+  *bytes = (int64_t)net_train_scratch_bytes(n);
+  return SDPM_OK;
+}
+
+int sdpm_conv3d_wgrad(int32_t n, const void* in_bf16, const void* g_bf16, float* dw, float* db,
+                      void* scratch, int64_t scratch_bytes, void* stream) {
+  if (!net_size_ok(n) || !in_bf16 || !g_bf16 || !dw || !db || !scratch)
+    return fail(nullptr, SDPM_EINVAL, "conv3d_wgrad: bad arguments");
+  if ((size_t)scratch_bytes < wgrad_scratch_bytes(n))
+    return fail(nullptr, SDPM_ENOMEM, "conv3d_wgrad: scratch too small");
+  launch_conv_wgrad(n, (const uint16_t*)in_bf16, (const uint16_t*)g_bf16, dw, db, (float*)scratch,
+                    (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "wgrad launch failed");
+}
+
+int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi, void* act0,
+                  void* stream) {
+  if (!net_size_ok(n) || !r || !phi || !act0) return fail(nullptr, SDPM_EINVAL, "net_prep: bad arguments");
+  launch_net_prep<float, float, false>(n, r, phi, s_r, s_phi, nullptr, (uint16_t*)act0,
+                                       (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "net_prep launch failed");
+}
+
+int sdpm_net_forward(int32_t n, const float* params, const void* act0, void* act_a, void* act_b,
+                     float* out, void* stream) {
+  if (!net_size_ok(n) || !params || !act0 || !act_a || !act_b || !out)
+    return fail(nullptr, SDPM_EINVAL, "net_forward: bad arguments");
+  net_forward(n, params, (const uint16_t*)act0, (uint16_t*)act_a, (uint16_t*)act_b, out,
+              (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "net_forward failed");
+}
+
+int sdpm_net_train_step(int32_t n, float* params, float* m1, float* m2, int32_t step, float lr,
+                        const void* act0, const float* target, float target_scale, void* scratch,
+                        int64_t scratch_bytes, float* loss_dev, void* stream) {
+  if (!net_size_ok(n) || !params || !m1 || !m2 || !act0 || !target || !scratch || !loss_dev ||
+      step < 1 || !(lr > 0.f))
+    return fail(nullptr, SDPM_EINVAL, "net_train_step: bad arguments");
+  if ((size_t)scratch_bytes < net_train_scratch_bytes(n))
+    return fail(nullptr, SDPM_ENOMEM, "net_train_step: scratch too small");
+  net_train_step(n, params, m1, m2, step, lr, (const uint16_t*)act0, target, target_scale, scratch,
+                 loss_dev, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "train step failed");
 }
 
 int sdpm_profile(sdpm_ctx* c, int32_t enable) {

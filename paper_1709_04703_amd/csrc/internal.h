@@ -137,6 +137,38 @@ template <typename PT>
 void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, void* sort_scratch,
                         void* particle_scratch, hipStream_t st);
 
+// Learned warm start (net.hip).
+constexpr int kNetParams = 5 * (27 * 16 * 16 + 16);
+bool net_size_ok(int n);
+void launch_conv(int n, const uint16_t* in, const float* w, const float* bias, int flags,
+                 const uint16_t* mask, void* out, hipStream_t st);
+size_t wgrad_scratch_bytes(int n);
+void launch_conv_wgrad(int n, const uint16_t* in, const uint16_t* g, float* dw, float* db,
+                       float* scratch, hipStream_t st);
+template <typename RT, typename PT, bool SPLIT>
+void launch_net_prep(int n, const RT* r, const PT* phi, float s_r, float s_phi, const Box* box,
+                     uint16_t* act0, hipStream_t st);
+void net_forward(int n, const float* params, const uint16_t* act0, uint16_t* a, uint16_t* b,
+                 float* out, hipStream_t st);
+size_t net_train_scratch_bytes(int n);
+void net_train_step(int n, float* params, float* m1, float* m2, int step, float lr,
+                    const uint16_t* act0, const float* target, float target_scale, void* scratch,
+                    float* loss_out, hipStream_t st);
+// mesh.hip helpers for the warm start and for recording solves
+template <typename T>
+void launch_residual_guess(const double* phi, const float* d, double scale, const double* rhs,
+                           T* r_out, int n, const Box& b, double kappa, double* partial,
+                           int* nblocks, hipStream_t st);
+void launch_apply_guess(double* phi, const float* d, double scale, int n, const Box& b,
+                        hipStream_t st);
+void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,
+                   hipStream_t st);
+template <typename T>
+void launch_record_start(const T* r_split, const double* phi, int n, const Box& b, float* rec,
+                         hipStream_t st);
+template <typename T>
+void launch_record_accum(const T* e_split, int n, const Box& b, float* dphi, hipStream_t st);
+
 // flags written by kernels
 enum : uint32_t { kFlagDomain = 1u, kFlagOverflow = 2u };
 
@@ -150,7 +182,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
-  K_SORT, K_GATHER,
+  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

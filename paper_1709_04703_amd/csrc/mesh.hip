@@ -436,6 +436,107 @@ k_coarse(T* __restrict__ e, const T* __restrict__ r, int n, Box b, T scale, T in
     if (u < nown) e[gidx[u]] = es[own[u]] - emean;
 }
 
+// Residual of phi + scale * d, with d applied only inside the box (the
+// learned initial guess); written colour-split like k_residual.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_residual_guess(const double* __restrict__ phi, const float* __restrict__ d, double scale,
+                 const double* __restrict__ rhs, T* __restrict__ rout, int n, Box b, double kappa,
+                 double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  const int m = n - 1;
+  auto inb = [&](int x, int y, int z) {
+    return x >= b.lo[0] && x <= b.hi[0] && y >= b.lo[1] && y <= b.hi[1] && z >= b.lo[2] &&
+           z <= b.hi[2];
+  };
+  auto v = [&](int x, int y, int z) -> double {
+    const int64_t c = lin(x, y, z, n);
+    return inb(x, y, z) ? phi[c] + scale * (double)d[c] : phi[c];
+  };
+  double acc = 0.0;
+  if (i <= b.hi[0] && j <= b.hi[1]) {
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
+    const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+    const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
+    for (int k = k0; k <= k1; ++k) {
+      const int kp = (k + 1) & m, km = (k - 1) & m;
+      const double ctr = v(i, j, k);
+      const double nb = v(ip, j, k) + v(im, j, k) + v(i, jp, k) + v(i, jm, k) + v(i, j, kp) +
+                        v(i, j, km);
+      const double res = rhs[lin(i, j, k, n)] - (nb - 6.0 * ctr - kappa * ctr);
+      rout[sidx(i, j, k, n)] = (T)res;
+      acc += res * res;
+    }
+  }
+  const double s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
+}
+
+__global__ void __launch_bounds__(256)
+k_apply_guess(double* __restrict__ phi, const float* __restrict__ d, double scale, int n, Box b) {
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  for (int k = k0; k <= k1; ++k) {
+    const int64_t c = lin(i, j, k, n);
+    phi[c] += scale * (double)d[c];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_sum_sq(const double* __restrict__ phi, int n, Box b, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  double acc = 0.0;
+  if (i <= b.hi[0] && j <= b.hi[1]) {
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
+    const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+    for (int k = k0; k <= k1; ++k) {
+      const double v = phi[lin(i, j, k, n)];
+      acc += v * v;
+    }
+  }
+  const double s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
+}
+
+// Solve recording (training pairs): rec = [r0 | phi_old | dphi], each n^3
+// FP32 in natural order; r0 is zero outside the box, dphi starts at zero.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_record_start(const T* __restrict__ r, const double* __restrict__ phi, int n, Box b,
+               float* __restrict__ rec) {
+  const int64_t V = (int64_t)n * n * n;
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V) return;
+  const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((int64_t)n * n));
+  const bool in = i >= b.lo[0] && i <= b.hi[0] && j >= b.lo[1] && j <= b.hi[1] && k >= b.lo[2] &&
+                  k <= b.hi[2];
+  rec[v] = in ? (float)r[sidx(i, j, k, n)] : 0.f;
+  rec[V + v] = (float)phi[v];
+  rec[2 * V + v] = 0.f;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_record_accum(const T* __restrict__ e, int n, Box b, float* __restrict__ dphi) {
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  for (int k = k0; k <= k1; ++k) dphi[lin(i, j, k, n)] += (float)e[sidx(i, j, k, n)];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -505,6 +606,59 @@ void launch_reduce_final(const double* partial, int nblocks, int nslots, double*
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, st, partial, nblocks, nslots, out);
   prof_end(st, K_REDUCE, 8.0 * nblocks * nslots);
 }
+
+
+template <typename T>
+void launch_residual_guess(const double* phi, const float* d, double scale, const double* rhs,
+                           T* r_out, int n, const Box& b, double kappa, double* partial,
+                           int* nblocks, hipStream_t st) {
+  const dim3 g = box_grid(b);
+  *nblocks = (int)g.x;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_residual_guess<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, rhs, r_out,
+                     n, b, kappa, partial);
+  prof_end(st, K_NET_MISC, (20.0 + sizeof(T)) * box_cells(b));
+}
+template void launch_residual_guess<float>(const double*, const float*, double, const double*,
+                                           float*, int, const Box&, double, double*, int*,
+                                           hipStream_t);
+template void launch_residual_guess<double>(const double*, const float*, double, const double*,
+                                            double*, int, const Box&, double, double*, int*,
+                                            hipStream_t);
+
+void launch_apply_guess(double* phi, const float* d, double scale, int n, const Box& b,
+                        hipStream_t st) {
+  prof_begin(st);
+  hipLaunchKernelGGL(k_apply_guess, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, n, b);
+  prof_end(st, K_NET_MISC, 20.0 * box_cells(b));
+}
+
+void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,
+                   hipStream_t st) {
+  const dim3 g = box_grid(b);
+  *nblocks = (int)g.x;
+  hipLaunchKernelGGL(k_sum_sq, g, dim3(kBoxTx, kBoxTy), 0, st, phi, n, b, partial);
+}
+
+template <typename T>
+void launch_record_start(const T* r_split, const double* phi, int n, const Box& b, float* rec,
+                         hipStream_t st) {
+  const int64_t V = (int64_t)n * n * n;
+  hipLaunchKernelGGL(k_record_start<T>, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, r_split,
+                     phi, n, b, rec);
+}
+template void launch_record_start<float>(const float*, const double*, int, const Box&, float*,
+                                         hipStream_t);
+template void launch_record_start<double>(const double*, const double*, int, const Box&, float*,
+                                          hipStream_t);
+
+template <typename T>
+void launch_record_accum(const T* e_split, int n, const Box& b, float* dphi, hipStream_t st) {
+  hipLaunchKernelGGL(k_record_accum<T>, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, e_split, n, b,
+                     dphi);
+}
+template void launch_record_accum<float>(const float*, int, const Box&, float*, hipStream_t);
+template void launch_record_accum<double>(const double*, int, const Box&, float*, hipStream_t);
 
 template <typename T>
 static void smooth_color(T* e, const T* r, const Level& L, int color, bool first, T scale,

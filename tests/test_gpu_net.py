@@ -1,0 +1,202 @@
+"""GPU checks of the learned warm start: each matrix-core convolution kernel
+against the oracle's FP64 convolution on identical BF16 operands, the whole
+net forward, training on the method's own recorded solves, and the warm
+start inside the solve (accepted only when it lowers the residual; plain
+multigrid is the fallback, including for non-finite weights)."""
+import numpy as np
+import pytest
+
+from oracle import conv as oc
+from synth import zeldovich_ics
+
+from helpers import lib_config, log, make_sim, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_tensor(x):
+    """float64 array (already BF16-representable) -> int16 device tensor."""
+    import torch
+    u = np.asarray(x, dtype=np.float32).view(np.uint32) >> 16
+    return torch.as_tensor(u.astype(np.uint16).view(np.int16)).cuda()
+
+
+def _from_bf16(t):
+    u = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def _random_act(n, seed, positive=False):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.normal(size=(n, n, n, 16))
+    if positive:
+        x = np.maximum(x, 0.0)
+    return oc.bf16_round(x)
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_conv_forward_matches_oracle(n):
+    import torch
+    import paper_1709_04703_amd as P
+    log(f"conv forward n={n}")
+    x = _random_act(n, n)
+    rng = np.random.Generator(np.random.PCG64(100 + n))
+    w = rng.normal(size=(27, 16, 16)) * 0.1
+    b = rng.normal(size=16) * 0.1
+    wq = oc.bf16_round(w)
+    ref = oc.conv(x, wq, b)
+    xin = _bf16_tensor(x).reshape(-1, 16)
+    wt = torch.as_tensor(w.astype(np.float32)).cuda()
+    bt = torch.as_tensor(b.astype(np.float32)).cuda()
+    out0 = torch.zeros(n**3, dtype=torch.float32, device="cuda")
+    P.conv3d(n, xin, wt, bt, P.CONV_OUT_FP32_CH0, None, out0)
+    got0 = out0.cpu().numpy().reshape(n, n, n)
+    assert rel_rms(got0, ref[..., 0]) < 1e-5
+    outb = torch.zeros_like(xin)
+    P.conv3d(n, xin, wt, bt, P.CONV_RELU, None, outb)
+    got = _from_bf16(outb).reshape(n, n, n, 16)
+    refr = np.maximum(ref, 0.0)
+    refq = oc.bf16_round(refr)
+    # equal up to one BF16 rounding step where the FP32 sum straddles a
+    # rounding boundary (or the ReLU threshold, within FP32 accumulation error)
+    diff = np.abs(got - refq)
+    tol = np.maximum(np.abs(refq) * 2.0**-7, 1e-5 * np.sqrt(np.mean(ref**2)))
+    assert np.all(diff <= 1.01 * tol)
+    assert np.mean(diff > 0) < 0.01
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_conv_backward_data_matches_oracle(n):
+    import torch
+    import paper_1709_04703_amd as P
+    g = _random_act(n, 7 + n)
+    mask = _random_act(n, 9 + n, positive=True)
+    rng = np.random.Generator(np.random.PCG64(n))
+    w = rng.normal(size=(27, 16, 16)) * 0.1
+    ref = oc.conv_dgrad(g, oc.bf16_round(w)) * (mask > 0)
+    out = torch.zeros((n**3, 16), dtype=torch.int16, device="cuda")
+    P.conv3d(n, _bf16_tensor(g).reshape(-1, 16), torch.as_tensor(w.astype(np.float32)).cuda(), None,
+             P.CONV_BACKWARD_DATA | P.CONV_MASK, _bf16_tensor(mask).reshape(-1, 16), out)
+    got = _from_bf16(out).reshape(n, n, n, 16)
+    refq = oc.bf16_round(ref)
+    diff = np.abs(got - refq)
+    tol = np.maximum(np.abs(refq) * 2.0**-7, 1e-5 * np.sqrt(np.mean(ref**2)))
+    assert np.all(diff <= 1.01 * tol)
+    assert rel_rms(got, ref) < 5e-3
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_conv_weight_gradient_matches_oracle(n):
+    import torch
+    import paper_1709_04703_amd as P
+    x = _random_act(n, 3 * n)
+    g = _random_act(n, 5 * n)
+    dw_ref, db_ref, _ = oc.conv_wgrad(x, g)
+    dw = torch.zeros((27, 16, 16), dtype=torch.float32, device="cuda")
+    db = torch.zeros(16, dtype=torch.float32, device="cuda")
+    scratch = torch.zeros(P.net_scratch_bytes(n), dtype=torch.uint8, device="cuda")
+    P.conv3d_wgrad(n, _bf16_tensor(x).reshape(-1, 16), _bf16_tensor(g).reshape(-1, 16), dw, db,
+                   scratch)
+    assert rel_rms(dw.cpu().numpy(), dw_ref) < 1e-5
+    assert rel_rms(db.cpu().numpy(), db_ref) < 1e-5
+    dw2 = torch.zeros_like(dw)
+    P.conv3d_wgrad(n, _bf16_tensor(x).reshape(-1, 16), _bf16_tensor(g).reshape(-1, 16), dw2, db,
+                   scratch)
+    assert torch.equal(dw, dw2)                     # deterministic reduction
+
+
+def test_net_forward_matches_oracle():
+    import torch
+    import paper_1709_04703_amd as P
+    from paper_1709_04703_amd.train import init_params
+    n = 16
+    rng = np.random.Generator(np.random.PCG64(4))
+    r = rng.normal(size=(n, n, n))
+    phi = rng.normal(size=(n, n, n))
+    vec = init_params(3)
+    params = oc.unflatten(vec)
+    x0 = np.zeros((n, n, n, 16))
+    x0[..., 0] = r * 0.5
+    x0[..., 1] = phi * 2.0
+    _, ref = oc.forward(x0, params, round_bf16=True)
+    act0 = torch.zeros((n**3, 16), dtype=torch.int16, device="cuda")
+    P.net_prep(n, torch.as_tensor(r.astype(np.float32)).cuda().reshape(-1),
+               torch.as_tensor(phi.astype(np.float32)).cuda().reshape(-1), 0.5, 2.0, act0)
+    assert np.array_equal(_from_bf16(act0).reshape(n, n, n, 16), oc.bf16_round(x0))
+    a = torch.zeros_like(act0)
+    b = torch.zeros_like(act0)
+    out = torch.zeros(n**3, dtype=torch.float32, device="cuda")
+    P.net_forward(n, torch.as_tensor(vec).cuda(), act0, a, b, out)
+    err = rel_rms(out.cpu().numpy().reshape(n, n, n), ref)
+    log(f"  net forward rel rms vs oracle = {err:.2e}")
+    assert err < 2e-2
+
+
+def test_training_reduces_loss_on_one_sample():
+    import torch
+    from paper_1709_04703_amd.train import Trainer, init_params
+    n = 16
+    rng = np.random.Generator(np.random.PCG64(8))
+    r = torch.as_tensor(rng.normal(size=n**3).astype(np.float32)).cuda()
+    phi = torch.as_tensor(rng.normal(size=n**3).astype(np.float32)).cuda()
+    # target: a smooth function of r (a local average), learnable by the net
+    rr = r.cpu().numpy().reshape(n, n, n)
+    tgt = sum(np.roll(rr, s, axis=a) for a in range(3) for s in (-1, 1)) / 6.0
+    buf = torch.stack([r, phi, torch.as_tensor(tgt.astype(np.float32).ravel()).cuda()])[None]
+    tr = Trainer(n, init_params(1), lr=3e-3)
+    hist = tr.train(buf, np.array([1.0]), np.array([1.0]), 300, log_every=50)
+    log(f"  loss history {hist}")
+    assert hist[-1][1] < 0.2 * hist[0][1]
+
+
+def test_learned_warm_start_trains_and_falls_back():
+    """Train on the method's own solves (64^3, periodic phase) and use the
+    net as the initial guess of the same configuration with another seed:
+    the solve still reaches tol, the accepted guesses lower the starting
+    residual, and non-finite weights fall back to plain multigrid."""
+    import paper_1709_04703_amd as P
+    from paper_1709_04703_amd.train import Trainer, init_params, record_pairs
+    ng, box, a0, nsteps = 64, 2000.0, 1.0 / 50.0, 40
+    ics = [zeldovich_ics(ng, box, a0, s) for s in (11, 12)]
+    buf, kap, rms_r, rms_phi = record_pairs(ics, ng, box, a0, nsteps, 60)
+    log(f"  recorded {buf.shape[0]} solves")
+    assert buf.shape[0] >= 40
+    tr = Trainer(ng, init_params(0), lr=1e-3)
+    hist = tr.train(buf, rms_r, rms_phi, 400, log_every=100)
+    log(f"  loss history {hist}")
+    err = tr.evaluate(buf, rms_r, rms_phi, range(0, buf.shape[0], 7))
+    log(f"  relative error of the predicted change on training pairs: {err:.3f}")
+    weights = tr.weights()
+    x, p, ids = zeldovich_ics(ng, box, a0, 13)
+    res = {}
+    for mode in ("prev", "learned", "nan"):
+        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3,
+                         warm_start=P.SDPM_WS_PREV if mode == "prev" else P.SDPM_WS_LEARNED)
+        sim = make_sim(cfg, ng**3)
+        if mode == "learned":
+            sim.set_warmstart_weights(weights)
+        elif mode == "nan":
+            bad = weights.copy()
+            bad[::7] = np.nan
+            sim.set_warmstart_weights(bad)
+        sim.bind(x, p, ids)
+        sim.init_potential(a0)
+        edges = np.linspace(a0, 1.0, nsteps + 1)
+        iters, used, g0, r0 = [], 0, [], []
+        for s in range(12):
+            st = sim.step(edges[s], edges[s + 1] - edges[s])
+            assert max(st["res"]) <= cfg.tol
+            iters.append(sum(st["outer_iters"]))
+            used += st["warm_used"]
+            g0.append(st["res_guess"][0])
+            r0.append(st["res0"][0])
+        res[mode] = (np.array(iters), used, np.array(g0), np.array(r0), sim.phi_numpy().copy())
+        log(f"  {mode}: iterations {iters} guesses used {used} "
+            f"median res0 {np.median(r0):.2e} -> guess {np.median(g0):.2e}")
+        sim.close()
+    assert res["nan"][1] == 0
+    assert np.array_equal(res["nan"][0], res["prev"][0])
+    # every accepted guess lowered the residual; the converged fields agree
+    iters_l, used_l, g_l, r_l, phi_l = res["learned"]
+    assert np.all(g_l <= r_l)
+    assert rel_rms(phi_l, res["prev"][4]) < 1e-5

@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(P):
 
 def test_struct_sizes_match_header_layout(P):
     assert ctypes.sizeof(P.Config) == 136
-    assert ctypes.sizeof(P.StepStats) == 8 * 2 + 4 * 4 + 8 * 4 + 8 * 5 + 4 * 7 + 4 * 8 + 4
+    assert ctypes.sizeof(P.StepStats) == 8 * 2 + 4 * 4 + 8 * 4 + 8 * 5 + 4 * 7 + 4 * 8 + 4 + 16
 
 
 @pytest.mark.parametrize("a,da,cg", [(0.02, 0.0049, -1.0), (0.5, 0.01, 0.0), (0.9, 0.1, 3000.0),
