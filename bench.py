@@ -5,10 +5,17 @@ Lambda-CDM Zel'dovich initial conditions at z = 49 (seed 512), steps of the
 200-step schedule uniform in a to z = 0, shrinking domain with the paper's
 reduced gravity speed, multigrid to 1e-8 relative residual.  A step is one
 sdpm_step (all of Table 2, lightcone elimination included) on inputs resident
-in HBM.  Two solver modes are timed on the same inputs:
-  mixed: FP32 V(2,2) cycles (6 levels) inside FP64 defect correction, FP32
-         momenta (the headline value);
-  plain: FP64 V-cycles, FP64 momenta.
+in HBM.  Three solver modes are timed on the same inputs, each to the same
+1e-8 relative residual:
+  plain:   FP64 V-cycles warm-started from the previous potential, FP64 momenta;
+  mixed:   FP32 V(2,2) cycles (6 levels) inside FP64 defect correction, FP32
+           momenta, previous-potential warm start;
+  learned: mixed, with the conv-net warm start, gated: the library keeps the
+           net only while the outer iterations it saves outweigh its measured
+           cost (the headline value);
+  learned_always: mixed, with the conv-net guess tried before every solve.
+The net is trained once before the timed regions, on the GPU, on solves
+recorded from 128^3 runs of the same schedule with other seeds.
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -34,13 +41,89 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_mode(P, torch, ics, args, precision, profile):
+# HBM bytes per dispatch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE passes, each
+# scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
+# kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
+# Valid only for the kernel source it was measured on.
+MEASURED_TRAFFIC = {"smooth_color": 198.7e6}
+
+MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def kernel_roofline(name, d):
+    """Achieved rate of one kernel from the library's live HIP-event profile:
+    algorithmic bytes (or matrix-core flops) per launch / mean launch time."""
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    per_launch = d["bytes"] / max(d["launches"], 1)
+    if name in MFMA_KERNELS:
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": d["launches"]}
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_ms": avg_ms, "launches": d["launches"]}
+
+
+def roofline_of(prof):
+    """Roofline entry of the kernel with the largest total time, plus every
+    kernel's total time and rate."""
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    out = kernel_roofline(dom, prof[dom])
+    out["kernels"] = {
+        k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+            ("TFLOP/s" if k in MFMA_KERNELS else "GB/s"):
+                round(v["bytes"] / (v["ms"] * 1e-3) / (1e12 if k in MFMA_KERNELS else 1e9), 1)
+                if v["ms"] > 0 else None}
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"]}
+    return out
+
+
+def train_net(P, torch, args):
+    """Record solves from args.train_ng^3 runs (periodic phase) and train the
+    warm-start net on them; returns (weights, info)."""
+    from paper_1709_04703_amd.train import Trainer, init_params, record_pairs
+    from synth import zeldovich_ics
+
+    t0 = time.perf_counter()
+    a0 = 1.0 / (1.0 + args.z_init)
+    seeds = [int(s) for s in args.train_seeds.split(",")]
+    ics = [zeldovich_ics(args.train_ng, args.box, a0, s) for s in seeds]
+    per_run = max(1, args.train_pairs // (2 * len(seeds)))
+    buf, kap, rms_r, rms_phi = record_pairs(ics, args.train_ng, args.box, a0, args.schedule,
+                                            args.train_pairs, steps_per_run=per_run)
+    del ics
+    t1 = time.perf_counter()
+    tr = Trainer(args.train_ng, init_params(0), lr=args.train_lr)
+    hist = tr.train(buf, kap, rms_r, rms_phi, args.train_iters,
+                    log_every=max(1, args.train_iters // 5))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    err = tr.evaluate(buf, kap, rms_r, rms_phi, range(0, buf.shape[0], max(1, buf.shape[0] // 20)))
+    w = tr.weights()
+    del buf, tr
+    torch.cuda.empty_cache()
+    info = {"train_mesh": args.train_ng, "seeds": seeds, "pairs": int(len(kap)),
+            "iterations": args.train_iters, "record_s": round(t1 - t0, 2),
+            "train_s": round(t2 - t1, 2), "loss": [(i, round(v, 5)) for i, v in hist],
+            "rel_err_dphi": round(err, 4)}
+    log(f"net: {info}")
+    return w, info
+
+
+def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True):
     x, p, ids = ics
     ng, box = args.ng, args.box
     n = x.shape[0]
     cfg = P.config_default(ng, box, c_grav=-1.0, shrink=1, precision=precision, n_initial=n,
-                           sort_every=args.sort_every)
+                           sort_every=args.sort_every,
+                           warm_start=P.SDPM_WS_PREV if weights is None else
+                           P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
     sim = P.Simulation(cfg, n)
+    if weights is not None:
+        sim.set_warmstart_weights(weights)
     sim.bind(x, p, ids)
     a0 = 1.0 / (1.0 + args.z_init)
     edges = np.linspace(a0, 1.0, args.schedule + 1)
@@ -53,7 +136,7 @@ def run_mode(P, torch, ics, args, precision, profile):
         sim.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    updates, vcyc, solve_ms, iters, stats = 0, 0, 0.0, [], []
+    updates, vcyc, solve_ms, iters, stats, used = 0, 0, 0.0, [], [], 0
     for _ in range(args.steps):
         n_act = sim.n_active
         st = sim.step(edges[step], edges[step + 1] - edges[step])
@@ -61,6 +144,7 @@ def run_mode(P, torch, ics, args, precision, profile):
         vcyc += st["vcycles"]
         solve_ms += st["ms"][2] + st["ms"][4]
         iters.append(st["outer_iters"])
+        used += st["warm_used"]
         stats.append(st)
         step += 1
     torch.cuda.synchronize()
@@ -70,7 +154,25 @@ def run_mode(P, torch, ics, args, precision, profile):
     del sim
     torch.cuda.empty_cache()
     return dict(seconds=dt, updates=updates, vcycles=vcyc, solve_ms=solve_ms, iters=iters,
-                stats=stats, prof=prof, cfg=cfg)
+                stats=stats, prof=prof, cfg=cfg, warm_used=used)
+
+
+def copy_bandwidth(torch, mib=2048, reps=5):
+    """Achieved HBM rate of a plain device-to-device copy (read + write bytes
+    over time), a practical ceiling for the streaming kernels."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(ics, args):
@@ -114,7 +216,9 @@ def cpu_baseline(ics, args):
         "sample": (f"one {ng}^3 step of the same workload: both FP64 FFT solves and the force "
                    f"mesh timed at full size ({t_mesh:.1f} s), deposit + interpolation + "
                    f"leapfrog timed on the first {m} of {n} particles ({t_dep + t_int:.1f} s) "
-                   f"and scaled by n; estimated {t_step:.1f} s per step"),
+                   f"and scaled by n; estimated {t_step:.1f} s per step. The FFTs use every "
+                   f"core (scipy.fft workers=-1); the np.add.at deposit and the interpolation "
+                   f"run on one"),
     }
 
 
@@ -128,10 +232,18 @@ def main():
     ap.add_argument("--z-init", type=float, default=49.0)
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
-    ap.add_argument("--modes", default="mixed,plain")
+    ap.add_argument("--modes", default="plain,mixed,learned,learned_always")
+    ap.add_argument("--train-ng", type=int, default=128)
+    ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
+    ap.add_argument("--train-pairs", type=int, default=400)
+    ap.add_argument("--train-iters", type=int, default=2000)
+    ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this size (a "
+                         "known-size kernel that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -146,17 +258,32 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     t = time.perf_counter()
     ics = zeldovich_ics(args.ng, args.box, 1.0 / (1.0 + args.z_init), args.seed)
     log(f"ICs {args.ng}^3 in {time.perf_counter() - t:.1f} s")
     results = {}
+    net_info = None
     for mode in args.modes.split(","):
-        prec = P.SDPM_MIXED if mode == "mixed" else P.SDPM_PLAIN_FP64
-        r = run_mode(P, torch, ics, args, prec, profile=(mode == "mixed"))
+        prec = P.SDPM_PLAIN_FP64 if mode == "plain" else P.SDPM_MIXED
+        weights = None
+        if mode.startswith("learned"):
+            if net_info is None:
+                net_weights, net_info = train_net(P, torch, args)
+            weights = net_weights
+        r = run_mode(P, torch, ics, args, prec, profile=(mode != "plain"), weights=weights,
+                     gated=(mode != "learned_always"))
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
-    head = results.get("mixed") or next(iter(results.values()))
+    head_mode = next(m for m in ("learned", "mixed", "plain") if m in results)
+    head = results[head_mode]
     value = head["updates"] / head["seconds"]
     modes = {}
     for mode, r in results.items():
@@ -167,22 +294,25 @@ def main():
             "outer_iters_per_solve": float(np.mean([sum(i) / 2 for i in r["iters"]])),
             "final_residual_max": max(max(s["res"]) for s in r["stats"]),
             "kappa_h2": r["stats"][0]["kappa_h2"][0],
+            "warm_starts_used": r["warm_used"],
+            "net_calls": (r["prof"].get("conv3d_mfma", {}).get("launches", 0) // 5
+                          if r["prof"] else 0),
         }
-    roofline = None
-    if head["prof"]:
-        prof = head["prof"]
-        dom = max(prof, key=lambda k: prof[k]["ms"])
-        d = prof[dom]
-        avg_ms = d["ms"] / max(d["launches"], 1)
-        achieved = (d["bytes"] / max(d["launches"], 1)) / (avg_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "avg_launch_ms": avg_ms, "launches": d["launches"],
-                    "kernels": {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                                    "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
-                                    if v["ms"] > 0 else None}
-                                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])
-                                if v["launches"]}}
+    if "plain" in modes:
+        for m in modes.values():
+            m["speedup_vs_plain"] = m["particle_updates_per_s"] / modes["plain"]["particle_updates_per_s"]
+    roofline = roofline_of(head["prof"]) if head["prof"] else None
+    if roofline and args.ng == 512 and roofline["kernel"] in MEASURED_TRAFFIC:
+        roofline["traffic"] = MEASURED_TRAFFIC[roofline["kernel"]]
+        roofline["traffic_unit"] = "bytes per launch"
+    learned_roofline = None
+    lmode = next((m for m in ("learned_always", "learned") if m in results), None)
+    if lmode and results[lmode]["prof"]:
+        lp = results[lmode]["prof"]
+        if lp.get("conv3d_mfma", {}).get("launches"):
+            learned_roofline = kernel_roofline("conv3d_mfma", lp["conv3d_mfma"])
+            learned_roofline["mode"] = lmode
+    copy_gbs = copy_bandwidth(torch)
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -199,7 +329,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycles in f64 defect correction; f64 positions, f32 momenta",
+        "dtype": {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
+                  "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
@@ -209,9 +340,13 @@ def main():
             "global_batch": int(ics[0].shape[0]),
             "parallelism": "single GPU",
         },
-        "vcycles_per_s": modes[next(iter(modes))]["vcycles_per_s"],
+        "headline_mode": head_mode,
+        "vcycles_per_s": modes[head_mode]["vcycles_per_s"],
         "modes": modes,
         "roofline": roofline,
+        "hbm_copy_GBps": copy_gbs,
+        "roofline_learned": learned_roofline,
+        "net": net_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -52,7 +52,15 @@ enum {
 };
 
 enum { SDPM_MIXED = 0, SDPM_PLAIN_FP64 = 1 };      /* sdpm_config.precision  */
-enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1 };    /* sdpm_config.warm_start */
+/* sdpm_config.warm_start.  PREV: the previous potential.  LEARNED: the
+ * learned guess (below) before every solve.  LEARNED_GATED: the learned
+ * guess only while it pays: per sub-step kind (first / second field
+ * half-step) the context times the guess and one outer iteration with HIP
+ * events and estimates the outer iterations an accepted guess saved (its
+ * residual reduction in units of the solve's measured convergence factor);
+ * when the saving is below the cost, the next 8, 16, 32, ... 256 solves of
+ * that kind skip the net (the count doubles at each failed try).          */
+enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1, SDPM_WS_LEARNED_GATED = 2 };
 
 typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
 
@@ -78,7 +86,7 @@ typedef struct sdpm_config {
   int32_t precision;     /* SDPM_MIXED: FP32 V-cycles in FP64 defect
                             correction, FP32 momenta; SDPM_PLAIN_FP64: FP64
                             V-cycles and momenta                               */
-  int32_t warm_start;    /* SDPM_WS_PREV or SDPM_WS_LEARNED                    */
+  int32_t warm_start;    /* SDPM_WS_PREV, SDPM_WS_LEARNED(_GATED)              */
   int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
   int32_t sort_every;    /* Morton re-sort before every k-th step (0: never)   */
   int32_t sort_shift;    /* sort key: cells grouped in blocks of 2^shift       */
@@ -205,21 +213,23 @@ int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);
  * activations with FP32 accumulation on the matrix cores.  Input channels:
  * the residual of the previous potential r0 = rhs - A phi_old (the density
  * source minus the Laplacian of phi_old) scaled by 1/rms(r0), and phi_old
- * scaled by 1/rms(phi_old).  Output: the change of the potential in units of
+ * scaled by 1/rms(phi_old), and the constant kappa h^2 of the sub-step (the
+ * change solves (A) dphi = r0, whose kernel depends on kappa h^2 only).
+ * Output: the change of the potential in units of
  * 1/rms(r0).  The guess replaces phi_old only if its residual is smaller;
  * the solve always continues to tol, so plain multigrid decides the result and
  * the fallback.
  * Parameters: SDPM_NET_PARAMS FP32 values, per layer l = 0..4 the weights
  * W[t][ci][co] (27 x 16 x 16, tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) reading
  * the input at (i+dx, j+dy, k+dz)) then the bias b[co] (16); input channels
- * ci >= 2 of layer 0 and output channels co >= 1 of layer 4 are unused.
+ * ci >= 3 of layer 0 and output channels co >= 1 of layer 4 are unused.
  * Activations: ng^3 x 16 BF16 (uint16), channels fastest, voxel (i,j,k) at
  * (k ng + j) ng + i.  Device pointers; work is enqueued on `stream`.        */
 #define SDPM_NET_PARAMS (5 * (27 * 16 * 16 + 16))
 enum { SDPM_CONV_RELU = 1, SDPM_CONV_OUT_FP32_CH0 = 2, SDPM_CONV_BACKWARD_DATA = 4,
        SDPM_CONV_MASK = 8 };
 /* Loads FP32 parameters (host memory, n_params == SDPM_NET_PARAMS) into a
- * context created with warm_start = SDPM_WS_LEARNED.                       */
+ * context created with warm_start = SDPM_WS_LEARNED or _LEARNED_GATED.    */
 int sdpm_set_warmstart_weights(sdpm_ctx* ctx, const float* params_host, int64_t n_params);
 /* One convolution layer (flags: SDPM_CONV_*):
  *   out[v][co] = bias[co] + sum_t sum_ci in[v + off_t][ci] W[t][ci][co],
@@ -236,9 +246,10 @@ int sdpm_conv3d_wgrad(int32_t n, const void* in_bf16, const void* g_bf16, float*
                       void* scratch, int64_t scratch_bytes, void* stream);
 /* Device scratch needed by sdpm_conv3d_wgrad and sdpm_net_train_step.      */
 int sdpm_net_scratch_bytes(int32_t n, int64_t* bytes);
-/* act0[v] = (r[v] s_r, phi[v] s_phi, 0, ..., 0) in BF16; r, phi FP32 ng^3. */
-int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi, void* act0,
-                  void* stream);
+/* act0[v] = (r[v] s_r, phi[v] s_phi, kappa_h2, 0, ..., 0) in BF16; r, phi
+ * FP32 ng^3.                                                               */
+int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi,
+                  float kappa_h2, void* act0, void* stream);
 /* Net forward: out (FP32 ng^3) = channel 0 of layer 5; act_a / act_b: two
  * BF16 ng^3 x 16 buffers for the hidden layers.                            */
 int sdpm_net_forward(int32_t n, const float* params, const void* act0, void* act_a, void* act_b,

@@ -22,6 +22,7 @@ import numpy as np
 TAPS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 C = 16
 N_LAYERS = 5
+N_INPUTS = 3      # channels of the net input: residual, previous potential, kappa h^2
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
@@ -108,10 +109,10 @@ def init_params(seed: int, scale: float = 1.0):
     rng = np.random.Generator(np.random.PCG64(seed))
     params = []
     for l in range(N_LAYERS):
-        fan_in = 27 * (2 if l == 0 else C)
+        fan_in = 27 * (N_INPUTS if l == 0 else C)
         w = rng.normal(0.0, scale * np.sqrt(2.0 / fan_in), size=(27, C, C))
         if l == 0:
-            w[:, 2:, :] = 0.0
+            w[:, N_INPUTS:, :] = 0.0
         if l == N_LAYERS - 1:
             w[:, :, 1:] = 0.0
         b = np.zeros(C)

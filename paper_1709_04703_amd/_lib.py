@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsdpm.so")
 SDPM_OK, SDPM_EINVAL, SDPM_ENOMEM, SDPM_EHIP = 0, -1, -2, -3
 SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE = -4, -5, -6, -7
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
-SDPM_WS_PREV, SDPM_WS_LEARNED = 0, 1
+SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED = 0, 1, 2
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",
@@ -134,7 +134,7 @@ def library() -> ctypes.CDLL:
         "sdpm_conv3d": [i32, vp, vp, vp, i32, vp, vp, vp],
         "sdpm_conv3d_wgrad": [i32, vp, vp, vp, vp, vp, i64, vp],
         "sdpm_net_scratch_bytes": [i32, P(i64)],
-        "sdpm_net_prep": [i32, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp],
+        "sdpm_net_prep": [i32, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp],
         "sdpm_net_forward": [i32, vp, vp, vp, vp, vp, vp],
         "sdpm_net_train_step": [i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, ctypes.c_float, vp,
                                 i64, vp, vp],
@@ -232,8 +232,9 @@ def conv3d_wgrad(n, inp, g, dw, db, scratch):
                                       scratch.numel() * scratch.element_size(), _stream()))
 
 
-def net_prep(n, r, phi, s_r, s_phi, act0):
-    check(library().sdpm_net_prep(n, _ptr(r), _ptr(phi), s_r, s_phi, _ptr(act0), _stream()))
+def net_prep(n, r, phi, s_r, s_phi, kappa_h2, act0):
+    check(library().sdpm_net_prep(n, _ptr(r), _ptr(phi), s_r, s_phi, kappa_h2, _ptr(act0),
+                                  _stream()))
 
 
 def net_forward(n, params, act0, act_a, act_b, out):

@@ -37,13 +37,19 @@ struct sdpm_ctx {
   void* r_alt = nullptr;
   bool net_ready = false;
   int warm_used = 0;
+  // gate of the learned guess (SDPM_WS_LEARNED_GATED), per sub-step kind:
+  // moving averages of the guess time and of one outer iteration, and the
+  // number of solves to skip the net before the next try
+  double gate_net_ms = 0.0, gate_cycle_ms = 0.0;
+  int gate_skip[2] = {0, 0};
+  int gate_backoff[2] = {kGateProbe, kGateProbe};
   // solve recording
   float* rec_buf = nullptr;
   int64_t rec_max = 0, rec_count = 0;
   std::vector<double> rec_kappa, rec_rms_r, rec_rms_phi;
   int64_t steps_done = 0;
   double* hpin = nullptr;       // host copies of device scalars
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[12] = {};      // [0..6] step phases, [8..11] gate timing
   Profiler prof;
   bool bound = false;
   sdpm_particles parts{};
@@ -122,9 +128,10 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (!(c->tol > 0.0)) return snprintf(msg, len, "tol must be > 0"), SDPM_EINVAL;
   if (c->precision != SDPM_MIXED && c->precision != SDPM_PLAIN_FP64)
     return snprintf(msg, len, "unknown precision %d", c->precision), SDPM_EINVAL;
-  if (c->warm_start != SDPM_WS_PREV && c->warm_start != SDPM_WS_LEARNED)
+  if (c->warm_start != SDPM_WS_PREV && c->warm_start != SDPM_WS_LEARNED &&
+      c->warm_start != SDPM_WS_LEARNED_GATED)
     return snprintf(msg, len, "unknown warm_start %d", c->warm_start), SDPM_EINVAL;
-  if (c->warm_start == SDPM_WS_LEARNED && !net_size_ok(c->ng))
+  if (c->warm_start != SDPM_WS_PREV && !net_size_ok(c->ng))
     return snprintf(msg, len, "the learned warm start needs ng >= 16"), SDPM_EINVAL;
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
   if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
@@ -170,7 +177,7 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
   void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
   void* sscr = c.sort_every > 0 ? take(sort_scratch_bytes(capacity)) : nullptr;
-  if (c.warm_start == SDPM_WS_LEARNED) {
+  if (c.warm_start != SDPM_WS_PREV) {
     const size_t V = (size_t)c.ng * c.ng * c.ng;
     float* prm = (float*)take(kNetParams * sizeof(float));
     uint16_t* a0 = (uint16_t*)take(V * 16 * sizeof(uint16_t));
@@ -356,7 +363,7 @@ struct SolveOut {
 // FP64 defect correction around V-cycles in T; rhs and ||rhs||^2 (dscal[0])
 // must be in place.  phi is the initial guess and the result.
 template <typename T>
-int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
+int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   const sdpm_config& g = c->cfg;
   const Box& b = c->lv[0].box;
   int nb = 0;
@@ -375,7 +382,13 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
   const bool recording = c->rec_buf && c->rec_count < c->rec_max;
   float* rec = recording ? c->rec_buf + (size_t)c->rec_count * 3 * (size_t)g.ng * g.ng * g.ng : nullptr;
   double rms_phi = 0.0;
-  if ((c->net_ready && rn > thresh) || recording) {
+  const bool gated = g.warm_start == SDPM_WS_LEARNED_GATED;
+  bool try_net = c->net_ready && rn > thresh && rn > 0.0;
+  if (try_net && gated && c->gate_skip[slot] > 0) {
+    --c->gate_skip[slot];
+    try_net = false;
+  }
+  if (try_net || recording) {
     launch_sum_sq(c->fields.phi, g.ng, full_box(g.ng), c->partial, &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 3, c->st);
     rc = sync_scalars(c, 4);
@@ -389,19 +402,30 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
     c->rec_rms_phi.push_back(rms_phi);
     ++c->rec_count;
   }
-  if (c->net_ready && rn > thresh && rn > 0.0 && rms_phi > 0.0) {
+  const double rn_prev = rn;
+  bool net_ran = false;
+  if (try_net && rms_phi > 0.0) {
     // learned initial guess, kept only if it lowers the residual
+    net_ran = true;
+    if (gated) HIP_TRY(c, hipEventRecord(c->ev[8], c->st));
     const double rms_r = rn / std::sqrt(cells);
     const Box* pb = c->periodic ? nullptr : &b;
     launch_net_prep<T, double, true>(g.ng, (const T*)c->lv[0].r, c->fields.phi,
-                                     (float)(1.0 / rms_r), (float)(1.0 / rms_phi), pb, c->net_act0,
+                                     (float)(1.0 / rms_r), (float)(1.0 / rms_phi), (float)kappa, pb,
+                                     c->net_act0,
                                      c->st);
     net_forward(g.ng, c->net_params, c->net_act0, c->net_a, c->net_b, c->net_out, c->st);
     launch_residual_guess<T>(c->fields.phi, c->net_out, rms_r, c->fields.rhs, (T*)c->r_alt, g.ng, b,
                              kappa, c->partial, &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+    if (gated) HIP_TRY(c, hipEventRecord(c->ev[9], c->st));
     rc = sync_scalars(c, 2);
     if (rc) return rc;
+    if (gated) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[8], c->ev[9]) == hipSuccess)
+        c->gate_net_ms = c->gate_net_ms > 0.0 ? 0.5 * (c->gate_net_ms + ms) : ms;
+    }
     const double rg = std::sqrt(c->hpin[1]);
     if (std::isfinite(rg) && rg < rn) {
       launch_apply_guess(c->fields.phi, c->net_out, rms_r, g.ng, b, c->st);
@@ -412,7 +436,10 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
   }
   so->res_guess = rn / denom;
   int it = 0;
+  const double rn_start = rn;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
+    const bool time_it = gated && it == 0;
+    if (time_it) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
     const T* e0 =
         vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
     launch_correct<T>(c->fields.phi, e0, g.ng, b, c->st);
@@ -420,10 +447,39 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+    if (time_it) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
     rc = sync_scalars(c, 2);
     if (rc) return rc;
+    if (time_it) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess)
+        c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + ms) : ms;
+    }
     rn = std::sqrt(c->hpin[1]);
     ++it;
+  }
+  if (gated && net_ran) {
+    // outer iterations the guess saved: its residual reduction measured in
+    // this solve's own convergence factor per iteration; keep the net for
+    // this sub-step kind while that exceeds its cost in iterations, else skip
+    // it for a doubling number of solves
+    double saved = 0.0;
+    if (so->warm) {
+      if (it == 0) {
+        saved = 1e30;
+      } else if (rn > 0.0 && rn_start > 0.0) {
+        const double rho = std::pow(rn / rn_start, 1.0 / it);
+        if (rho > 0.0 && rho < 1.0) saved = std::log(rn_prev / rn_start) / std::log(1.0 / rho);
+      }
+    }
+    const double cost = c->gate_net_ms / std::max(c->gate_cycle_ms, 1e-6);
+    if (saved >= cost) {
+      c->gate_backoff[slot] = kGateProbe;
+      c->gate_skip[slot] = 0;
+    } else {
+      c->gate_skip[slot] = c->gate_backoff[slot];
+      c->gate_backoff[slot] = std::min(2 * c->gate_backoff[slot], kGateProbeMax);
+    }
   }
   so->iters = it;
   so->vcycles = it;
@@ -442,9 +498,9 @@ int solve_impl(sdpm_ctx* c, double kappa, SolveOut* so) {
   return SDPM_OK;
 }
 
-int solve(sdpm_ctx* c, double kappa, SolveOut* so) {
-  return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, so)
-                                        : solve_impl<double>(c, kappa, so);
+int solve(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
+  return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, slot, so)
+                                        : solve_impl<double>(c, kappa, slot, so);
 }
 
 int deposit(sdpm_ctx* c, double drift_coef, int drift) {
@@ -714,7 +770,7 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   deposit(c, 0.0, 0);
   assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0);
   SolveOut so;
-  const int src = solve(c, 0.0, &so);
+  const int src = solve(c, 0.0, 0, &so);
   rc = flags_error(c);
   st.n_removed = removed;
   st.outer_iters[0] = so.iters;
@@ -753,7 +809,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   assemble_rhs(c, sc.s_half, sc.kappa1_h2);
   HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
   SolveOut s1;
-  const int src1 = solve(c, sc.kappa1_h2, &s1);
+  const int src1 = solve(c, sc.kappa1_h2, 0, &s1);
   if (src1 && src1 != SDPM_ENOCONV) return src1;
   HIP_TRY(c, hipEventRecord(c->ev[3], c->st));
   // grad Phi, CIC interpolation, kick with a(t+dt/2), drift with a(t+dt)  (rows 4-6)
@@ -778,7 +834,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   int src2 = SDPM_OK;
   if (sc.kappa2_h2 > 0.0) {
     assemble_rhs(c, sc.s_half, sc.kappa2_h2);
-    src2 = solve(c, sc.kappa2_h2, &s2);
+    src2 = solve(c, sc.kappa2_h2, 1, &s2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], c->st));
@@ -867,7 +923,7 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
     return fail(c, SDPM_EINVAL, "kappa_h2 must be >= 0 and s finite");
   assemble_rhs(c, s_source, kappa_h2);
   SolveOut so;
-  rc = solve(c, kappa_h2, &so);
+  rc = solve(c, kappa_h2, 0, &so);
   if (out) {
     std::memset(out, 0, sizeof(*out));
     out->outer_iters[0] = so.iters;
@@ -913,7 +969,7 @@ int sdpm_interp_force(sdpm_ctx* c, double* g_dev[3]) {
 int sdpm_set_warmstart_weights(sdpm_ctx* c, const float* params_host, int64_t n_params) {
   if (!c) return SDPM_EINVAL;
   if (!c->net_params)
-    return fail(c, SDPM_ESTATE, "the context was created without warm_start = SDPM_WS_LEARNED");
+    return fail(c, SDPM_ESTATE, "the context was created with warm_start = SDPM_WS_PREV");
   if (!params_host || n_params != kNetParams)
     return fail(c, SDPM_EINVAL, "expected %d parameters", kNetParams);
   HIP_TRY(c, hipMemcpyAsync(c->net_params, params_host, kNetParams * sizeof(float),
@@ -979,10 +1035,10 @@ int sdpm_conv3d_wgrad(int32_t n, const void* in_bf16, const void* g_bf16, float*
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "wgrad launch failed");
 }
 
-int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi, void* act0,
-                  void* stream) {
+int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float s_phi,
+                  float kappa_h2, void* act0, void* stream) {
   if (!net_size_ok(n) || !r || !phi || !act0) return fail(nullptr, SDPM_EINVAL, "net_prep: bad arguments");
-  launch_net_prep<float, float, false>(n, r, phi, s_r, s_phi, nullptr, (uint16_t*)act0,
+  launch_net_prep<float, float, false>(n, r, phi, s_r, s_phi, kappa_h2, nullptr, (uint16_t*)act0,
                                        (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "net_prep launch failed");
 }

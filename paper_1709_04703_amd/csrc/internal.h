@@ -13,6 +13,7 @@
 namespace sdpm {
 
 constexpr int kMaxLevels = 12;
+constexpr int kGateProbe = 8, kGateProbeMax = 256;   // solves skipped by the net gate
 constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
 constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
 constexpr int kBoxTy = 4;
@@ -139,6 +140,7 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
 
 // Learned warm start (net.hip).
 constexpr int kNetParams = 5 * (27 * 16 * 16 + 16);
+constexpr int kNetInputs = 3;   // r0, phi_old, kappa h^2
 bool net_size_ok(int n);
 void launch_conv(int n, const uint16_t* in, const float* w, const float* bias, int flags,
                  const uint16_t* mask, void* out, hipStream_t st);
@@ -146,7 +148,7 @@ size_t wgrad_scratch_bytes(int n);
 void launch_conv_wgrad(int n, const uint16_t* in, const uint16_t* g, float* dw, float* db,
                        float* scratch, hipStream_t st);
 template <typename RT, typename PT, bool SPLIT>
-void launch_net_prep(int n, const RT* r, const PT* phi, float s_r, float s_phi, const Box* box,
+void launch_net_prep(int n, const RT* r, const PT* phi, float s_r, float s_phi, float kap, const Box* box,
                      uint16_t* act0, hipStream_t st);
 void net_forward(int n, const float* params, const uint16_t* act0, uint16_t* a, uint16_t* b,
                  float* out, hipStream_t st);

@@ -211,12 +211,12 @@ k_wgrad_reduce(const float* __restrict__ partial, int nblocks, float* __restrict
 }
 
 // ------------------------------------------------------------- inputs, loss
-// act0[v] = (r[v] s_r, phi[v] s_phi, 0, ...) in BF16.  RT / PT: input types;
+// act0[v] = (r[v] s_r, phi[v] s_phi, kap, 0, ...) in BF16.  RT / PT: input types;
 // SPLIT: r stored colour-split; with a box, r outside it counts as zero.
 template <typename RT, typename PT, bool SPLIT>
 __global__ void __launch_bounds__(256)
 k_net_prep(int n, const RT* __restrict__ r, const PT* __restrict__ phi, float s_r, float s_phi,
-           Box b, int use_box, uint16_t* __restrict__ act0) {
+           float kap, Box b, int use_box, uint16_t* __restrict__ act0) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t V = (int64_t)n * n * n;
   if (v >= V) return;
@@ -232,7 +232,8 @@ k_net_prep(int n, const RT* __restrict__ r, const PT* __restrict__ phi, float s_
   const float pv = (float)phi[v] * s_phi;
   uint4 o0, o1;
   o0.x = (uint32_t)f2bf(rv) | ((uint32_t)f2bf(pv) << 16);
-  o0.y = o0.z = o0.w = 0u;
+  o0.y = (uint32_t)f2bf(kap);
+  o0.z = o0.w = 0u;
   o1.x = o1.y = o1.z = o1.w = 0u;
   ((uint4*)(act0 + v * kNC))[0] = o0;
   ((uint4*)(act0 + v * kNC))[1] = o1;
@@ -288,7 +289,7 @@ k_adam(int np, float* __restrict__ p, const float* __restrict__ grad, float* __r
   bool frozen = false;
   if (o < 27 * kNC * kNC) {
     const int ci = (o / kNC) % kNC, co = o % kNC;
-    frozen = (l == 0 && ci >= 2) || (l == 4 && co >= 1);
+    frozen = (l == 0 && ci >= kNetInputs) || (l == 4 && co >= 1);
   } else {
     frozen = (l == 4 && o - 27 * kNC * kNC >= 1);
   }
@@ -342,20 +343,20 @@ void launch_conv_wgrad(int n, const uint16_t* in, const uint16_t* g, float* dw, 
 }
 
 template <typename RT, typename PT, bool SPLIT>
-void launch_net_prep(int n, const RT* r, const PT* phi, float s_r, float s_phi, const Box* box,
-                     uint16_t* act0, hipStream_t st) {
+void launch_net_prep(int n, const RT* r, const PT* phi, float s_r, float s_phi, float kap,
+                     const Box* box, uint16_t* act0, hipStream_t st) {
   const int64_t V = (int64_t)n * n * n;
   Box b{};
   if (box) b = *box;
   hipLaunchKernelGGL((k_net_prep<RT, PT, SPLIT>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0,
-                     st, n, r, phi, s_r, s_phi, b, box ? 1 : 0, act0);
+                     st, n, r, phi, s_r, s_phi, kap, b, box ? 1 : 0, act0);
 }
 template void launch_net_prep<float, float, false>(int, const float*, const float*, float, float,
-                                                   const Box*, uint16_t*, hipStream_t);
+                                                   float, const Box*, uint16_t*, hipStream_t);
 template void launch_net_prep<float, double, true>(int, const float*, const double*, float, float,
-                                                   const Box*, uint16_t*, hipStream_t);
+                                                   float, const Box*, uint16_t*, hipStream_t);
 template void launch_net_prep<double, double, true>(int, const double*, const double*, float, float,
-                                                    const Box*, uint16_t*, hipStream_t);
+                                                    float, const Box*, uint16_t*, hipStream_t);
 
 // Net forward: act0 -> 4 hidden layers (ReLU, BF16) -> FP32 channel 0 in out.
 void net_forward(int n, const float* params, const uint16_t* act0, uint16_t* a, uint16_t* b,

@@ -4,7 +4,7 @@ Training pairs come from the method itself: a shrinking-domain run records,
 for every implicit gravity sub-step it solves, the residual of the previous
 potential r0, the previous potential phi_old and the converged change
 dphi = phi - phi_old (sdpm_record).  The net maps (r0 / rms r0, phi_old /
-rms phi_old) to dphi / rms r0.  Training runs on the GPU with the library's
+rms phi_old, kappa h^2) to dphi / rms r0.  Training runs on the GPU with the library's
 own forward / backward kernels and Adam (sdpm_net_train_step); this module
 only selects samples and moves buffers.  Pairs come from the periodic phase
 of the runs (the net pads periodically).
@@ -17,10 +17,12 @@ from . import _lib as L
 
 
 def record_pairs(ics_list, ng: int, box: float, a0: float, nsteps: int, max_pairs: int,
-                 precision: int = L.SDPM_MIXED, c_grav: float = -1.0, device: str = "cuda:0"):
-    """Run the given initial conditions (list of (x, p, ids)) and record up to
-    max_pairs solves.  Returns (buf [P, 3, ng^3] float32 device tensor,
-    kappa, rms_r, rms_phi arrays)."""
+                 precision: int = L.SDPM_MIXED, c_grav: float = -1.0, device: str = "cuda:0",
+                 steps_per_run: int | None = None):
+    """Run the given initial conditions (list of (x, p, ids)) on the schedule
+    of nsteps steps uniform in a from a0 to 1, each for at most steps_per_run
+    steps of its periodic phase, and record up to max_pairs solves.  Returns
+    (buf [P, 3, ng^3] float32 device tensor, kappa h^2, rms_r, rms_phi arrays)."""
     import torch
 
     V = ng ** 3
@@ -37,7 +39,7 @@ def record_pairs(ics_list, ng: int, box: float, a0: float, nsteps: int, max_pair
         sim.init_potential(a0)
         sim.record(buf[got:], max_pairs - got)
         edges = np.linspace(a0, 1.0, nsteps + 1)
-        for s in range(nsteps):
+        for s in range(min(nsteps, steps_per_run or nsteps)):
             st = sim.step(edges[s], edges[s + 1] - edges[s])
             if not st["periodic"]:
                 break
@@ -72,15 +74,17 @@ class Trainer:
         self.lr = lr
         self.step_count = 0
 
-    def _prep(self, pair, rms_r, rms_phi):
-        L.net_prep(self.ng, pair[0], pair[1], 1.0 / rms_r, 1.0 / rms_phi, self.act0)
+    def _prep(self, pair, kap, rms_r, rms_phi):
+        L.net_prep(self.ng, pair[0], pair[1], 1.0 / rms_r, 1.0 / rms_phi, kap, self.act0)
 
-    def train(self, buf, rms_r, rms_phi, iters: int, seed: int = 0, log_every: int = 0):
+    def train(self, buf, kap, rms_r, rms_phi, iters: int, seed: int = 0, log_every: int = 0):
+        """Adam steps, one recorded pair each, drawn uniformly at random;
+        returns [(iteration, loss)] every log_every iterations."""
         rng = np.random.Generator(np.random.PCG64(seed))
         losses = []
         for it in range(iters):
             q = int(rng.integers(0, buf.shape[0]))
-            self._prep(buf[q], rms_r[q], rms_phi[q])
+            self._prep(buf[q], kap[q], rms_r[q], rms_phi[q])
             self.step_count += 1
             L.net_train_step(self.ng, self.params, self.m1, self.m2, self.step_count, self.lr,
                              self.act0, buf[q, 2], float(1.0 / rms_r[q]), self.scratch, self.loss)
@@ -88,18 +92,18 @@ class Trainer:
                 losses.append((it, float(self.loss.item())))
         return losses
 
-    def predict(self, pair, rms_r, rms_phi):
+    def predict(self, pair, kap, rms_r, rms_phi):
         """Net output (normalised dphi) for one recorded pair, device tensor."""
-        self._prep(pair, rms_r, rms_phi)
+        self._prep(pair, kap, rms_r, rms_phi)
         L.net_forward(self.ng, self.params, self.act0, self.act_a, self.act_b, self.out)
         return self.out
 
-    def evaluate(self, buf, rms_r, rms_phi, idx):
+    def evaluate(self, buf, kap, rms_r, rms_phi, idx):
         """Mean relative error of the predicted change, ||pred - dphi|| / ||dphi||,
         over the pairs idx (also for the trivial guess dphi = 0, which is 1)."""
         errs = []
         for q in idx:
-            pred = self.predict(buf[q], rms_r[q], rms_phi[q]) * float(rms_r[q])
+            pred = self.predict(buf[q], kap[q], rms_r[q], rms_phi[q]) * float(rms_r[q])
             tgt = buf[q, 2]
             errs.append(float((pred - tgt).norm() / tgt.norm().clamp_min(1e-30)))
         return float(np.mean(errs))
@@ -114,10 +118,10 @@ def init_params(seed: int = 0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for l in range(5):
-        fan_in = 27 * (2 if l == 0 else 16)
+        fan_in = 27 * (3 if l == 0 else 16)
         w = rng.normal(0.0, np.sqrt(2.0 / fan_in), size=(27, 16, 16))
         if l == 0:
-            w[:, 2:, :] = 0.0
+            w[:, 3:, :] = 0.0
         if l == 4:
             w[:, :, 1:] = 0.0
             w *= 0.1

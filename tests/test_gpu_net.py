@@ -118,10 +118,11 @@ def test_net_forward_matches_oracle():
     x0 = np.zeros((n, n, n, 16))
     x0[..., 0] = r * 0.5
     x0[..., 1] = phi * 2.0
+    x0[..., 2] = 0.3
     _, ref = oc.forward(x0, params, round_bf16=True)
     act0 = torch.zeros((n**3, 16), dtype=torch.int16, device="cuda")
     P.net_prep(n, torch.as_tensor(r.astype(np.float32)).cuda().reshape(-1),
-               torch.as_tensor(phi.astype(np.float32)).cuda().reshape(-1), 0.5, 2.0, act0)
+               torch.as_tensor(phi.astype(np.float32)).cuda().reshape(-1), 0.5, 2.0, 0.3, act0)
     assert np.array_equal(_from_bf16(act0).reshape(n, n, n, 16), oc.bf16_round(x0))
     a = torch.zeros_like(act0)
     b = torch.zeros_like(act0)
@@ -144,7 +145,7 @@ def test_training_reduces_loss_on_one_sample():
     tgt = sum(np.roll(rr, s, axis=a) for a in range(3) for s in (-1, 1)) / 6.0
     buf = torch.stack([r, phi, torch.as_tensor(tgt.astype(np.float32).ravel()).cuda()])[None]
     tr = Trainer(n, init_params(1), lr=3e-3)
-    hist = tr.train(buf, np.array([1.0]), np.array([1.0]), 300, log_every=50)
+    hist = tr.train(buf, np.array([0.2]), np.array([1.0]), np.array([1.0]), 300, log_every=50)
     log(f"  loss history {hist}")
     assert hist[-1][1] < 0.2 * hist[0][1]
 
@@ -153,7 +154,8 @@ def test_learned_warm_start_trains_and_falls_back():
     """Train on the method's own solves (64^3, periodic phase) and use the
     net as the initial guess of the same configuration with another seed:
     the solve still reaches tol, the accepted guesses lower the starting
-    residual, and non-finite weights fall back to plain multigrid."""
+    residual, non-finite weights fall back to plain multigrid, and the gated
+    mode runs the net at most as often as the ungated one."""
     import paper_1709_04703_amd as P
     from paper_1709_04703_amd.train import Trainer, init_params, record_pairs
     ng, box, a0, nsteps = 64, 2000.0, 1.0 / 50.0, 40
@@ -161,19 +163,22 @@ def test_learned_warm_start_trains_and_falls_back():
     buf, kap, rms_r, rms_phi = record_pairs(ics, ng, box, a0, nsteps, 60)
     log(f"  recorded {buf.shape[0]} solves")
     assert buf.shape[0] >= 40
-    tr = Trainer(ng, init_params(0), lr=1e-3)
-    hist = tr.train(buf, rms_r, rms_phi, 400, log_every=100)
+    tr = Trainer(ng, init_params(0), lr=4e-4)
+    hist = tr.train(buf, kap, rms_r, rms_phi, 1500, log_every=250)
     log(f"  loss history {hist}")
-    err = tr.evaluate(buf, rms_r, rms_phi, range(0, buf.shape[0], 7))
+    err = tr.evaluate(buf, kap, rms_r, rms_phi, range(0, buf.shape[0], 7))
     log(f"  relative error of the predicted change on training pairs: {err:.3f}")
     weights = tr.weights()
     x, p, ids = zeldovich_ics(ng, box, a0, 13)
     res = {}
-    for mode in ("prev", "learned", "nan"):
-        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3,
-                         warm_start=P.SDPM_WS_PREV if mode == "prev" else P.SDPM_WS_LEARNED)
+    ws = {"prev": P.SDPM_WS_PREV, "learned": P.SDPM_WS_LEARNED, "nan": P.SDPM_WS_LEARNED,
+          "gated": P.SDPM_WS_LEARNED_GATED}
+    net_calls = {}
+    for mode in ("prev", "learned", "gated", "nan"):
+        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3, warm_start=ws[mode])
         sim = make_sim(cfg, ng**3)
-        if mode == "learned":
+        sim.profile(True)
+        if mode in ("learned", "gated"):
             sim.set_warmstart_weights(weights)
         elif mode == "nan":
             bad = weights.copy()
@@ -191,8 +196,10 @@ def test_learned_warm_start_trains_and_falls_back():
             g0.append(st["res_guess"][0])
             r0.append(st["res0"][0])
         res[mode] = (np.array(iters), used, np.array(g0), np.array(r0), sim.phi_numpy().copy())
+        net_calls[mode] = sim.profile_read().get("conv3d_mfma", {}).get("launches", 0) // 5
         log(f"  {mode}: iterations {iters} guesses used {used} "
-            f"median res0 {np.median(r0):.2e} -> guess {np.median(g0):.2e}")
+            f"median res0 {np.median(r0):.2e} -> guess {np.median(g0):.2e} "
+            f"net calls {net_calls[mode]}")
         sim.close()
     assert res["nan"][1] == 0
     assert np.array_equal(res["nan"][0], res["prev"][0])
@@ -200,3 +207,7 @@ def test_learned_warm_start_trains_and_falls_back():
     iters_l, used_l, g_l, r_l, phi_l = res["learned"]
     assert np.all(g_l <= r_l)
     assert rel_rms(phi_l, res["prev"][4]) < 1e-5
+    assert net_calls["prev"] == 0 and net_calls["learned"] >= 12
+    assert 1 <= net_calls["gated"] <= net_calls["learned"]
+    assert np.all(res["gated"][2] <= res["gated"][3])
+    assert rel_rms(res["gated"][4], res["prev"][4]) < 1e-5
