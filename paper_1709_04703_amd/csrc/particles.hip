@@ -52,6 +52,16 @@ __device__ inline uint32_t cic_setup(const double x[3], const MeshMap& mm, Cic& 
   return bad;
 }
 
+// Position update x + p c as two roundings (no fused multiply-add), the
+// leapfrog drift of Eqs. 7 and 9 as written, so that drifted positions (and
+// the fixed-point cells derived from them) are the same FP64 values as those
+// of a plain evaluation of the formula.
+__device__ inline double drift_nofma(double x, double p, double c) {
+#pragma clang fp contract(off)
+  const double dp = p * c;
+  return x + dp;
+}
+
 // Squared distance ((dx^2 + dy^2) + dz^2) without fused multiply-adds, so
 // that the lightcone test is the same FP64 expression everywhere.
 __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0, double o1,
@@ -107,7 +117,7 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     for (int d = 0; d < 3; ++d) {
       double v = pa.x[d][i];
       if (DRIFT) {
-        v = v + (double)((const PT*)pa.p[d])[i] * coef;
+        v = drift_nofma(v, (double)((const PT*)pa.p[d])[i], coef);
         if (mm.periodic) {
           if (v < 0.0) v += mm.box;
           if (v >= mm.box) v -= mm.box;
@@ -244,7 +254,7 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm,
         PT* p = (PT*)pa.p[d];
         const PT pn = (PT)((double)p[i] + g[d] * kick_coef);
         p[i] = pn;
-        double v = x[d] + (double)pn * drift_coef;
+        double v = drift_nofma(x[d], (double)pn, drift_coef);
         if (mm.periodic) {
           if (v < 0.0) v += mm.box;
           if (v >= mm.box) v -= mm.box;

@@ -1,0 +1,173 @@
+"""Parity at the benchmark's full size and launch configuration: 512^3
+particles on a 512^3 mesh, 2000 Mpc/h, synthetic LCDM Zel'dovich ICs at z = 49
+(seed 512), the paper's reduced gravity speed, FP32 V-cycles in FP64 defect
+correction to 1e-8, Morton re-sort every 10 steps.  The oracle cannot redo a
+whole step at this size in seconds, so it checks what it can compute one by
+one and properties that hold at any size, on one full sdpm_step (the first of
+the run, which also sorts):
+
+ * sort: the particle order is exactly the stable sort by the Morton key of
+   the cell (a stable sort has one result);
+ * drift + deposit: positions after the first drift equal x + p c evaluated
+   in FP64 (no fused multiply-add), so the total mass (sum of counts =
+   n 2^(3B)) and the counts of whole z-planes (both periodic edges and the
+   middle) are bit-exact against the oracle's deposit of the particles that
+   reach those planes;
+ * both solves: the potentials against the oracle's exact FFT solves of the
+   oracle's own source of those counts, within cond(A) * tol;
+ * kick + second drift: sampled momenta within FP32 rounding plus a 1e-5
+   relative force error, and positions bit-exact given the GPU's momenta;
+ * force: sampled interpolated forces at the end of the step, 1e-5 relative
+   RMS against central differences of the exact potential;
+ * removal: the removed set and the stable order of the survivors, exact, for
+   a sphere that cuts the box, and the Dirichlet index box it implies."""
+import numpy as np
+import pytest
+
+from oracle import cosmology as ocosmo
+from oracle import pm
+from synth import zeldovich_ics
+
+from helpers import cond_periodic, lib_config, log, make_sim, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+NG, BOX, Z_INIT, SEED, SCHEDULE, B = 512, 2000.0, 49.0, 512, 200, 14
+
+
+def morton_key(x, ng, box, shift):
+    """Cell Morton key: bit b of the cell's x, y, z index goes to bit 3b,
+    3b+1, 3b+2 of the key (a table of the bit spreading of 0..1023)."""
+    table = np.array([sum(((v >> b) & 1) << (3 * b) for b in range(10)) for v in range(1024)],
+                     dtype=np.int64)
+    key = np.zeros(x.shape[0], dtype=np.int64)
+    for d in range(3):
+        c = np.clip(np.floor(x[:, d] * (ng / box)), 0, ng - 1).astype(np.int64) >> shift
+        key |= table[c] << d
+    return key
+
+
+def wrap(x, box):
+    x = np.where(x < 0.0, x + box, x)
+    return np.where(x >= box, x - box, x)
+
+
+@pytest.fixture(scope="module")
+def big():
+    import paper_1709_04703_amd as P
+    a0 = 1.0 / (1.0 + Z_INIT)
+    log(f"full size: ICs {NG}^3, seed {SEED}")
+    x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
+    n = x.shape[0]
+    cfg = lib_config(NG, BOX, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED, n_initial=n,
+                     sort_every=10)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    del x, p, ids
+    sim.init_potential(a0)
+    yield dict(sim=sim, cfg=cfg, n=n, a0=a0, edges=np.linspace(a0, 1.0, SCHEDULE + 1))
+    sim.close()
+
+
+def test_fullsize_step(big):
+    sim, cfg, n = big["sim"], big["cfg"], big["n"]
+    a, da = big["edges"][0], big["edges"][1] - big["edges"][0]
+    h = BOX / NG
+    x0, p0, ids0 = sim.particles()
+    phi0 = sim.phi_numpy().copy()
+    log("full size: one step (sorts first)")
+    st = sim.step(a, da)
+    assert st["n_active"] == n and st["periodic"] == 1
+    assert max(st["res"]) <= cfg.tol
+    x1, p1, ids1 = sim.particles()
+
+    # sort: exactly the stable sort by cell Morton key (ids are the initial
+    # indices): a permutation with non-decreasing keys, ties in index order
+    assert np.array_equal(ids0, np.arange(n, dtype=np.uint32))
+    order = ids1.astype(np.int64)
+    seen = np.zeros(n, dtype=bool)
+    seen[order] = True
+    assert seen.all()
+    key = morton_key(x0, NG, BOX, cfg.sort_shift)[order]
+    dk = np.diff(key)
+    assert np.all(dk >= 0)
+    assert np.all(np.diff(order)[dk == 0] > 0)
+    del seen, key, dk
+    x0, p0 = x0[order], p0[order]
+    del order
+
+    # first drift and the deposit: exact
+    c1 = 0.5 * st["dtau"] / a
+    xh = wrap(x0 + p0 * c1, BOX)
+    counts = sim.counts_numpy().reshape(NG, NG, NG)
+    lo = int((counts & np.uint64(0xFFFFFFFF)).sum(dtype=np.uint64))
+    hi = int((counts >> np.uint64(32)).sum(dtype=np.uint64))
+    assert (hi << 32) + lo == n << (3 * B)
+    kz = pm.fixed_point_coords(xh[:, 2:3], NG, BOX, B, True)[:, 0] >> B
+    for k in (0, 1, 255, 256, NG - 1):
+        sel = (kz == k) | (kz == (k - 1) % NG)
+        ref = pm.deposit(xh[sel], NG, BOX, B, True)[k]
+        assert np.array_equal(counts[k], ref), f"plane {k}"
+    del kz
+    log("  sort, drift and deposit planes exact")
+
+    # both solves against the oracle's exact solves of its own source
+    sc = ocosmo.step_scalars(a, da, cfg.omega_m, cfg.omega_l, BOX, NG, cfg.c_grav, cfg.c_light)
+    k1, k2 = st["kappa_h2"]
+    assert k1 == pytest.approx(sc["kappa1_h2"], rel=1e-12)
+    assert k2 == pytest.approx(sc["kappa2_h2"], rel=1e-12)
+    f = pm.source(counts, n, B, sc["s_half"], h, True)
+    del counts
+    phi_half = pm.solve_periodic(f - k1 * phi0, k1)
+    del phi0
+    rhs2 = sim.rhs.cpu().numpy()
+    phi_half_gpu = (f - rhs2) / k2
+    err1 = rel_rms(phi_half_gpu, phi_half)
+    phi1 = pm.solve_periodic(f - k2 * phi_half, k2)
+    err2 = rel_rms(sim.phi_numpy(), phi1)
+    log(f"  potential errors: half step {err1:.2e}, full step {err2:.2e}")
+    assert err1 <= cond_periodic(NG, k1) * cfg.tol
+    assert err2 <= 2.0 * cond_periodic(NG, k2) * cfg.tol
+    del f, rhs2, phi_half_gpu
+
+    # kick with the exact force at the drifted positions, second drift exact
+    rng = np.random.Generator(np.random.PCG64(5))
+    idx = np.sort(rng.choice(n, size=1 << 17, replace=False))
+    g = pm.interpolate(xh[idx], pm.force_mesh(phi_half, h), NG, BOX, B, True)
+    kick = st["a_half"] * st["dtau"]
+    p_ref = p0[idx] + g * kick
+    dp = np.sqrt(np.mean((p1[idx] - p_ref) ** 2))
+    bound = 2.0**-24 * np.sqrt(np.mean(p_ref**2)) + 1e-5 * kick * np.sqrt(np.mean(g**2))
+    log(f"  momentum rms error {dp:.3e} (bound {bound:.3e})")
+    assert dp <= bound
+    c2 = 0.5 * st["dtau"] / (a + da)
+    assert np.array_equal(x1[idx], wrap(xh[idx] + p1[idx] * c2, BOX))
+    del phi_half, xh
+
+    # force at the end of the step
+    g_gpu = sim.interp_force()[:, idx].cpu().numpy().T
+    g_ref = pm.interpolate(x1[idx], pm.force_mesh(phi1, h), NG, BOX, B, True)
+    ferr = rel_rms(g_gpu, g_ref)
+    log(f"  force rel rms {ferr:.2e}")
+    assert ferr <= 1e-5
+
+
+def test_fullsize_removal(big):
+    sim, cfg = big["sim"], big["cfg"]
+    x, _, ids = sim.particles()
+    n = x.shape[0]
+    r = 600.0
+    out = pm.outside_lightcone(x, np.asarray(cfg.x_obs), r)
+    log(f"full size: removal at r = {r}, {int(out.sum())} of {n} outside")
+    nr = sim.shrink_radius(r)
+    assert nr == int(out.sum())
+    xa, _, ida = sim.particles(all_particles=True)
+    keep = ~out
+    assert np.array_equal(ida[: n - nr], ids[keep])
+    assert np.array_equal(ida[n - nr: n], ids[out])
+    assert np.array_equal(xa[: n - nr], x[keep])
+    st = sim.state()
+    dirichlet, lo, hi = pm.box_for_radius(r, np.asarray(cfg.x_obs), BOX / NG, NG, cfg.margin,
+                                          cfg.box_align)
+    assert dirichlet and st["periodic"] == 0
+    assert list(st["lo"]) == list(lo) and list(st["hi"]) == list(hi)
