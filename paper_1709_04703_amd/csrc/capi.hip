@@ -28,6 +28,7 @@ struct sdpm_ctx {
   uint32_t* boffsets = nullptr;
   void* scratch = nullptr;
   void* sort_scratch = nullptr;
+  float* gmesh = nullptr;       // FP32 force mesh (mixed precision)
   // learned warm start
   float* net_params = nullptr;
   uint16_t* net_act0 = nullptr;
@@ -43,6 +44,9 @@ struct sdpm_ctx {
   double gate_net_ms = 0.0, gate_cycle_ms = 0.0;
   int gate_skip[2] = {0, 0};
   int gate_backoff[2] = {kGateProbe, kGateProbe};
+  // residual reduction per outer iteration of the last solve (geometric
+  // mean), used to run ahead of the host without a sync per iteration
+  double rho_est = 0.1;
   // solve recording
   float* rec_buf = nullptr;
   int64_t rec_max = 0, rec_count = 0;
@@ -169,7 +173,7 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   const dim3 g = box_grid(fb);
   const size_t maxblocks = (size_t)g.x * g.y * g.z;
   double* partial = (double*)take(maxblocks * kReduceSlots * sizeof(double));
-  double* dscal = (double*)take(16 * sizeof(double));
+  double* dscal = (double*)take(64 * sizeof(double));
   uint32_t* dflags = (uint32_t*)take(16 * sizeof(uint32_t));
   uint64_t* dkept = (uint64_t*)take(2 * sizeof(uint64_t));
   const size_t nb = (size_t)((capacity + kChunk - 1) / kChunk) + 1;
@@ -177,6 +181,9 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
   void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
   void* sscr = c.sort_every > 0 ? take(sort_scratch_bytes(capacity)) : nullptr;
+  // FP32 force mesh of the mixed-precision step (3 values per cell)
+  float* g3 = c.precision == SDPM_MIXED ? (float*)take((size_t)c.ng * c.ng * c.ng * 3 * sizeof(float))
+                                        : nullptr;
   if (c.warm_start != SDPM_WS_PREV) {
     const size_t V = (size_t)c.ng * c.ng * c.ng;
     float* prm = (float*)take(kNetParams * sizeof(float));
@@ -196,6 +203,7 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   }
   if (ctx) {
     ctx->sort_scratch = sscr;
+    ctx->gmesh = g3;
     ctx->partial = partial;
     ctx->dscal = dscal;
     ctx->dflags = dflags;
@@ -327,6 +335,14 @@ struct ProfScope {
   ~ProfScope() { g_prof = nullptr; }
 };
 
+// Copies the residual norms of every outer iteration (device slots
+// dscal[kNormSlot + it % kNormRing]) to hpin[kHostNorm + ...] and waits.
+int sync_norms(sdpm_ctx* c) {
+  HIP_TRY(c, hipMemcpyAsync(c->hpin + kHostNorm, c->dscal + kNormSlot, kNormRing * sizeof(double),
+                            hipMemcpyDeviceToHost, c->st));
+  return sync_scalars(c, 0);
+}
+
 uint32_t host_flags(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[0]; }
 uint32_t host_removed(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[1]; }
 
@@ -437,6 +453,13 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   so->res_guess = rn / denom;
   int it = 0;
   const double rn_start = rn;
+  // Outer iterations are enqueued without waiting for their residual norm
+  // while the norm predicted from the last known one and the convergence
+  // factor of the previous solve stays well above the threshold; then the
+  // host waits and reads the norms.  A wrong prediction can only add
+  // iterations (the residual keeps falling), never stop early.
+  double rn_known = rn;
+  int it_known = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
     const bool time_it = gated && it == 0;
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
@@ -446,17 +469,26 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
-    launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + kNormSlot + (it % kNormRing), c->st);
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
-    rc = sync_scalars(c, 2);
+    ++it;
+    const int ahead = it - it_known;
+    const double pred = rn_known * std::pow(c->rho_est, ahead);
+    if (!time_it && it < g.max_outer && ahead < kMaxAhead && pred > kAheadMargin * thresh) continue;
+    rc = sync_norms(c);
     if (rc) return rc;
     if (time_it) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess)
         c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + ms) : ms;
     }
-    rn = std::sqrt(c->hpin[1]);
-    ++it;
+    rn = std::sqrt(c->hpin[kHostNorm + (it - 1) % kNormRing]);
+    rn_known = rn;
+    it_known = it;
+  }
+  if (it > 0 && rn > 0.0 && rn_start > 0.0 && std::isfinite(rn)) {
+    const double rho = std::pow(rn / rn_start, 1.0 / it);
+    if (rho > 0.0 && rho < 1.0) c->rho_est = std::min(std::max(rho, 1e-3), 0.9);
   }
   if (gated && net_ran) {
     // outer iterations the guess saved: its residual reduction measured in
@@ -708,7 +740,7 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
   c->box = full_box(cfg->ng);
   c->counts_box = full_box(cfg->ng);
   set_levels(c);
-  c->hpin = new (std::nothrow) double[64]();
+  c->hpin = new (std::nothrow) double[kHostScalars]();
   if (!c->hpin) {
     delete c;
     return fail(nullptr, SDPM_ENOMEM, "host allocation failed");
@@ -819,14 +851,17 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     const ParticleArgs pa = particle_args(c);
     const MeshMap mm = mesh_map(c);
     const double kick = sc.a_half * sc.dtau, drift = 0.5 * sc.dtau / (a + da);
-    if (g.precision == SDPM_MIXED)
-      launch_interp_kick_drift<float>(pa, c->fields.phi, mm, 0.5 / h, kick, drift, g.x_obs,
-                                      sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1, c->dflags,
-                                      c->st);
-    else
-      launch_interp_kick_drift<double>(pa, c->fields.phi, mm, 0.5 / h, kick, drift, g.x_obs,
-                                       sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
+    if (g.precision == SDPM_MIXED) {
+      // FP32 force mesh (FP64 differences), then 12-byte gathers per CIC cell
+      launch_force_mesh(c->fields.phi, c->gmesh, g.ng, mm.active, 0.5 / h, c->st);
+      launch_interp_kick_drift<float>(pa, c->fields.phi, c->gmesh, mm, 0.5 / h, kick, drift,
+                                      g.x_obs, sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
+                                      c->dflags, c->st);
+    } else {
+      launch_interp_kick_drift<double>(pa, c->fields.phi, nullptr, mm, 0.5 / h, kick, drift,
+                                       g.x_obs, sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
                                        c->dflags, c->st);
+    }
   }
   HIP_TRY(c, hipEventRecord(c->ev[4], c->st));
   // Phi from t + dt/2 to t + dt with the same density    (row 7)

@@ -14,6 +14,13 @@ namespace sdpm {
 
 constexpr int kMaxLevels = 12;
 constexpr int kGateProbe = 8, kGateProbeMax = 256;   // solves skipped by the net gate
+// host scalars: hpin[0..15] reduction results, [16..19] flags, [20] kept
+// count, [kHostNorm ..] the ring of per-iteration residual norms
+constexpr int kNormSlot = 16, kNormRing = 32, kHostNorm = 64, kHostScalars = 128;
+// run-ahead of the outer iterations: at most kMaxAhead without a host wait,
+// and only while the predicted norm exceeds kAheadMargin * threshold
+constexpr int kMaxAhead = 16;
+constexpr double kAheadMargin = 10.0;
 constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
 constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
 constexpr int kBoxTy = 4;
@@ -26,6 +33,17 @@ struct Box {
   int lo[3];
   int hi[3];
 };
+
+// Logical workgroup of a 1-D launch: the hardware deals consecutive
+// workgroup ids to the 8 XCDs in turn; this gives each XCD one contiguous run
+// of logical ids, so work items that are neighbours in memory (Morton-ordered
+// particles, neighbouring mesh tiles) share that XCD's L2.
+__device__ inline int64_t xcd_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t xcd = b & 7, slot = b >> 3;
+  const int64_t per = nb >> 3, rem = nb & 7;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
 
 __host__ __device__ inline int64_t lin(int i, int j, int k, int n) {
   return ((int64_t)k * n + j) * n + i;
@@ -116,9 +134,15 @@ template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
                           const MeshMap& mm, uint64_t* counts, uint32_t* flags,
                           hipStream_t st);
+// g3 (FP32, 3 per cell in natural order) = -grad Phi by central differences
+// on the cells of box b.
+void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
+                       hipStream_t st);
+// With g3 != nullptr the force is interpolated from that mesh (made by
+// launch_force_mesh), else from phi directly (FP64 differences).
 template <typename PT>
-void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
-                              double inv2h, double kick_coef, double drift_coef,
+void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,
+                              const MeshMap& mm, double inv2h, double kick_coef, double drift_coef,
                               const double* x_obs, double r2, int count_removed,
                               uint32_t* removed_count, uint32_t* flags, hipStream_t st);
 void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
@@ -184,7 +208,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
-  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC,
+  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

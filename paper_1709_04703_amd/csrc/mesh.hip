@@ -307,37 +307,45 @@ k_restrict(const T* __restrict__ tf, T* __restrict__ rc, int nf, int nc, Box bc)
 // with the red colour, whose update reads only black neighbours and
 // overwrites the red values, so red cells need no correction.  Threads map
 // to (h, j, k) like the smoother; with all_cells each thread also corrects
-// the red cell of its pair.
-template <typename T>
-__device__ inline T prolong_at(const T* __restrict__ ec, int nc, int i, int j, int k) {
-  const int mc = nc - 1;
-  const int i0 = i >> 1, i1 = ((i >> 1) + (i & 1)) & mc;
-  const int j0 = j >> 1, j1 = ((j >> 1) + (j & 1)) & mc;
-  const int c0 = k >> 1, c1 = ((k >> 1) + (k & 1)) & mc;
-  // trilinear: each axis averages (0, 1), which coincide on even indices
-  const T a = ec[sidx(i0, j0, c0, nc)] + ec[sidx(i1, j0, c0, nc)] + ec[sidx(i0, j1, c0, nc)] +
-              ec[sidx(i1, j1, c0, nc)] + ec[sidx(i0, j0, c1, nc)] + ec[sidx(i1, j0, c1, nc)] +
-              ec[sidx(i0, j1, c1, nc)] + ec[sidx(i1, j1, c1, nc)];
-  return (T)0.125 * a;
-}
+// the red cell of its pair.  Trilinear: fine cell i takes the mean of coarse
+// cells i >> 1 and (i >> 1) + (i & 1) per axis (they coincide for even i).
+// A workgroup's fine tile (2 kBoxTx x kBoxTy x kBoxKz cells) reads coarse
+// cells in a (kBoxTx + 1) x 3 x (kBoxKz / 2 + 1) block, staged once in LDS.
+constexpr int kPcx = kBoxTx + 1, kPcy = kBoxTy / 2 + 1, kPcz = kBoxKz / 2 + 1;
 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_prolong(const T* __restrict__ ec, T* __restrict__ ef, int nc, int nf, Box bf, int all_cells) {
+  __shared__ T cs[kPcz][kPcy][kPcx];
   const Tile tl = tile_half(bf);
-  const int j = bf.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  const int h0 = (bf.lo[0] >> 1) + tl.bx * kBoxTx;
+  const int j0 = bf.lo[1] + tl.by * kBoxTy;
+  const int k0 = bf.lo[2] + tl.bz * kBoxKz;
+  const int J0 = j0 >> 1, K0 = k0 >> 1, mc = nc - 1;
+  const int tid = threadIdx.y * kBoxTx + threadIdx.x;
+  for (int q = tid; q < kPcz * kPcy * kPcx; q += 256) {
+    const int ii = q % kPcx, jj = (q / kPcx) % kPcy, kk = q / (kPcx * kPcy);
+    cs[kk][jj][ii] = ec[sidx((h0 + ii) & mc, (J0 + jj) & mc, (K0 + kk) & mc, nc)];
+  }
+  __syncthreads();
+  const int j = j0 + threadIdx.y;
   if (j > bf.hi[1]) return;
-  const int h = (bf.lo[0] >> 1) + tl.bx * kBoxTx + threadIdx.x;
+  const int h = h0 + threadIdx.x;
   const int hn = nf >> 1;
   const int64_t hc = half_cells(nf);
-  const int k0 = bf.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, bf.hi[2]);
+  const int y0 = (j >> 1) - J0, y1 = y0 + (j & 1);
+  const int x0 = threadIdx.x;
   for (int k = k0; k <= k1; ++k) {
     const int64_t row = ((int64_t)k * nf + j) * hn + h;
+    const int z0 = (k >> 1) - K0, z1 = z0 + (k & 1);
     for (int color = all_cells ? 0 : 1; color < 2; ++color) {
       const int i = 2 * h + ((color + j + k) & 1);
       if (i < bf.lo[0] || i > bf.hi[0]) continue;
-      ef[color * hc + row] += prolong_at(ec, nc, i, j, k);
+      const int x1 = x0 + (i & 1);
+      const T a = cs[z0][y0][x0] + cs[z0][y0][x1] + cs[z0][y1][x0] + cs[z0][y1][x1] +
+                  cs[z1][y0][x0] + cs[z1][y0][x1] + cs[z1][y1][x0] + cs[z1][y1][x1];
+      ef[color * hc + row] += (T)0.125 * a;
     }
   }
 }

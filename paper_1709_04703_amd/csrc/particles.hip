@@ -233,9 +233,62 @@ __device__ inline void interp_g(const double* __restrict__ phi, const MeshMap& m
   }
 }
 
-template <typename PT>
+// The same from the FP32 force mesh g3 (3 values per cell): one 12-byte
+// load per CIC cell instead of six FP64 potential values.
+__device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm, const Cic& c,
+                                 double g[3]) {
+  const int n = mm.ng, m = n - 1;
+  const double norm = ldexp(1.0, -3 * mm.frac_bits);
+  g[0] = g[1] = g[2] = 0.0;
+  for (int dz = 0; dz < 2; ++dz) {
+    const int k = (c.cell[2] + dz) & m;
+    for (int dy = 0; dy < 2; ++dy) {
+      const int j = (c.cell[1] + dy) & m;
+      const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
+      if (wyz == 0) continue;
+      for (int dx = 0; dx < 2; ++dx) {
+        const uint64_t wgt = c.w[0][dx] * wyz;
+        if (wgt == 0) continue;
+        const float* q = g3 + 3 * lin((c.cell[0] + dx) & m, j, k, n);
+        const double wd = (double)wgt * norm;
+        g[0] += wd * (double)q[0];
+        g[1] += wd * (double)q[1];
+        g[2] += wd * (double)q[2];
+      }
+    }
+  }
+}
+
+// g3 = -(Phi(i+1) - Phi(i-1)) / 2h per axis on the box; each thread walks
+// kBoxKz planes carrying Phi at k-1 and k.
 __global__ void __launch_bounds__(256)
-k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, double inv2h,
+k_force_mesh(const double* __restrict__ phi, float* __restrict__ g3, int n, Box b, double inv2h,
+             int gx, int gy) {
+  const int64_t bl = xcd_block();
+  const int bx = (int)(bl % gx), by = (int)((bl / gx) % gy), bz = (int)(bl / ((int64_t)gx * gy));
+  const int i = b.lo[0] + bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int m = n - 1;
+  const int k0 = b.lo[2] + bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
+  double below = phi[lin(i, j, (k0 - 1) & m, n)], ctr = phi[lin(i, j, k0, n)];
+  for (int k = k0; k <= k1; ++k) {
+    const double above = phi[lin(i, j, (k + 1) & m, n)];
+    float* q = g3 + 3 * lin(i, j, k, n);
+    q[0] = (float)(-(phi[lin(ip, j, k, n)] - phi[lin(im, j, k, n)]) * inv2h);
+    q[1] = (float)(-(phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]) * inv2h);
+    q[2] = (float)(-(above - below) * inv2h);
+    below = ctr;
+    ctr = above;
+  }
+}
+
+template <typename PT, bool G3>
+__global__ void __launch_bounds__(256)
+k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float* __restrict__ g3,
+                    MeshMap mm, double inv2h,
                     double kick_coef, double drift_coef, double o0, double o1, double o2,
                     double r2, int count_removed, uint32_t* __restrict__ removed_count,
                     uint32_t* __restrict__ flags) {
@@ -249,7 +302,10 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm,
       atomicOr(flags, bad);
     } else {
       double g[3];
-      interp_g(phi, mm, c, inv2h, g);
+      if (G3)
+        interp_g3(g3, mm, c, g);
+      else
+        interp_g(phi, mm, c, inv2h, g);
       for (int d = 0; d < 3; ++d) {
         PT* p = (PT*)pa.p[d];
         const PT pn = (PT)((double)p[i] + g[d] * kick_coef);
@@ -419,24 +475,43 @@ template void launch_drift_deposit<float>(const ParticleArgs&, double, int, cons
 template void launch_drift_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
                                            uint64_t*, uint32_t*, hipStream_t);
 
+void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
+                       hipStream_t st) {
+  const int gx = (b.hi[0] - b.lo[0] + kBoxTx) / kBoxTx, gy = (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy;
+  const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_force_mesh, dim3((unsigned)gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st, phi, g3,
+                     n, b, inv2h, gx, gy);
+  prof_end(st, K_FORCE_MESH, 20.0 * box_cells(b));
+}
+
 template <typename PT>
-void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
-                              double inv2h, double kick_coef, double drift_coef,
+void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,
+                              const MeshMap& mm, double inv2h, double kick_coef, double drift_coef,
                               const double* x_obs, double r2, int count_removed,
                               uint32_t* removed_count, uint32_t* flags, hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st);
-  hipLaunchKernelGGL(k_interp_kick_drift<PT>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi,
-                     mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2], r2,
-                     count_removed, removed_count, flags);
-  prof_end(st, K_INTERP_KICK_DRIFT, (48.0 + 6.0 * sizeof(PT)) * pa.n + 8.0 * box_cells(mm.active));
+  if (g3)
+    hipLaunchKernelGGL((k_interp_kick_drift<PT, true>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st,
+                       pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2],
+                       r2, count_removed, removed_count, flags);
+  else
+    hipLaunchKernelGGL((k_interp_kick_drift<PT, false>), dim3(grid_for(pa.n, 256)), dim3(256), 0,
+                       st, pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1],
+                       x_obs[2], r2, count_removed, removed_count, flags);
+  // particles 36 B read and written; the mesh read once (FP32 force or FP64 potential)
+  prof_end(st, K_INTERP_KICK_DRIFT,
+           (48.0 + 6.0 * sizeof(PT)) * pa.n + (g3 ? 12.0 : 8.0) * box_cells(mm.active));
 }
-template void launch_interp_kick_drift<float>(const ParticleArgs&, const double*, const MeshMap&,
-                                              double, double, double, const double*, double, int,
-                                              uint32_t*, uint32_t*, hipStream_t);
-template void launch_interp_kick_drift<double>(const ParticleArgs&, const double*, const MeshMap&,
-                                               double, double, double, const double*, double,
-                                               int, uint32_t*, uint32_t*, hipStream_t);
+template void launch_interp_kick_drift<float>(const ParticleArgs&, const double*, const float*,
+                                              const MeshMap&, double, double, double,
+                                              const double*, double, int, uint32_t*, uint32_t*,
+                                              hipStream_t);
+template void launch_interp_kick_drift<double>(const ParticleArgs&, const double*, const float*,
+                                               const MeshMap&, double, double, double,
+                                               const double*, double, int, uint32_t*, uint32_t*,
+                                               hipStream_t);
 
 void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
                          double inv2h, double* g0, double* g1, double* g2, uint32_t* flags,
