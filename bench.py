@@ -277,7 +277,7 @@ def main():
             if net_info is None:
                 net_weights, net_info = train_net(P, torch, args)
             weights = net_weights
-        r = run_mode(P, torch, ics, args, prec, profile=(mode != "plain"), weights=weights,
+        r = run_mode(P, torch, ics, args, prec, profile=True, weights=weights,
                      gated=(mode != "learned_always"))
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
@@ -297,6 +297,9 @@ def main():
             "warm_starts_used": r["warm_used"],
             "net_calls": (r["prof"].get("conv3d_mfma", {}).get("launches", 0) // 5
                           if r["prof"] else 0),
+            "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in
+                                   sorted(r["prof"].items(), key=lambda kv: -kv[1]["ms"])[:10]
+                                   if v["launches"]} if r["prof"] else None,
         }
     if "plain" in modes:
         for m in modes.values():

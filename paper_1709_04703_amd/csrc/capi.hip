@@ -889,7 +889,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {0, 6}};
   for (int q = 0; q < 7; ++q) {
     float ms = 0.f;
-    hipEventElapsedTime(&ms, c->ev[pairs[q][0]], c->ev[pairs[q][1]]);
+    (void)hipEventElapsedTime(&ms, c->ev[pairs[q][0]], c->ev[pairs[q][1]]);
     st.ms[q] = ms;
   }
   // solve 1 includes rhs assembly in ms[2]; report rhs separately as ms[1]

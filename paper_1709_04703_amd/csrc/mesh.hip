@@ -49,6 +49,17 @@ __host__ __device__ inline int64_t sidx(int i, int j, int k, int n) {
   return (int64_t)((i + j + k) & 1) * half_cells(n) + ((int64_t)k * n + j) * (n >> 1) + (i >> 1);
 }
 
+// Aligned vectors of 2 and 4 values (one wide load or store).
+template <typename T>
+struct alignas(2 * sizeof(T)) Vec2 {
+  T v[2];
+};
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Vec4 {
+  T v[4];
+};
+
 __device__ inline int block_linear() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
@@ -154,6 +165,75 @@ k_residual(const double* __restrict__ phi, const double* __restrict__ rhs, T* __
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
+// k_residual with 4 consecutive cells per thread (vector loads of phi and
+// rhs, two 2-wide stores per colour of r).  Vectors start at multiples of 4
+// (the box's first x index rounded down); cells outside the box are masked.
+// A tile is 256 x kBoxTy cells x kBoxKz planes.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T* __restrict__ rout,
+              int n, Box b, double kappa, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int ib = b.lo[0] & ~3;
+  const Tile tl = tile_of((b.hi[0] - ib + 256) / 256, (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
+  const int i0 = ib + (tl.bx * kBoxTx + threadIdx.x) * 4;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  const int m = n - 1;
+  double acc = 0.0;
+  if (i0 <= b.hi[0] && j <= b.hi[1]) {
+    const int k0 = b.lo[2] + tl.bz * kBoxKz;
+    const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+    const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
+    const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
+    const int hn = n >> 1;
+    const int64_t hc = half_cells(n);
+    Vec4<double> below = *(const Vec4<double>*)(phi + lin(i0, j, (k0 - 1) & m, n));
+    Vec4<double> ctr = *(const Vec4<double>*)(phi + lin(i0, j, k0, n));
+    for (int k = k0; k <= k1; ++k) {
+      const Vec4<double> above = *(const Vec4<double>*)(phi + lin(i0, j, (k + 1) & m, n));
+      const Vec4<double> ym = *(const Vec4<double>*)(phi + lin(i0, jm, k, n));
+      const Vec4<double> yp = *(const Vec4<double>*)(phi + lin(i0, jp, k, n));
+      const Vec4<double> rv = *(const Vec4<double>*)(rhs + lin(i0, j, k, n));
+      const double xl = phi[lin(il, j, k, n)], xr = phi[lin(ir, j, k, n)];
+      double res[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double left = q == 0 ? xl : ctr.v[q - 1];
+        const double right = q == 3 ? xr : ctr.v[q + 1];
+        const double nb = left + right + ym.v[q] + yp.v[q] + above.v[q] + below.v[q];
+        res[q] = rv.v[q] - (nb - 6.0 * ctr.v[q] - kappa * ctr.v[q]);
+      }
+      // cells i0, i0 + 2 have colour (i0 + j + k) & 1, cells i0 + 1, i0 + 3 the
+      // other; both pairs sit at half indices i0 / 2, i0 / 2 + 1 of their colour
+      const int c0 = (i0 + j + k) & 1;
+      const int64_t row = ((int64_t)k * n + j) * hn + (i0 >> 1);
+      if (full) {
+        Vec2<T> a, bb;
+        a.v[0] = (T)res[0];
+        a.v[1] = (T)res[2];
+        bb.v[0] = (T)res[1];
+        bb.v[1] = (T)res[3];
+        *(Vec2<T>*)(rout + (int64_t)c0 * hc + row) = a;
+        *(Vec2<T>*)(rout + (int64_t)(c0 ^ 1) * hc + row) = bb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += res[q] * res[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + q;
+          if (i < b.lo[0] || i > b.hi[0]) continue;
+          rout[(int64_t)((c0 + q) & 1) * hc + row + (q >> 1)] = (T)res[q];
+          acc += res[q] * res[q];
+        }
+      }
+      below = ctr;
+      ctr = above;
+    }
+  }
+  const double s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_correct(double* __restrict__ phi, const T* __restrict__ e, int n, Box b) {
@@ -241,6 +321,120 @@ k_smooth_color(T* __restrict__ e, const T* __restrict__ r, int n, Box b, int col
                    e[oth + ((int64_t)k * n + jm) * hn + h] + e[oth + ((int64_t)k * n + jp) * hn + h] +
                    e[oth + ((int64_t)km * n + j) * hn + h] + e[oth + ((int64_t)kp * n + j) * hn + h];
       e[c] = (nb - scale * r[c]) * inv_diag;
+    }
+  }
+}
+
+// The same sweep with 4 consecutive cells of the colour per thread (16-byte
+// loads and stores in FP32): the row of the other colour is one vector load
+// plus one scalar for the cell beyond the vector's edge, the y / z
+// neighbours and r one vector load each.  Vectors start at multiples of 4
+// (the box's first half-row index rounded down; n / 2 is a multiple of 4, so
+// a vector never leaves its row) and cells outside the box are masked.
+// Tiles are 4 TXV half-row entries x 256 / TXV rows x kBoxKz planes.
+template <typename T, bool FIRST, int TXV>
+__global__ void __launch_bounds__(256)
+k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restrict__ ro, int n,
+                  Box b, int color, T scale, T inv_diag) {
+  // eo / ro: this colour's half of e / r; ex: the other colour's half of e
+  constexpr int TY = 256 / TXV;
+  const int hb = (b.lo[0] >> 1) & ~3, hhi = b.hi[0] >> 1;
+  const Tile tl = tile_of((hhi - hb + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
+  const int h0 = hb + (tl.bx * TXV + threadIdx.x) * 4;
+  if (j > b.hi[1] || h0 > hhi) return;
+  const int m = n - 1, hn = n >> 1;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int jp = (j + 1) & m, jm = (j - 1) & m;
+#pragma unroll 2
+  for (int k = k0; k <= k1; ++k) {
+    const int p = (color + j + k) & 1;          // cell q of the vector: i = 2 (h0 + q) + p
+    const int64_t row = ((int64_t)k * n + j) * hn;
+    const Vec4<T> rv = *(const Vec4<T>*)(ro + row + h0);
+    T out[4];
+    if (FIRST) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q] = -scale * rv.v[q] * inv_diag;
+    } else {
+      const int kp = (k + 1) & m, km = (k - 1) & m;
+      const Vec4<T> xc = *(const Vec4<T>*)(ex + row + h0);
+      const Vec4<T> ym = *(const Vec4<T>*)(ex + ((int64_t)k * n + jm) * hn + h0);
+      const Vec4<T> yp = *(const Vec4<T>*)(ex + ((int64_t)k * n + jp) * hn + h0);
+      const Vec4<T> zm = *(const Vec4<T>*)(ex + ((int64_t)km * n + j) * hn + h0);
+      const Vec4<T> zp = *(const Vec4<T>*)(ex + ((int64_t)kp * n + j) * hn + h0);
+      // x neighbours i -+ 1 sit at half index h - 1 + p and h + p; the one
+      // outside the vector: cell 2 h0 - 1 (p = 0) or 2 h0 + 8 (p = 1)
+      const T xs = ex[row + ((p ? (2 * h0 + 8) : (2 * h0 - 1)) & m) / 2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T xl = p ? xc.v[q] : (q == 0 ? xs : xc.v[q - 1]);
+        const T xr = p ? (q == 3 ? xs : xc.v[q + 1]) : xc.v[q];
+        out[q] = (xl + xr + ym.v[q] + yp.v[q] + zm.v[q] + zp.v[q] - scale * rv.v[q]) * inv_diag;
+      }
+    }
+    if (2 * h0 + p >= b.lo[0] && 2 * h0 + 6 + p <= b.hi[0]) {
+      Vec4<T> o;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o.v[q] = out[q];
+      *(Vec4<T>*)(eo + row + h0) = o;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 2 * (h0 + q) + p;
+        if (i >= b.lo[0] && i <= b.hi[0]) eo[row + h0 + q] = out[q];
+      }
+    }
+  }
+}
+
+// k_resid_red with 4 red cells per thread (see k_smooth_color_v4).
+template <typename T, int TXV>
+__global__ void __launch_bounds__(256)
+k_resid_red_v4(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__ tout, int n, Box b,
+               T inv_scale, T kappa) {
+  constexpr int TY = 256 / TXV;
+  const int hb = (b.lo[0] >> 1) & ~3, hhi = b.hi[0] >> 1;
+  const Tile tl = tile_of((hhi - hb + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
+  const int h0 = hb + (tl.bx * TXV + threadIdx.x) * 4;
+  if (j > b.hi[1] || h0 > hhi) return;
+  const int m = n - 1, hn = n >> 1;
+  const int64_t oth = half_cells(n);
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int jp = (j + 1) & m, jm = (j - 1) & m;
+  for (int k = k0; k <= k1; ++k) {
+    const int p = (j + k) & 1;
+    const int kp = (k + 1) & m, km = (k - 1) & m;
+    const int64_t row = ((int64_t)k * n + j) * hn;
+    const Vec4<T> ctr = *(const Vec4<T>*)(e + row + h0);
+    const Vec4<T> rv = *(const Vec4<T>*)(r + row + h0);
+    const Vec4<T> xc = *(const Vec4<T>*)(e + oth + row + h0);
+    const Vec4<T> ym = *(const Vec4<T>*)(e + oth + ((int64_t)k * n + jm) * hn + h0);
+    const Vec4<T> yp = *(const Vec4<T>*)(e + oth + ((int64_t)k * n + jp) * hn + h0);
+    const Vec4<T> zm = *(const Vec4<T>*)(e + oth + ((int64_t)km * n + j) * hn + h0);
+    const Vec4<T> zp = *(const Vec4<T>*)(e + oth + ((int64_t)kp * n + j) * hn + h0);
+    const T xs = e[oth + row + ((p ? (2 * h0 + 8) : (2 * h0 - 1)) & m) / 2];
+    T out[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T xl = p ? xc.v[q] : (q == 0 ? xs : xc.v[q - 1]);
+      const T xr = p ? (q == 3 ? xs : xc.v[q + 1]) : xc.v[q];
+      const T nb = xl + xr + ym.v[q] + yp.v[q] + zm.v[q] + zp.v[q];
+      out[q] = rv.v[q] - (nb - (T)6 * ctr.v[q]) * inv_scale + kappa * ctr.v[q];
+    }
+    if (2 * h0 + p >= b.lo[0] && 2 * h0 + 6 + p <= b.hi[0]) {
+      Vec4<T> o;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o.v[q] = out[q];
+      *(Vec4<T>*)(tout + row + h0) = o;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 2 * (h0 + q) + p;
+        if (i >= b.lo[0] && i <= b.hi[0]) tout[row + h0 + q] = out[q];
+      }
     }
   }
 }
@@ -572,11 +766,21 @@ void launch_rhs(const uint64_t* counts, const double* phi, double* rhs, int n, c
 template <typename T>
 void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
                      double kappa, double* partial, int* nblocks, hipStream_t st) {
-  const dim3 g = box_grid(b);
-  *nblocks = (int)(g.x * g.y * g.z);
+  const int ib = b.lo[0] & ~3;
   prof_begin(st);
-  hipLaunchKernelGGL(k_residual<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, rhs, r_out, n, b, kappa,
-                     partial);
+  if (b.hi[0] - ib + 1 >= 64) {
+    const unsigned gx = (unsigned)((b.hi[0] - ib + 256) / 256);
+    const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
+    const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz);
+    *nblocks = (int)(gx * gy * gz);
+    hipLaunchKernelGGL(k_residual_v4<T>, dim3(gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st, phi, rhs,
+                       r_out, n, b, kappa, partial);
+  } else {
+    const dim3 g = box_grid(b);
+    *nblocks = (int)(g.x * g.y * g.z);
+    hipLaunchKernelGGL(k_residual<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, rhs, r_out, n, b, kappa,
+                       partial);
+  }
   prof_end(st, K_RESIDUAL, (16.0 + sizeof(T)) * box_cells(b));
 }
 template void launch_residual<float>(const double*, const double*, float*, int, const Box&,
@@ -668,22 +872,90 @@ void launch_record_accum(const T* e_split, int n, const Box& b, float* dphi, hip
 template void launch_record_accum<float>(const float*, int, const Box&, float*, hipStream_t);
 template void launch_record_accum<double>(const double*, int, const Box&, float*, hipStream_t);
 
+// Vector width of the colour kernels for a level box: 4 cells per thread
+// with 64, 32 or 16 threads across a tile row when the box is wide enough;
+// 0 selects the scalar kernels.
+inline int v4_threads(const Box& b) {
+  const int ext = (b.hi[0] >> 1) - ((b.lo[0] >> 1) & ~3) + 1;
+  return ext >= 256 ? 64 : ext >= 128 ? 32 : ext >= 32 ? 16 : 0;
+}
+
+inline dim3 v4_grid(const Box& b, int txv) {
+  const int ty = 256 / txv;
+  const int gx = ((b.hi[0] >> 1) - ((b.lo[0] >> 1) & ~3) + 4 * txv) / (4 * txv);
+  const int gy = (b.hi[1] - b.lo[1] + ty) / ty;
+  const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
+  return dim3((unsigned)gx * gy * gz);
+}
+
 template <typename T>
 static void smooth_color(T* e, const T* r, const Level& L, int color, bool first, T scale,
                          T inv_diag, hipStream_t st) {
   const Box& b = L.box;
-  const dim3 g = half_grid(b);
+  const int txv = sizeof(T) == 4 ? v4_threads(b) : 0;   // FP64 levels: the scalar kernel is faster
   prof_begin(st);
-  if (first)
-    hipLaunchKernelGGL((k_smooth_color<T, true>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
-                       color, scale, inv_diag);
-  else
-    hipLaunchKernelGGL((k_smooth_color<T, false>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
-                       color, scale, inv_diag);
+  const int64_t hc = (int64_t)L.n * L.n * (L.n >> 1);
+  T* eo = e + color * hc;
+  const T* ex = e + (color ^ 1) * hc;
+  const T* ro = r + color * hc;
+  if (txv == 64) {
+    const dim3 g = v4_grid(b, 64), blk(64, 4);
+    if (first)
+      hipLaunchKernelGGL((k_smooth_color_v4<T, true, 64>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+    else
+      hipLaunchKernelGGL((k_smooth_color_v4<T, false, 64>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+  } else if (txv == 32) {
+    const dim3 g = v4_grid(b, 32), blk(32, 8);
+    if (first)
+      hipLaunchKernelGGL((k_smooth_color_v4<T, true, 32>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+    else
+      hipLaunchKernelGGL((k_smooth_color_v4<T, false, 32>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+  } else if (txv == 16) {
+    const dim3 g = v4_grid(b, 16), blk(16, 16);
+    if (first)
+      hipLaunchKernelGGL((k_smooth_color_v4<T, true, 16>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+    else
+      hipLaunchKernelGGL((k_smooth_color_v4<T, false, 16>), g, blk, 0, st, eo, ex, ro, L.n, b, color,
+                         scale, inv_diag);
+  } else {
+    const dim3 g = half_grid(b);
+    if (first)
+      hipLaunchKernelGGL((k_smooth_color<T, true>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
+                         color, scale, inv_diag);
+    else
+      hipLaunchKernelGGL((k_smooth_color<T, false>), g, dim3(kBoxTx, kBoxTy), 0, st, e, r, L.n, b,
+                         color, scale, inv_diag);
+  }
   // first (red, zero guess): r + e of the colour; otherwise e of the other
   // colour + r and e of this colour: half the cells each
   const double cells = (double)box_cells(b);
   prof_end(st, first ? K_SMOOTH_FIRST : K_SMOOTH, (first ? 1.0 : 1.5) * sizeof(T) * cells);
+}
+
+template <typename T>
+static void resid_red(const T* e, const T* r, T* t, const Level& L, T inv_scale, T kappa,
+                      hipStream_t st) {
+  const Box& b = L.box;
+  const int txv = sizeof(T) == 4 ? v4_threads(b) : 0;
+  prof_begin(st);
+  if (txv == 64)
+    hipLaunchKernelGGL((k_resid_red_v4<T, 64>), v4_grid(b, 64), dim3(64, 4), 0, st, e, r, t, L.n, b,
+                       inv_scale, kappa);
+  else if (txv == 32)
+    hipLaunchKernelGGL((k_resid_red_v4<T, 32>), v4_grid(b, 32), dim3(32, 8), 0, st, e, r, t, L.n, b,
+                       inv_scale, kappa);
+  else if (txv == 16)
+    hipLaunchKernelGGL((k_resid_red_v4<T, 16>), v4_grid(b, 16), dim3(16, 16), 0, st, e, r, t, L.n, b,
+                       inv_scale, kappa);
+  else
+    hipLaunchKernelGGL(k_resid_red<T>, half_grid(b), dim3(kBoxTx, kBoxTy), 0, st, e, r, t, L.n, b,
+                       inv_scale, kappa);
+  prof_end(st, K_RESID_LEVEL, 2.0 * sizeof(T) * (double)box_cells(b));
 }
 
 template <typename T>
@@ -702,13 +974,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
       smooth_color<T>(e, r, L, 0, s == 0, scale, inv_diag, st);
       smooth_color<T>(e, r, L, 1, false, scale, inv_diag, st);
     }
-    {
-      const dim3 g = half_grid(L.box);
-      prof_begin(st);
-      hipLaunchKernelGGL(k_resid_red<T>, g, blk, 0, st, e, r, (T*)L.t, L.n, L.box,
-                         (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa);
-      prof_end(st, K_RESID_LEVEL, 2.0 * es * cells);
-    }
+    resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
     prof_begin(st);
     hipLaunchKernelGGL(k_restrict<T>, box_grid(C.box), blk, 0, st, (const T*)L.t, (T*)C.r, L.n,

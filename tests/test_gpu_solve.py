@@ -60,25 +60,29 @@ def test_periodic_solve_and_force(ng, kappa, prec, tol):
     sim.close()
 
 
-@pytest.mark.parametrize("kappa,prec,align", [(0.0, 0, None), (0.25, 0, None), (0.0, 1, None),
-                                              (0.0, 0, 1), (0.06, 0, 2)])
-def test_dirichlet_box_solve_with_frozen_ring(kappa, prec, align):
-    ng, box, n = 64, 640.0, 6000
+@pytest.mark.parametrize("kappa,prec,align,ng", [
+    (0.0, 0, None, 64), (0.25, 0, None, 64), (0.0, 1, None, 64), (0.0, 0, 1, 64), (0.06, 0, 2, 64),
+    # boxes wide enough for the 4-cell vector kernels, aligned and unaligned
+    (0.0, 0, None, 128), (0.25, 0, 1, 128), (0.06, 1, 4, 128),
+])
+def test_dirichlet_box_solve_with_frozen_ring(kappa, prec, align, ng):
+    box, n = 10.0 * ng, 6000 * (ng // 64) ** 3
     kw = dict(shrink=1, precision=prec, n_initial=n)
     if align is not None:
         kw["box_align"] = align
     cfg = lib_config(ng, box, **kw)
     ocfg = oracle_config(cfg)
-    x, p, ids = clustered_particles(n, box, 3, ng=ng, width_cells=1.5, lo=230.0, hi=410.0)
+    x, p, ids = clustered_particles(n, box, 3, ng=ng, width_cells=1.5, lo=0.36 * box, hi=0.64 * box)
     rng = np.random.Generator(np.random.PCG64(11))
     phi0 = rng.normal(size=(ng, ng, ng)) * 1e-2
     log(f"dirichlet solve kappa={kappa} precision={prec} align={cfg.box_align}")
     sim = make_sim(cfg, n)
     sim.bind(x, p, ids, phi=phi0)
-    sim.shrink_radius(200.0)
+    radius = box * 200.0 / 640.0
+    sim.shrink_radius(radius)
     st0 = sim.state()
     ost = pm.State(x.copy(), p.copy(), ids.copy(), n, phi0.copy(), 0.5)
-    pm.shrink_radius(ost, ocfg, 200.0)
+    pm.shrink_radius(ost, ocfg, radius)
     assert st0["periodic"] == 0 and not ost.periodic
     assert st0["lo"] == list(ost.lo) and st0["hi"] == list(ost.hi)
     sim.deposit()
