@@ -282,7 +282,7 @@ def main():
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
-    head_mode = next(m for m in ("learned", "mixed", "plain") if m in results)
+    head_mode = next(m for m in ("learned", "mixed", "plain", "learned_always") if m in results)
     head = results[head_mode]
     value = head["updates"] / head["seconds"]
     modes = {}
@@ -333,7 +333,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
-                  "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net"}[head_mode],
+                  "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
+                  "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "

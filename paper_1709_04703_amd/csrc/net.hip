@@ -2,14 +2,13 @@
 // net with 16 channels (ReLU between layers, periodic padding), BF16 weights
 // and activations, FP32 accumulation on the matrix cores of gfx950.
 //
-// Each layer is an implicit GEMM per tap t:  Out^T (16 co x voxels) +=
-// W_t^T (16 co x 16 ci) * In_t^T (16 ci x voxels), one
-// v_mfma_f32_16x16x16_bf16 per (tap, 16 voxels).  Activations are stored
-// channels-last (16 BF16 = 32 B per voxel), so a lane's B fragment (4
-// channels of one voxel) is one 8-byte read and its D fragment (4 channels
-// of one voxel) one 8-byte write.  MFMA 16x16x16 lane layout (64 lanes,
-// g = lane / 16, r = lane % 16): A[r][4g..4g+3], B[4g..4g+3][r],
-// D[4g..4g+3][r].
+// Each layer is an implicit GEMM over taps t:  Out^T (16 co x voxels) +=
+// W_t^T (16 co x 16 ci) * In_t^T (16 ci x voxels).  Activations are stored
+// channels-last (16 BF16 = 32 B per voxel), so a lane's B fragment (8 or 4
+// channels of one voxel) is one 16- or 8-byte read and its D fragment (4
+// channels of one voxel) one 8-byte write.  MFMA lane layouts (64 lanes,
+// g = lane / 16, r = lane % 16): 16x16x16 A[r][4g..4g+3], B[4g..4g+3][r];
+// 16x16x32 A[r][8g..8g+7], B[8g..8g+7][r]; both D[4g..4g+3][r].
 //
 // The data gradient of a layer is the same kernel with the taps mirrored and
 // the channel roles swapped (BACKWARD flag); the weight gradient reduces
@@ -26,8 +25,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNC = 16;                 // channels
-constexpr int kCTX = 64, kCTY = 4, kCTZ = 8;   // forward tile: 64 x 4 voxels, 8 planes
-constexpr int kWX = kCTX + 2, kWY = kCTY + 2;  // LDS plane with halo
+constexpr int kCTY = 4, kCTZ = 8;             // weight-gradient tile: 4 rows, 8 planes
 
 __device__ inline uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -42,27 +40,50 @@ __device__ inline int64_t vox(int i, int j, int k, int n) { return ((int64_t)k *
 // ---------------------------------------------------------------- forward
 // flags: 1 ReLU, 2 FP32 output of channel 0 only, 4 backward-data (mirrored
 // taps, swapped channels, no bias), 8 multiply by [mask > 0].
+//
+// v_mfma_f32_16x16x32_bf16 (K = 32: two taps of 16 input channels at once;
+// gfx950 runs it at twice the rate of the K = 16 form).  Lane layout (g =
+// lane / 16, r = lane % 16): A[r][8g .. 8g+7], B[8g .. 8g+7][r],
+// D[4g .. 4g+3][r].  Taps are paired along x: one MFMA takes dx = -1 (k < 16)
+// and dx = 0 (k >= 16) of an input row, a second dx = +1 (k < 16; the other
+// half has zero weights).  A workgroup walks kZB blocks of kCZ planes; for
+// each it holds the input voxels (64 + 2) x (kCY + 2) x (kCZ + 2) in an LDS
+// ring of kBZ planes (consecutive blocks share two planes, so a block loads
+// kCZ new ones); each of its 4 waves owns 16 output voxels in x for all
+// kCY x kCZ output rows and reuses every input-row fragment it loads for the
+// (up to 9) output rows that row feeds.  The weights stay in registers for
+// all blocks.
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kCY = 4, kCZ = 4;                  // output rows per block (y, z)
+constexpr int kZB = 8;                           // z blocks per workgroup (weights loaded once)
+constexpr int kBX = 64 + 2, kBY = kCY + 2, kBZ = kCZ + 2;
+
 template <int FLAGS>
 __global__ void __launch_bounds__(256)
 k_conv(int n, const uint16_t* __restrict__ in, const float* __restrict__ w,
        const float* __restrict__ bias, const uint16_t* __restrict__ mask, void* __restrict__ out) {
   constexpr bool RELU = FLAGS & 1, OUT0 = FLAGS & 2, BWD = FLAGS & 4, MASK = FLAGS & 8;
-  __shared__ __attribute__((aligned(16))) uint16_t win[3][kWY][kWX][kNC];
+  __shared__ __attribute__((aligned(16))) uint16_t blk[kBZ][kBY][kBX][kNC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, r = lane & 15;
+  const int g = lane >> 4, r = lane & 15, hi = g >> 1, cg = g & 1;
   const int m = n - 1;
-  const int gx = (n + kCTX - 1) / kCTX, gy = n / kCTY;
+  const int gx = (n + 63) / 64, gy = n / kCY;
   const int bx = blockIdx.x % gx, by = (blockIdx.x / gx) % gy, bz = blockIdx.x / (gx * gy);
-  const int x0 = bx * kCTX, y0 = by * kCTY, z0 = bz * kCTZ;
-  // A fragments: A[co = r][ci = 4g + q] of every tap, converted to BF16
-  bf16x4 af[27];
+  const int x0 = bx * 64, y0 = by * kCY;
+  // weight fragments per (dy, dz): a01 = taps dx = -1 (k < 16), dx = 0 (k >= 16);
+  // a2 = tap dx = +1 (k < 16), zero for k >= 16.  Element j of lane (g, r):
+  // input channel 8 cg + j, output channel r.
+  bf16x8 a01[9], a2[9];
 #pragma unroll
-  for (int t = 0; t < 27; ++t) {
+  for (int yz = 0; yz < 9; ++yz) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ci = 4 * g + q;
-      const float v = BWD ? w[((26 - t) * kNC + r) * kNC + ci] : w[(t * kNC + ci) * kNC + r];
-      af[t][q] = (short)f2bf(v);
+    for (int j = 0; j < 8; ++j) {
+      const int ci = 8 * cg + j;
+      const int t01 = yz * 3 + (hi ? 1 : 0), t2 = yz * 3 + 2;
+      const float v01 = BWD ? w[((26 - t01) * kNC + r) * kNC + ci] : w[(t01 * kNC + ci) * kNC + r];
+      const float v2 = BWD ? w[((26 - t2) * kNC + r) * kNC + ci] : w[(t2 * kNC + ci) * kNC + r];
+      a01[yz][j] = (short)f2bf(v01);
+      a2[yz][j] = hi ? (short)0 : (short)f2bf(v2);
     }
   }
   float bq[4] = {0.f, 0.f, 0.f, 0.f};
@@ -70,45 +91,62 @@ k_conv(int n, const uint16_t* __restrict__ in, const float* __restrict__ w,
 #pragma unroll
     for (int q = 0; q < 4; ++q) bq[q] = bias[4 * g + q];
   }
-  auto load_plane = [&](int z) {
-    uint4* dst = (uint4*)&win[((z % 3) + 3) % 3][0][0][0];
-    const int zz = z & m;
-    for (int c = tid; c < kWY * kWX * 2; c += 256) {
-      const int half = c & 1, vv = c >> 1;
-      const int px = vv % kWX, py = vv / kWX;
-      const int xx = (x0 - 1 + px) & m, yy = (y0 - 1 + py) & m;
-      dst[c] = ((const uint4*)(in + vox(xx, yy, zz, n) * kNC))[half];
-    }
-  };
-  load_plane(z0 - 1);
-  load_plane(z0);
-  const int y = y0 + wave;
-  for (int z = z0; z < z0 + kCTZ && z < n; ++z) {
-    load_plane(z + 1);
-    __syncthreads();
-    f32x4 acc[4];
+  for (int zb = 0; zb < kZB; ++zb) {
+  const int z0 = (bz * kZB + zb) * kCZ;
+  if (z0 >= n) break;
+  __syncthreads();                               // the planes to overwrite are consumed
+  // input plane z0 - 1 + pz sits in ring slot (kCZ zb + pz) % kBZ; planes
+  // pz < 2 were loaded with the previous block.  16 bytes per load.
+  const int pz0 = zb == 0 ? 0 : 2;
+  for (int c = tid; c < (kBZ - pz0) * kBY * kBX * 2; c += 256) {
+    const int half = c & 1, v = c >> 1;
+    const int px = v % kBX, py = (v / kBX) % kBY, pz = pz0 + v / (kBX * kBY);
+    const int xx = (x0 - 1 + px) & m, yy = (y0 - 1 + py) & m, zz = (z0 - 1 + pz) & m;
+    ((uint4*)&blk[(kCZ * zb + pz) % kBZ][py][px][0])[half] =
+        ((const uint4*)(in + vox(xx, yy, zz, n) * kNC))[half];
+  }
+  f32x4 acc[kCZ][kCY];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < kCZ; ++a)
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
-      const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-      const int slot = (((z + dz) % 3) + 3) % 3;
+    for (int b = 0; b < kCY; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+  // output voxel x0 + 16 wave + r reads block column 16 wave + r + 1 + dx
+  const int col = 16 * wave + r + 1;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const uint16_t* src = &win[slot][wave + 1 + dy][16 * s + r + 1 + dx][4 * g];
-        const bf16x4 b = *(const bf16x4*)src;
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[t], b, acc[s], 0, 0, 0);
+  for (int pz = 0; pz < kBZ; ++pz) {
+#pragma unroll
+    for (int py = 0; py < kBY; ++py) {
+      // F01: k < 16 from x - 1, k >= 16 from x; F2: x + 1 (both halves)
+      const int sl = (kCZ * zb + pz) % kBZ;
+      const bf16x8 f01 = *(const bf16x8*)&blk[sl][py][col - 1 + hi][8 * cg];
+      const bf16x8 f2 = *(const bf16x8*)&blk[sl][py][col + 1][8 * cg];
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int oz = pz - 1 - dz;            // output row fed with this tap
+        if (oz < 0 || oz >= kCZ) continue;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int oy = py - 1 - dy;
+          if (oy < 0 || oy >= kCY) continue;
+          const int yz = (dz + 1) * 3 + (dy + 1);
+          acc[oz][oy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a01[yz], f01, acc[oz][oy], 0, 0, 0);
+          acc[oz][oy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[yz], f2, acc[oz][oy], 0, 0, 0);
+        }
       }
     }
-    // D[co = 4g + q][voxel = r] of sub-tile s
+  }
+  // D[co = 4g + q][voxel = r] of each output row
+  const int x = (x0 + 16 * wave + r) & m;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int x = (x0 + 16 * s + r) & m;
-      const int64_t v = vox(x, y & m, z, n);
+  for (int oz = 0; oz < kCZ; ++oz) {
+#pragma unroll
+    for (int oy = 0; oy < kCY; ++oy) {
+      const int64_t v = vox(x, (y0 + oy) & m, (z0 + oz) & m, n);
       float val[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        float a = acc[s][q] + bq[q];
+        float a = acc[oz][oy][q] + bq[q];
         if (RELU) a = a > 0.f ? a : 0.f;
         val[q] = a;
       }
@@ -127,7 +165,7 @@ k_conv(int n, const uint16_t* __restrict__ in, const float* __restrict__ w,
         *(bf16x4*)((uint16_t*)out + v * kNC + 4 * g) = o;
       }
     }
-    __syncthreads();
+  }
   }
 }
 
@@ -305,7 +343,7 @@ k_adam(int np, float* __restrict__ p, const float* __restrict__ grad, float* __r
   p[q] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
 }
 
-int conv_blocks(int n) { return ((n + kCTX - 1) / kCTX) * (n / kCTY) * ((n + kCTZ - 1) / kCTZ); }
+int conv_blocks(int n) { return ((n + 63) / 64) * (n / kCY) * ((n / kCZ + kZB - 1) / kZB); }
 int wgrad_blocks(int n) {
   const int groups = n >= 64 ? 4 : n / 16;
   return (n / (16 * groups)) * (n / kCTY) * ((n + kCTZ - 1) / kCTZ);
