@@ -48,7 +48,8 @@ enum {
   SDPM_ENOCONV = -4,    /* multigrid did not reach tol in max_outer      */
   SDPM_EDOMAIN = -5,    /* a particle's CIC support left the active box  */
   SDPM_EOVERFLOW = -6,  /* fixed-point coordinate out of range           */
-  SDPM_ESTATE = -7      /* call out of order (e.g. step before bind)     */
+  SDPM_ESTATE = -7,     /* call out of order (e.g. step before bind)     */
+  SDPM_EFULL = -8       /* lightcone output full: later records dropped  */
 };
 
 enum { SDPM_MIXED = 0, SDPM_PLAIN_FP64 = 1 };      /* sdpm_config.precision  */
@@ -187,6 +188,34 @@ int sdpm_shrink(sdpm_ctx* ctx, double a, int64_t* n_removed, uint32_t* removed_i
 /* As sdpm_shrink but with an explicit lightcone radius r (for tests).       */
 int sdpm_shrink_radius(sdpm_ctx* ctx, double r, int64_t* n_removed,
                        uint32_t* removed_ids_dev);
+
+/* Lightcone output ----------------------------------------------------------
+ * The natural output of the method is the past lightcone of the observer
+ * (Sec. 1 list of the framework's characteristics; Table 2 last row: the
+ * particles leaving the lightcone are eliminated).  When enabled, every
+ * particle removed by sdpm_step is recorded where it crosses the lightcone
+ * during that step: traced back from its end-of-step position x1 along its
+ * end-of-step velocity, x(u) = x1 - u w with w = p1 dtau / a1, while the
+ * lightcone radius grows back as r(u) = r1 + u c dtau (r_lc is linear in
+ * conformal time), u in [0, 1] the fraction of the step before its end; the
+ * crossing is the root of |x(u) - x_obs| = r(u) (u = 1, the step's start,
+ * for a particle that was already outside then).  Record: id, a = a1 - u da,
+ * x(u), p1.  sdpm_shrink(a) and sdpm_init_potential record their removals
+ * at u = 0; sdpm_shrink_radius records nothing.  Records are appended in
+ * removal order (the order of the stable partition); once `capacity` is
+ * reached later records are dropped and the call returns SDPM_EFULL after
+ * completing its work.  Device arrays of `capacity` entries, caller-owned.  */
+typedef struct sdpm_lightcone {
+  uint32_t* id;
+  double* a;
+  double* x[3];
+  double* p[3];
+  int64_t capacity;
+} sdpm_lightcone;
+/* Enables the output into `out` (NULL disables) and resets the count.      */
+int sdpm_set_lightcone(sdpm_ctx* ctx, const sdpm_lightcone* out);
+/* Records written since sdpm_set_lightcone.                                */
+int sdpm_lightcone_count(sdpm_ctx* ctx, int64_t* count);
 
 /* Current state: n_active, box, boundary mode (host scalars).              */
 int sdpm_get_state(sdpm_ctx* ctx, sdpm_step_stats* out);

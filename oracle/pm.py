@@ -277,6 +277,40 @@ def outside_lightcone(x: np.ndarray, x_obs: np.ndarray, r_lc: float) -> np.ndarr
     return d2 > r_lc * r_lc
 
 
+def lightcone_crossing(x1: np.ndarray, p1: np.ndarray, x_obs: np.ndarray, r1: float,
+                       light: float, disp: float, a1: float, da: float):
+    """Where removed particles crossed the lightcone during their last step
+    (the lightcone output; the reading stated in the C header): the particle
+    is traced back from its end-of-step position x1 along w = p1 disp
+    (disp = dtau / a1), x(u) = x1 - u w, while the radius grows back as
+    r(u) = r1 + u light (light = c dtau), u in [0, 1] the fraction of the step
+    before its end.  u is the root of f(u) = |x(u) - x_obs|^2 - r(u)^2, found
+    by bisection (f(0) > 0 for a removed particle); u = 1 when f(1) > 0 (the
+    particle was already outside at the step's start), u = 0 when light = 0.
+    Returns (u, a = a1 - u da, x(u), p1)."""
+    d = x1 - x_obs
+    w = p1 * disp
+
+    def f(u):
+        y = d - u[:, None] * w
+        return np.sum(y * y, axis=1) - (r1 + u * light) ** 2
+
+    n = x1.shape[0]
+    if light <= 0.0:
+        u = np.zeros(n)
+    else:
+        lo, hi = np.zeros(n), np.ones(n)
+        outside_at_start = f(hi) > 0.0
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            pos = f(mid) > 0.0
+            lo = np.where(pos, mid, lo)
+            hi = np.where(pos, hi, mid)
+        u = np.where(outside_at_start, 1.0, 0.5 * (lo + hi))
+        u = np.where(np.sum(d * d, axis=1) - r1 * r1 > 0.0, u, 0.0)
+    return u, a1 - u * da, x1 - u[:, None] * w, p1.copy()
+
+
 def box_for_radius(r_lc: float, x_obs: np.ndarray, h: float, ng: int, margin: int,
                    align: int = 1):
     """Index box covering the sphere of radius r_lc about x_obs plus `margin`

@@ -16,14 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdpm.so")
 
 SDPM_OK, SDPM_EINVAL, SDPM_ENOMEM, SDPM_EHIP = 0, -1, -2, -3
-SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE = -4, -5, -6, -7
+SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6, -7, -8
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
 SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED = 0, 1, 2
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",
     SDPM_ENOCONV: "ENOCONV", SDPM_EDOMAIN: "EDOMAIN", SDPM_EOVERFLOW: "EOVERFLOW",
-    SDPM_ESTATE: "ESTATE",
+    SDPM_ESTATE: "ESTATE", SDPM_EFULL: "EFULL",
 }
 
 # every symbol include/sdpm.h declares
@@ -34,7 +34,7 @@ EXPORTS = [
     "sdpm_interp_force", "sdpm_sort", "sdpm_set_warmstart_weights", "sdpm_conv3d",
     "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
     "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
-    "sdpm_destroy", "sdpm_last_error",
+    "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
 ]
 NET_PARAMS = 5 * (27 * 16 * 16 + 16)
 CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
@@ -65,6 +65,11 @@ class Config(ctypes.Structure):
 class Particles(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 3), ("p", ctypes.c_void_p * 3),
                 ("id", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class Lightcone(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_void_p), ("a", ctypes.c_void_p), ("x", ctypes.c_void_p * 3),
+                ("p", ctypes.c_void_p * 3), ("capacity", ctypes.c_int64)]
 
 
 class Fields(ctypes.Structure):
@@ -143,6 +148,8 @@ def library() -> ctypes.CDLL:
         "sdpm_profile": [vp, i32],
         "sdpm_profile_read": [vp, P(KernelStat), i32, P(i32)],
         "sdpm_destroy": [vp],
+        "sdpm_set_lightcone": [vp, P(Lightcone)],
+        "sdpm_lightcone_count": [vp, P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -341,7 +348,8 @@ class Simulation:
     def step(self, a: float, da: float, raise_on_error: bool = True) -> dict:
         st = StepStats()
         rc = self.lib.sdpm_step(self.ctx, a, da, ctypes.byref(st))
-        self.n_active = st.n_active if rc in (SDPM_OK, SDPM_ENOCONV, SDPM_EDOMAIN) else self.n_active
+        self.n_active = (st.n_active if rc in (SDPM_OK, SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EFULL)
+                         else self.n_active)
         if raise_on_error:
             self._check(rc)
         d = st.as_dict()
@@ -384,6 +392,42 @@ class Simulation:
         arr = (ctypes.c_void_p * 3)(*(g[d].data_ptr() for d in range(3)))
         self._check(self.lib.sdpm_interp_force(self.ctx, arr))
         return g[:, :n]
+
+    # -- lightcone output
+    def set_lightcone(self, capacity: int):
+        """Record removed particles at their lightcone crossing into device
+        buffers of `capacity` records (capacity 0 disables)."""
+        torch = self.torch
+        if capacity <= 0:
+            self._lc = None
+            self._check(self.lib.sdpm_set_lightcone(self.ctx, None))
+            return
+        dev = self.device
+        self._lc = dict(id=torch.zeros(capacity, dtype=torch.int32, device=dev),
+                        a=torch.zeros(capacity, dtype=torch.float64, device=dev),
+                        x=torch.zeros((3, capacity), dtype=torch.float64, device=dev),
+                        p=torch.zeros((3, capacity), dtype=torch.float64, device=dev))
+        lc = Lightcone()
+        lc.id = self._lc["id"].data_ptr()
+        lc.a = self._lc["a"].data_ptr()
+        for d in range(3):
+            lc.x[d] = self._lc["x"][d].data_ptr()
+            lc.p[d] = self._lc["p"][d].data_ptr()
+        lc.capacity = capacity
+        self._check(self.lib.sdpm_set_lightcone(self.ctx, ctypes.byref(lc)))
+
+    def lightcone_count(self) -> int:
+        cnt = ctypes.c_int64()
+        self._check(self.lib.sdpm_lightcone_count(self.ctx, ctypes.byref(cnt)))
+        return cnt.value
+
+    def lightcone_records(self):
+        """(ids, a, x (n, 3), p (n, 3)) of the records written so far (host)."""
+        n = self.lightcone_count()
+        self.torch.cuda.synchronize(self.device)
+        lc = self._lc
+        return (lc["id"][:n].cpu().numpy().view(np.uint32).copy(), lc["a"][:n].cpu().numpy().copy(),
+                lc["x"][:, :n].T.cpu().numpy().copy(), lc["p"][:, :n].T.cpu().numpy().copy())
 
     # -- learned warm start and solve recording
     def set_warmstart_weights(self, params):

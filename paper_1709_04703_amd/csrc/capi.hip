@@ -47,6 +47,10 @@ struct sdpm_ctx {
   // residual reduction per outer iteration of the last solve (geometric
   // mean), used to run ahead of the host without a sync per iteration
   double rho_est = 0.1;
+  // lightcone output
+  sdpm_lightcone lc{};
+  bool lc_on = false;
+  int64_t lc_count = 0;
   // solve recording
   float* rec_buf = nullptr;
   int64_t rec_max = 0, rec_count = 0;
@@ -549,9 +553,20 @@ int deposit(sdpm_ctx* c, double drift_coef, int drift) {
 
 // Lightcone radius r: eliminate outside particles (stable partition) and
 // update the active box.  `known_removed` < 0: count on the device first.
+// Lightcone records of one removal: light = c dtau (0: record at u = 0),
+// disp = dtau / a1, a1 the scale factor at the end of the removal, da the step.
+struct LcStep {
+  double light, disp, a1, da;
+};
+
+// Removes the active particles outside radius r (stable partition), records
+// them on the lightcone output when lcs != nullptr and it is enabled, and
+// updates the active box.  Returns SDPM_EFULL (after all of that) when the
+// lightcone output overflowed.
 int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed,
-                uint32_t* removed_ids) {
+                uint32_t* removed_ids, const LcStep* lcs = nullptr) {
   *n_removed = 0;
+  int full = SDPM_OK;
   if (!c->cfg.shrink) return SDPM_OK;
   const int64_t n = c->n_active;
   const double r2 = r * r;
@@ -569,6 +584,25 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
     if (removed_ids && *n_removed > 0)
       HIP_TRY(c, hipMemcpyAsync(removed_ids, c->parts.id + kept, *n_removed * sizeof(uint32_t),
                                 hipMemcpyDeviceToDevice, c->st));
+    if (lcs && c->lc_on && *n_removed > 0) {
+      const int64_t room = std::max<int64_t>(c->lc.capacity - c->lc_count, 0);
+      const int64_t cnt = std::min(*n_removed, room);
+      LcArgs out;
+      out.id = c->lc.id;
+      out.a = c->lc.a;
+      for (int d = 0; d < 3; ++d) {
+        out.x[d] = c->lc.x[d];
+        out.p[d] = c->lc.p[d];
+      }
+      if (c->cfg.precision == SDPM_MIXED)
+        launch_lightcone<float>(pa, kept, cnt, c->cfg.x_obs, r, lcs->light, lcs->disp, lcs->a1,
+                                lcs->da, out, c->lc_count, c->st);
+      else
+        launch_lightcone<double>(pa, kept, cnt, c->cfg.x_obs, r, lcs->light, lcs->disp, lcs->a1,
+                                 lcs->da, out, c->lc_count, c->st);
+      c->lc_count += cnt;
+      if (cnt < *n_removed) full = SDPM_EFULL;
+    }
     c->n_active = kept;
   }
   Box nb;
@@ -588,6 +622,8 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
       clear_all_levels(c);
     }
   }
+  if (full) return fail(c, SDPM_EFULL, "lightcone output full at %lld records; later records dropped",
+                        (long long)c->lc_count);
   return SDPM_OK;
 }
 
@@ -795,8 +831,10 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   sdpm_step_stats st{};
   int64_t removed = 0;
   const double r = lightcone_radius(a, c->cfg.omega_m, c->cfg.omega_l, c->cfg.c_light);
-  rc = shrink_impl(c, r, -1, &removed, nullptr);
-  if (rc) return rc;
+  const LcStep at_a{0.0, 0.0, a, 0.0};
+  rc = shrink_impl(c, r, -1, &removed, nullptr, &at_a);
+  const int full = rc == SDPM_EFULL ? rc : SDPM_OK;
+  if (rc && !full) return rc;
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, full_box(c->cfg.ng), 0ull, c->st);
   deposit(c, 0.0, 0);
@@ -812,7 +850,8 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   st.r_lc = r;
   fill_state(c, &st);
   if (out) *out = st;
-  return rc ? rc : src;
+  if (rc) return rc;
+  return src ? src : full;
 }
 
 int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
@@ -878,9 +917,15 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   const int ferr = flags_error(c);
   // lightcone at t + dt: eliminate particles and cells  (last row)
   int64_t removed = 0;
+  int full = SDPM_OK;
   if (!ferr) {
-    rc = shrink_impl(c, sc.r_lc_end, removal ? (int64_t)host_removed(c) : 0, &removed, nullptr);
-    if (rc) return rc;
+    const LcStep lcs{g.c_light * sc.dtau, sc.dtau / (a + da), a + da, da};
+    rc = shrink_impl(c, sc.r_lc_end, removal ? (int64_t)host_removed(c) : 0, &removed, nullptr,
+                     &lcs);
+    if (rc == SDPM_EFULL)
+      full = rc;
+    else if (rc)
+      return rc;
   }
   HIP_TRY(c, hipEventRecord(c->ev[6], c->st));
   HIP_TRY(c, hipEventSynchronize(c->ev[6]));
@@ -908,7 +953,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   if (out) *out = st;
   if (ferr) return ferr;
   if (src1) return src1;
-  return src2;
+  return src2 ? src2 : full;
 }
 
 int sdpm_shrink_radius(sdpm_ctx* c, double r, int64_t* n_removed, uint32_t* removed_ids_dev) {
@@ -927,9 +972,43 @@ int sdpm_shrink_radius(sdpm_ctx* c, double r, int64_t* n_removed, uint32_t* remo
 
 int sdpm_shrink(sdpm_ctx* c, double a, int64_t* n_removed, uint32_t* removed_ids_dev) {
   if (!c) return SDPM_EINVAL;
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
   if (!(a > 0.0) || a > 1.0) return fail(c, SDPM_EINVAL, "a must be in (0, 1]");
-  return sdpm_shrink_radius(c, lightcone_radius(a, c->cfg.omega_m, c->cfg.omega_l, c->cfg.c_light),
-                            n_removed, removed_ids_dev);
+  int64_t nr = 0;
+  const LcStep at_a{0.0, 0.0, a, 0.0};
+  rc = shrink_impl(c, lightcone_radius(a, c->cfg.omega_m, c->cfg.omega_l, c->cfg.c_light), -1, &nr,
+                   removed_ids_dev, &at_a);
+  if (rc && rc != SDPM_EFULL) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  if (n_removed) *n_removed = nr;
+  return rc;
+}
+
+int sdpm_set_lightcone(sdpm_ctx* c, const sdpm_lightcone* out) {
+  if (!c) return SDPM_EINVAL;
+  if (!out) {
+    c->lc_on = false;
+    c->lc = sdpm_lightcone{};
+    c->lc_count = 0;
+    return SDPM_OK;
+  }
+  if (out->capacity < 0 || (out->capacity > 0 && (!out->id || !out->a || !out->x[0] || !out->x[1] ||
+                                                  !out->x[2] || !out->p[0] || !out->p[1] ||
+                                                  !out->p[2])))
+    return fail(c, SDPM_EINVAL, "lightcone output: null array or negative capacity");
+  c->lc = *out;
+  c->lc_on = true;
+  c->lc_count = 0;
+  return SDPM_OK;
+}
+
+int sdpm_lightcone_count(sdpm_ctx* c, int64_t* count) {
+  if (!c || !count) return SDPM_EINVAL;
+  *count = c->lc_count;
+  return SDPM_OK;
 }
 
 int sdpm_get_state(sdpm_ctx* c, sdpm_step_stats* out) {

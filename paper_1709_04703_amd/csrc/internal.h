@@ -138,6 +138,18 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
 // on the cells of box b.
 void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
                        hipStream_t st);
+// Lightcone records of particles [first, first + count) (see sdpm.h): light
+// = c dtau, disp = dtau / a1; written at out index out_first + q.
+struct LcArgs {
+  uint32_t* id;
+  double* a;
+  double* x[3];
+  double* p[3];
+};
+template <typename PT>
+void launch_lightcone(const ParticleArgs& pa, int64_t first, int64_t count, const double* x_obs,
+                      double r1, double light, double disp, double a1, double da, const LcArgs& out,
+                      int64_t out_first, hipStream_t st);
 // With g3 != nullptr the force is interpolated from that mesh (made by
 // launch_force_mesh), else from phi directly (FP64 differences).
 template <typename PT>
@@ -208,7 +220,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
-  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH,
+  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

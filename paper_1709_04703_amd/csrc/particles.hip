@@ -327,6 +327,43 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
   }
 }
 
+// Lightcone crossing of removed particles: the root u in [0, 1] of
+// A u^2 + B u + C = 0 with A = w.w - L^2, B = -2 (d.w + r L), C = d.d - r^2
+// (d = x1 - x_obs, w = p1 dtau / a1, L = c dtau): |d - u w| = r + u L.  For
+// |w| < L (A < 0) and C > 0 there is one positive root, 2 C / (-B + sqrt(D)),
+// the cancellation-free form.
+template <typename PT>
+__global__ void __launch_bounds__(256)
+k_lightcone(ParticleArgs pa, int64_t first, int64_t count, double o0, double o1, double o2,
+            double r, double light, double disp, double a1, double da, LcArgs out,
+            int64_t out_first) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= count) return;
+  const int64_t i = first + q;
+  const double o[3] = {o0, o1, o2};
+  double d[3], w[3], p[3];
+  for (int k = 0; k < 3; ++k) {
+    p[k] = (double)((const PT*)pa.p[k])[i];
+    d[k] = pa.x[k][i] - o[k];
+    w[k] = p[k] * disp;
+  }
+  const double A = (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - light * light;
+  const double B = -2.0 * ((d[0] * w[0] + d[1] * w[1] + d[2] * w[2]) + r * light);
+  const double C = (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - r * r;
+  double u = 0.0;
+  if (C > 0.0 && light > 0.0) {
+    const double den = -B + sqrt(fmax(B * B - 4.0 * A * C, 0.0));
+    u = den > 0.0 ? fmin(2.0 * C / den, 1.0) : 1.0;
+  }
+  const int64_t j = out_first + q;
+  out.id[j] = pa.id[i];
+  out.a[j] = a1 - u * da;
+  for (int k = 0; k < 3; ++k) {
+    out.x[k][j] = pa.x[k][i] - u * w[k];
+    out.p[k][j] = p[k];
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_interp_force(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, double inv2h,
                double* __restrict__ g0, double* __restrict__ g1, double* __restrict__ g2,
@@ -522,6 +559,24 @@ void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMa
                      inv2h, g0, g1, g2, flags);
   prof_end(st, K_INTERP_FORCE, 48.0 * pa.n + 8.0 * box_cells(mm.active));
 }
+
+template <typename PT>
+void launch_lightcone(const ParticleArgs& pa, int64_t first, int64_t count, const double* x_obs,
+                      double r1, double light, double disp, double a1, double da, const LcArgs& out,
+                      int64_t out_first, hipStream_t st) {
+  if (count <= 0) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_lightcone<PT>, dim3(grid_for(count, 256)), dim3(256), 0, st, pa, first, count,
+                     x_obs[0], x_obs[1], x_obs[2], r1, light, disp, a1, da, out, out_first);
+  // particle read (x, p, id) and record written (id, a, x, p)
+  prof_end(st, K_LIGHTCONE, (24.0 + 3.0 * sizeof(PT) + 4.0 + 4.0 + 8.0 + 48.0) * count);
+}
+template void launch_lightcone<float>(const ParticleArgs&, int64_t, int64_t, const double*, double,
+                                      double, double, double, double, const LcArgs&, int64_t,
+                                      hipStream_t);
+template void launch_lightcone<double>(const ParticleArgs&, int64_t, int64_t, const double*, double,
+                                       double, double, double, double, const LcArgs&, int64_t,
+                                       hipStream_t);
 
 template <typename PT>
 void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
