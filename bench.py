@@ -16,6 +16,9 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
   learned_always: mixed, with the conv-net guess tried before every solve.
 The net is trained once before the timed regions, on the GPU, on solves
 recorded from 128^3 runs of the same schedule with other seeds.
+The shrinking phase of the same run (steps 160-164 by default: lightcone
+removal, the frozen-exterior box and the lightcone output all active) is
+timed separately and reported as shrink_phase.
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -45,7 +48,7 @@ def log(msg):
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
 # Valid only for the kernel source it was measured on.
-MEASURED_TRAFFIC = {"smooth_color": 198.7e6}
+MEASURED_TRAFFIC = {"smooth_color": 197.3e6}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
@@ -175,6 +178,57 @@ def copy_bandwidth(torch, mib=2048, reps=5):
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def shrink_phase(P, torch, ics, args):
+    """The shrinking phase of the same run: steps 0 .. shrink_from - 1 untimed,
+    then shrink_steps steps timed with lightcone removal, the frozen-exterior
+    box and the lightcone output on (mixed precision)."""
+    x, p, ids = ics
+    n = x.shape[0]
+    cfg = P.config_default(args.ng, args.box, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED,
+                           n_initial=n, sort_every=args.sort_every)
+    sim = P.Simulation(cfg, n)
+    sim.bind(x, p, ids)
+    sim.set_lightcone(n)
+    a0 = 1.0 / (1.0 + args.z_init)
+    edges = np.linspace(a0, 1.0, args.schedule + 1)
+    sim.init_potential(a0)
+    for s in range(args.shrink_from):
+        sim.step(edges[s], edges[s + 1] - edges[s])
+    n0, rec0 = sim.n_active, sim.lightcone_count()
+    st0 = sim.state()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates, removed = 0, 0
+    for s in range(args.shrink_from, args.shrink_from + args.shrink_steps):
+        n_act = sim.n_active
+        st = sim.step(edges[s], edges[s + 1] - edges[s])
+        updates += n_act
+        removed += st["n_removed"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = sim.profile_read()
+    out = {
+        "steps": f"{args.shrink_from}..{args.shrink_from + args.shrink_steps - 1}",
+        "z": [round(1.0 / edges[args.shrink_from] - 1.0, 3),
+              round(1.0 / edges[args.shrink_from + args.shrink_steps] - 1.0, 3)],
+        "active_fraction": [round(n0 / n, 4), round(sim.n_active / n, 4)],
+        "active_box_cells": int(np.prod([h - l + 1 for l, h in zip(st0["lo"], st0["hi"])])),
+        "periodic": int(st0["periodic"]),
+        "ms_per_step": 1e3 * dt / args.shrink_steps,
+        "particle_updates_per_s": updates / dt,
+        "removed": removed, "lightcone_records": sim.lightcone_count() - rec0,
+        "kernel_ms_per_step": {k: round(v["ms"] / args.shrink_steps, 3) for k, v in
+                               sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:10]
+                               if v["launches"]},
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    log(f"shrink phase: {out['ms_per_step']:.1f} ms/step, active {out['active_fraction']}")
+    return out
+
+
 def cpu_baseline(ics, args):
     """The oracle as it stands: one full-size mesh solve pair + force mesh at
     ng^3, and the particle phases on a sample, scaled to one full step."""
@@ -241,6 +295,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--shrink-from", type=int, default=160)
+    ap.add_argument("--shrink-steps", type=int, default=5)
+    ap.add_argument("--no-shrink-phase", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this size (a "
                          "known-size kernel that scales hardware byte counters)")
@@ -316,6 +373,9 @@ def main():
             learned_roofline = kernel_roofline("conv3d_mfma", lp["conv3d_mfma"])
             learned_roofline["mode"] = lmode
     copy_gbs = copy_bandwidth(torch)
+    shrink = None
+    if not args.no_shrink_phase and args.shrink_from + args.shrink_steps <= args.schedule:
+        shrink = shrink_phase(P, torch, ics, args)
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -349,6 +409,7 @@ def main():
         "modes": modes,
         "roofline": roofline,
         "hbm_copy_GBps": copy_gbs,
+        "shrink_phase": shrink,
         "roofline_learned": learned_roofline,
         "net": net_info,
         "cpu_baseline": cpu,
