@@ -10,12 +10,15 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
   plain:   FP64 V-cycles warm-started from the previous potential, FP64 momenta;
   mixed:   FP32 V(2,2) cycles (6 levels) inside FP64 defect correction, FP32
            momenta, previous-potential warm start;
-  learned: mixed, with the conv-net warm start, gated: the library keeps the
+  extrap:  mixed, each solve started from the potential plus the change the
+           same solve made in the previous step (linear extrapolation in time);
+  learned: extrap, plus the conv-net warm start, gated: the library keeps the
            net only while the outer iterations it saves outweigh its measured
            cost (the headline value);
-  learned_always: mixed, with the conv-net guess tried before every solve.
+  learned_always: extrap, plus the conv-net guess tried before every solve.
 The net is trained once before the timed regions, on the GPU, on solves
-recorded from 128^3 runs of the same schedule with other seeds.
+recorded (with the extrapolated start) from 128^3 runs of the same schedule
+with other seeds.
 The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
@@ -96,7 +99,8 @@ def train_net(P, torch, args):
     ics = [zeldovich_ics(args.train_ng, args.box, a0, s) for s in seeds]
     per_run = max(1, args.train_pairs // (2 * len(seeds)))
     buf, kap, rms_r, rms_phi = record_pairs(ics, args.train_ng, args.box, a0, args.schedule,
-                                            args.train_pairs, steps_per_run=per_run)
+                                            args.train_pairs, steps_per_run=per_run,
+                                            warm_start=P.SDPM_WS_EXTRAP)
     del ics
     t1 = time.perf_counter()
     tr = Trainer(args.train_ng, init_params(0), lr=args.train_lr)
@@ -116,14 +120,15 @@ def train_net(P, torch, args):
     return w, info
 
 
-def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True):
+def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, extrap=False):
     x, p, ids = ics
     ng, box = args.ng, args.box
     n = x.shape[0]
     cfg = P.config_default(ng, box, c_grav=-1.0, shrink=1, precision=precision, n_initial=n,
                            sort_every=args.sort_every,
-                           warm_start=P.SDPM_WS_PREV if weights is None else
-                           P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
+                           warm_start=(P.SDPM_WS_PREV if weights is None else
+                                       P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
+                           | (P.SDPM_WS_EXTRAP if extrap else 0))
     sim = P.Simulation(cfg, n)
     if weights is not None:
         sim.set_warmstart_weights(weights)
@@ -286,7 +291,7 @@ def main():
     ap.add_argument("--z-init", type=float, default=49.0)
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
-    ap.add_argument("--modes", default="plain,mixed,learned,learned_always")
+    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always")
     ap.add_argument("--train-ng", type=int, default=128)
     ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
     ap.add_argument("--train-pairs", type=int, default=400)
@@ -335,11 +340,12 @@ def main():
                 net_weights, net_info = train_net(P, torch, args)
             weights = net_weights
         r = run_mode(P, torch, ics, args, prec, profile=True, weights=weights,
-                     gated=(mode != "learned_always"))
+                     gated=(mode != "learned_always"), extrap=(mode != "plain" and mode != "mixed"))
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
-    head_mode = next(m for m in ("learned", "mixed", "plain", "learned_always") if m in results)
+    head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always")
+                     if m in results)
     head = results[head_mode]
     value = head["updates"] / head["seconds"]
     modes = {}
@@ -394,7 +400,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
                   "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
-                  "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net"}[head_mode],
+                  "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
+                  "extrap": "f32 V-cycles in f64 defect correction"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "

@@ -59,9 +59,17 @@ enum { SDPM_MIXED = 0, SDPM_PLAIN_FP64 = 1 };      /* sdpm_config.precision  */
  * half-step) the context times the guess and one outer iteration with HIP
  * events and estimates the outer iterations an accepted guess saved (its
  * residual reduction in units of the solve's measured convergence factor);
- * when the saving is below the cost, the next 8, 16, 32, ... 256 solves of
- * that kind skip the net (the count doubles at each failed try).          */
+ * when the saving is below the cost, the next B * max(1, cost / saving)
+ * solves of that kind skip the net, B = 8, 16, 32, ... (doubling at each
+ * failed try), at most 256.                                                */
 enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1, SDPM_WS_LEARNED_GATED = 2 };
+/* Flag OR-ed into warm_start: start each solve of sdpm_step from the
+ * potential plus the change that the same solve (first or second field
+ * half-step) made in the previous step, scaled by the ratio of the conformal
+ * steps (linear extrapolation in time; the first step of a run starts from
+ * the previous potential).  Costs two passes over the active box per solve
+ * (an FP32 copy of the start, then the change) and three FP32 meshes.      */
+enum { SDPM_WS_EXTRAP = 4 };
 
 typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
 
@@ -87,7 +95,7 @@ typedef struct sdpm_config {
   int32_t precision;     /* SDPM_MIXED: FP32 V-cycles in FP64 defect
                             correction, FP32 momenta; SDPM_PLAIN_FP64: FP64
                             V-cycles and momenta                               */
-  int32_t warm_start;    /* SDPM_WS_PREV, SDPM_WS_LEARNED(_GATED)              */
+  int32_t warm_start;    /* SDPM_WS_PREV, SDPM_WS_LEARNED(_GATED), | EXTRAP    */
   int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
   int32_t sort_every;    /* Morton re-sort before every k-th step (0: never)   */
   int32_t sort_shift;    /* sort key: cells grouped in blocks of 2^shift       */

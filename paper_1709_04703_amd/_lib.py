@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libsdpm.so")
 SDPM_OK, SDPM_EINVAL, SDPM_ENOMEM, SDPM_EHIP = 0, -1, -2, -3
 SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6, -7, -8
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
-SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED = 0, 1, 2
+SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED, SDPM_WS_EXTRAP = 0, 1, 2, 4
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",

@@ -44,6 +44,13 @@ struct sdpm_ctx {
   double gate_net_ms = 0.0, gate_cycle_ms = 0.0;
   int gate_skip[2] = {0, 0};
   int gate_backoff[2] = {kGateProbe, kGateProbe};
+  // extrapolated start (SDPM_WS_EXTRAP): per solve kind the FP32 change of
+  // the last solve and its conformal step; the FP32 copy of a solve's start
+  float* ex_d[2] = {nullptr, nullptr};
+  float* ex_start = nullptr;
+  bool ex_have[2] = {false, false};
+  double ex_dtau[2] = {0.0, 0.0};
+  double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
   // residual reduction per outer iteration of the last solve (geometric
   // mean), used to run ahead of the host without a sync per iteration
   double rho_est = 0.1;
@@ -136,10 +143,11 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (!(c->tol > 0.0)) return snprintf(msg, len, "tol must be > 0"), SDPM_EINVAL;
   if (c->precision != SDPM_MIXED && c->precision != SDPM_PLAIN_FP64)
     return snprintf(msg, len, "unknown precision %d", c->precision), SDPM_EINVAL;
-  if (c->warm_start != SDPM_WS_PREV && c->warm_start != SDPM_WS_LEARNED &&
-      c->warm_start != SDPM_WS_LEARNED_GATED)
+  const int ws = c->warm_start & ~SDPM_WS_EXTRAP;
+  if (c->warm_start < 0 ||
+      (ws != SDPM_WS_PREV && ws != SDPM_WS_LEARNED && ws != SDPM_WS_LEARNED_GATED))
     return snprintf(msg, len, "unknown warm_start %d", c->warm_start), SDPM_EINVAL;
-  if (c->warm_start != SDPM_WS_PREV && !net_size_ok(c->ng))
+  if (ws != SDPM_WS_PREV && !net_size_ok(c->ng))
     return snprintf(msg, len, "the learned warm start needs ng >= 16"), SDPM_EINVAL;
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
   if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
@@ -188,7 +196,18 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   // FP32 force mesh of the mixed-precision step (3 values per cell)
   float* g3 = c.precision == SDPM_MIXED ? (float*)take((size_t)c.ng * c.ng * c.ng * 3 * sizeof(float))
                                         : nullptr;
-  if (c.warm_start != SDPM_WS_PREV) {
+  if (c.warm_start & SDPM_WS_EXTRAP) {
+    const size_t V = (size_t)c.ng * c.ng * c.ng;
+    float* d0 = (float*)take(V * sizeof(float));
+    float* d1 = (float*)take(V * sizeof(float));
+    float* s0 = (float*)take(V * sizeof(float));
+    if (ctx) {
+      ctx->ex_d[0] = d0;
+      ctx->ex_d[1] = d1;
+      ctx->ex_start = s0;
+    }
+  }
+  if ((c.warm_start & ~SDPM_WS_EXTRAP) != SDPM_WS_PREV) {
     const size_t V = (size_t)c.ng * c.ng * c.ng;
     float* prm = (float*)take(kNetParams * sizeof(float));
     uint16_t* a0 = (uint16_t*)take(V * 16 * sizeof(uint16_t));
@@ -333,6 +352,14 @@ int sync_scalars(sdpm_ctx* c, int ndouble) {
   return SDPM_OK;
 }
 
+// The conformal step of the sdpm_step in progress, for the extrapolated
+// solve start; 0 outside a step.
+struct StepDtau {
+  sdpm_ctx* c;
+  StepDtau(sdpm_ctx* ctx, double dtau) : c(ctx) { c->cur_dtau = dtau; }
+  ~StepDtau() { c->cur_dtau = 0.0; }
+};
+
 // Makes the context's profiler the current one for the duration of a call.
 struct ProfScope {
   explicit ProfScope(sdpm_ctx* c) { g_prof = c ? &c->prof : nullptr; }
@@ -387,6 +414,14 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   const sdpm_config& g = c->cfg;
   const Box& b = c->lv[0].box;
   int nb = 0;
+  // extrapolated start (steps only): phi += (dtau / dtau_prev) (change of the
+  // same solve kind in the previous step); the rhs already holds phi_old
+  const bool extrap = (g.warm_start & SDPM_WS_EXTRAP) && c->cur_dtau > 0.0 && c->ex_start;
+  if (extrap) {
+    const bool apply = c->ex_have[slot] && c->ex_dtau[slot] > 0.0;
+    launch_extrap_begin(c->fields.phi, c->ex_d[slot], apply ? c->cur_dtau / c->ex_dtau[slot] : 0.0,
+                        apply ? 1 : 0, c->ex_start, g.ng, b, c->st);
+  }
   launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial, &nb,
                      c->st);
   launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
@@ -402,7 +437,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   const bool recording = c->rec_buf && c->rec_count < c->rec_max;
   float* rec = recording ? c->rec_buf + (size_t)c->rec_count * 3 * (size_t)g.ng * g.ng * g.ng : nullptr;
   double rms_phi = 0.0;
-  const bool gated = g.warm_start == SDPM_WS_LEARNED_GATED;
+  const bool gated = (g.warm_start & ~SDPM_WS_EXTRAP) == SDPM_WS_LEARNED_GATED;
   bool try_net = c->net_ready && rn > thresh && rn > 0.0;
   if (try_net && gated && c->gate_skip[slot] > 0) {
     --c->gate_skip[slot];
@@ -498,7 +533,8 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     // outer iterations the guess saved: its residual reduction measured in
     // this solve's own convergence factor per iteration; keep the net for
     // this sub-step kind while that exceeds its cost in iterations, else skip
-    // it for a doubling number of solves
+    // it for a number of solves that doubles with every failed try and scales
+    // with how far the net is from paying (cost / saving)
     double saved = 0.0;
     if (so->warm) {
       if (it == 0) {
@@ -513,7 +549,9 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
       c->gate_backoff[slot] = kGateProbe;
       c->gate_skip[slot] = 0;
     } else {
-      c->gate_skip[slot] = c->gate_backoff[slot];
+      const double ratio = std::min(cost / std::max(saved, 0.25), (double)kGateProbeMax);
+      c->gate_skip[slot] =
+          std::min((int)std::ceil(c->gate_backoff[slot] * std::max(ratio, 1.0)), kGateProbeMax);
       c->gate_backoff[slot] = std::min(2 * c->gate_backoff[slot], kGateProbeMax);
     }
   }
@@ -527,6 +565,11 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     rc = sync_scalars(c, 3);
     if (rc) return rc;
     launch_add_const(c->fields.phi, g.ng, b, -c->hpin[2] / (double)box_cells(b), c->st);
+  }
+  if (extrap) {
+    launch_extrap_end(c->fields.phi, c->ex_start, c->ex_d[slot], g.ng, b, c->st);
+    c->ex_have[slot] = true;
+    c->ex_dtau[slot] = c->cur_dtau;
   }
   if (!(rn <= thresh))
     return fail(c, SDPM_ENOCONV, "multigrid reached relative residual %.3e > tol %.1e after %d iterations",
@@ -879,6 +922,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   // Phi from t to t + dt/2                              (row 3)
   assemble_rhs(c, sc.s_half, sc.kappa1_h2);
   HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
+  const StepDtau step_dtau(c, sc.dtau);
   SolveOut s1;
   const int src1 = solve(c, sc.kappa1_h2, 0, &s1);
   if (src1 && src1 != SDPM_ENOCONV) return src1;

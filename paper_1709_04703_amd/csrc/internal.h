@@ -197,6 +197,12 @@ template <typename T>
 void launch_residual_guess(const double* phi, const float* d, double scale, const double* rhs,
                            T* r_out, int n, const Box& b, double kappa, double* partial,
                            int* nblocks, hipStream_t st);
+// Extrapolated start of a solve (start = (float) phi, then phi += scale d
+// when apply) and, after it, the change it made (d = phi - start).
+void launch_extrap_begin(double* phi, const float* d, double scale, int apply, float* start, int n,
+                         const Box& b, hipStream_t st);
+void launch_extrap_end(const double* phi, const float* start, float* d, int n, const Box& b,
+                       hipStream_t st);
 void launch_apply_guess(double* phi, const float* d, double scale, int n, const Box& b,
                         hipStream_t st);
 void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,
@@ -220,7 +226,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
-  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
+  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE, K_EXTRAP,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

@@ -691,6 +691,40 @@ k_apply_guess(double* __restrict__ phi, const float* __restrict__ d, double scal
   }
 }
 
+// Extrapolated start of a solve: start = (float) phi; phi += scale d.
+__global__ void __launch_bounds__(256)
+k_extrap_begin(double* __restrict__ phi, const float* __restrict__ d, double scale, int apply,
+               float* __restrict__ start, int n, Box b) {
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  for (int k = k0; k <= k1; ++k) {
+    const int64_t c = lin(i, j, k, n);
+    const double v = phi[c];
+    start[c] = (float)v;
+    if (apply) phi[c] = v + scale * (double)d[c];
+  }
+}
+
+// The change the solve made: d = phi - start.
+__global__ void __launch_bounds__(256)
+k_extrap_end(const double* __restrict__ phi, const float* __restrict__ start, float* __restrict__ d,
+             int n, Box b) {
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  for (int k = k0; k <= k1; ++k) {
+    const int64_t c = lin(i, j, k, n);
+    d[c] = (float)(phi[c] - (double)start[c]);
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_sum_sq(const double* __restrict__ phi, int n, Box b, double* __restrict__ partial) {
   __shared__ double sh[4];
@@ -843,6 +877,21 @@ void launch_apply_guess(double* phi, const float* d, double scale, int n, const 
   prof_begin(st);
   hipLaunchKernelGGL(k_apply_guess, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, n, b);
   prof_end(st, K_NET_MISC, 20.0 * box_cells(b));
+}
+
+void launch_extrap_begin(double* phi, const float* d, double scale, int apply, float* start, int n,
+                         const Box& b, hipStream_t st) {
+  prof_begin(st);
+  hipLaunchKernelGGL(k_extrap_begin, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, apply,
+                     start, n, b);
+  prof_end(st, K_EXTRAP, (apply ? 24.0 : 12.0) * box_cells(b));
+}
+
+void launch_extrap_end(const double* phi, const float* start, float* d, int n, const Box& b,
+                       hipStream_t st) {
+  prof_begin(st);
+  hipLaunchKernelGGL(k_extrap_end, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, start, d, n, b);
+  prof_end(st, K_EXTRAP, 16.0 * box_cells(b));
 }
 
 void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,

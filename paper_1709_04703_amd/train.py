@@ -18,10 +18,12 @@ from . import _lib as L
 
 def record_pairs(ics_list, ng: int, box: float, a0: float, nsteps: int, max_pairs: int,
                  precision: int = L.SDPM_MIXED, c_grav: float = -1.0, device: str = "cuda:0",
-                 steps_per_run: int | None = None):
+                 steps_per_run: int | None = None, warm_start: int = L.SDPM_WS_PREV):
     """Run the given initial conditions (list of (x, p, ids)) on the schedule
     of nsteps steps uniform in a from a0 to 1, each for at most steps_per_run
-    steps of its periodic phase, and record up to max_pairs solves.  Returns
+    steps of its periodic phase, and record up to max_pairs solves (each from
+    the start that warm_start gives: the previous potential, or with
+    SDPM_WS_EXTRAP its extrapolation).  Returns
     (buf [P, 3, ng^3] float32 device tensor, kappa h^2, rms_r, rms_phi arrays)."""
     import torch
 
@@ -33,7 +35,7 @@ def record_pairs(ics_list, ng: int, box: float, a0: float, nsteps: int, max_pair
         if got >= max_pairs:
             break
         cfg = L.config_default(ng, box, c_grav=c_grav, shrink=1, precision=precision,
-                               n_initial=x.shape[0])
+                               n_initial=x.shape[0], warm_start=warm_start)
         sim = L.Simulation(cfg, x.shape[0], device=device)
         sim.bind(x, p, ids)
         sim.init_potential(a0)

@@ -154,3 +154,33 @@ def test_step_argument_errors():
     with pytest.raises(P.SdpmError, match="EINVAL"):
         sim.step(0.5, -0.1)
     sim.close()
+
+
+def test_extrapolated_start_same_solution_fewer_iterations():
+    """SDPM_WS_EXTRAP: every solve still reaches tol, the run ends in the same
+    state as with the previous-potential start (to the solve tolerance), and
+    the extrapolated start needs fewer outer iterations."""
+    import paper_1709_04703_amd as P
+    ng, box, a0, nsteps = 64, 2000.0, 1.0 / 50.0, 40
+    x, p, ids = zeldovich_ics(ng, box, a0, 21)
+    edges = np.linspace(a0, 1.0, nsteps + 1)
+    out = {}
+    for name, ws in (("prev", P.SDPM_WS_PREV), ("extrap", P.SDPM_WS_EXTRAP)):
+        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3, warm_start=ws)
+        sim = make_sim(cfg, ng**3)
+        sim.bind(x, p, ids)
+        sim.init_potential(a0)
+        iters = []
+        for s in range(12):
+            st = sim.step(edges[s], edges[s + 1] - edges[s])
+            assert max(st["res"]) <= cfg.tol
+            iters.append(st["outer_iters"])
+        gx, gp, gid = sim.particles()
+        out[name] = (iters, sim.phi_numpy().copy(), _by_id(gx, gid))
+        sim.close()
+        log(f"  {name}: outer iterations {iters}")
+    tot = {k: sum(sum(i) for i in v[0]) for k, v in out.items()}
+    assert tot["extrap"] < tot["prev"]
+    assert rel_rms(out["extrap"][1], out["prev"][1]) < 1e-5
+    dx = periodic_delta(out["extrap"][2], out["prev"][2], box)
+    assert np.abs(dx).max() < 1e-5 * box / ng
