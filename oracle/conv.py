@@ -120,6 +120,54 @@ def init_params(seed: int, scale: float = 1.0):
     return params
 
 
+def frozen_mask() -> np.ndarray:
+    """Parameters the training keeps at zero, in flat order: input channels
+    >= N_INPUTS of layer 0 and output channels >= 1 (weights and bias) of the
+    last layer."""
+    out = []
+    for l in range(N_LAYERS):
+        w = np.zeros((27, C, C), dtype=bool)
+        b = np.zeros(C, dtype=bool)
+        if l == 0:
+            w[:, N_INPUTS:, :] = True
+        if l == N_LAYERS - 1:
+            w[:, :, 1:] = True
+            b[1:] = True
+        out.append(np.concatenate([w.ravel(), b]))
+    return np.concatenate(out)
+
+
+def adam(theta, grad, m1, m2, step: int, lr: float, b1: float = 0.9, b2: float = 0.999,
+         eps: float = 1e-8, frozen=None):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) on flat FP64 vectors:
+    biased first and second moment estimates, bias correction by 1 - b^t,
+    theta -= lr m_hat / (sqrt(v_hat) + eps).  Frozen entries are set to zero
+    and keep their moments.  Returns (theta, m1, m2)."""
+    m1n = b1 * m1 + (1.0 - b1) * grad
+    m2n = b2 * m2 + (1.0 - b2) * grad * grad
+    mh = m1n / (1.0 - b1 ** step)
+    vh = m2n / (1.0 - b2 ** step)
+    th = theta - lr * mh / (np.sqrt(vh) + eps)
+    if frozen is not None:
+        th = np.where(frozen, 0.0, th)
+        m1n = np.where(frozen, m1, m1n)
+        m2n = np.where(frozen, m2, m2n)
+    return th, m1n, m2n
+
+
+def train_step_grads(x0: np.ndarray, params: list, target: np.ndarray, target_scale: float):
+    """Loss mean((out - target_scale target)^2) of the net on input x0 and
+    its gradients as the GPU forms them: BF16 activations and weights, the
+    output gradient 2 (out - t) / V rounded to BF16 and every back-propagated
+    gradient rounded to BF16.  Returns (loss, flat FP64 gradient)."""
+    acts, out = forward(x0, params, round_bf16=True)
+    d = out - target * target_scale
+    g_out = bf16_round(2.0 * d / d.size)
+    grads = backward(acts, params, g_out, round_bf16=True)
+    flat = np.concatenate([np.concatenate([dw.ravel(), db]) for dw, db in grads])
+    return float(np.mean(d * d)), flat
+
+
 def flatten(params: list) -> np.ndarray:
     """FP32 parameter vector in the C ABI order: per layer W (27,16,16) then b (16)."""
     return np.concatenate([np.concatenate([w.ravel(), b]) for w, b in params]).astype(np.float32)

@@ -211,3 +211,61 @@ def test_learned_warm_start_trains_and_falls_back():
     assert 1 <= net_calls["gated"] <= net_calls["learned"]
     assert np.all(res["gated"][2] <= res["gated"][3])
     assert rel_rms(res["gated"][4], res["prev"][4]) < 1e-5
+
+
+def test_train_step_matches_oracle_adam():
+    """One training step (forward, MSE loss, backward through every layer,
+    Adam at step 5 from nonzero moments, so the update depends on the
+    gradient's size, not only its sign) against the oracle's BF16-rounded
+    forward / backward and its Adam (Kingma & Ba 2015): the loss, both moment
+    updates, the parameter change, and the frozen parameters left at zero."""
+    import torch
+    import paper_1709_04703_amd as P
+    from paper_1709_04703_amd.train import init_params
+    n = 16
+    rng = np.random.Generator(np.random.PCG64(21))
+    r32 = rng.normal(size=(n, n, n)).astype(np.float32)
+    phi32 = rng.normal(size=(n, n, n)).astype(np.float32)
+    tgt32 = rng.normal(size=(n, n, n)).astype(np.float32)
+    s_r, s_phi, kap, ts = np.float32(0.7), np.float32(1.3), np.float32(0.2), np.float32(0.5)
+    vec32 = init_params(2)
+    mask = oc.frozen_mask()
+    assert np.all(vec32[mask] == 0.0)
+    # oracle: the prep's FP32 products, rounded to BF16 by forward()
+    x0 = np.zeros((n, n, n, 16))
+    x0[..., 0] = (r32 * s_r).astype(np.float64)
+    x0[..., 1] = (phi32 * s_phi).astype(np.float64)
+    x0[..., 2] = float(kap)
+    loss_o, g = oc.train_step_grads(x0, oc.unflatten(vec32), tgt32.astype(np.float64), float(ts))
+    gr = np.sqrt(np.mean(g[~mask] ** 2))
+    m1 = (rng.normal(size=g.size) * gr).astype(np.float32)
+    m2 = (rng.uniform(0.5, 1.5, size=g.size) * gr * gr).astype(np.float32)
+    m1[mask] = 0.0
+    m2[mask] = 0.0
+    step, lr = 5, 1e-3
+    th_o, m1_o, m2_o = oc.adam(vec32.astype(np.float64), g, m1.astype(np.float64),
+                               m2.astype(np.float64), step, lr, frozen=mask)
+    # GPU
+    act0 = torch.zeros((n**3, 16), dtype=torch.int16, device="cuda")
+    P.net_prep(n, torch.as_tensor(r32).cuda().reshape(-1), torch.as_tensor(phi32).cuda().reshape(-1),
+               float(s_r), float(s_phi), float(kap), act0)
+    th_t = torch.as_tensor(vec32).cuda()
+    m1_t, m2_t = torch.as_tensor(m1).cuda(), torch.as_tensor(m2).cuda()
+    scratch = torch.zeros(P.net_scratch_bytes(n), dtype=torch.uint8, device="cuda")
+    loss_t = torch.zeros(1, dtype=torch.float32, device="cuda")
+    P.net_train_step(n, th_t, m1_t, m2_t, step, lr, act0, torch.as_tensor(tgt32).cuda().reshape(-1),
+                     float(ts), scratch, loss_t)
+    th_g, m1_g, m2_g = (t.cpu().numpy().astype(np.float64) for t in (th_t, m1_t, m2_t))
+    loss_g = float(loss_t.item())
+    live = ~mask
+    g_from_m1 = (m1_g - 0.9 * m1) / 0.1
+    log(f"  loss gpu {loss_g:.6e} oracle {loss_o:.6e}; gradient rel rms "
+        f"{rel_rms(g_from_m1[live], g[live]):.2e}; update rel rms "
+        f"{rel_rms((th_g - vec32)[live], (th_o - vec32)[live]):.2e}")
+    # the two sides round the same FP32 sums to BF16; they differ only where a
+    # sum falls within FP32 accumulation error of a rounding boundary
+    assert abs(loss_g - loss_o) <= 1e-4 * loss_o
+    assert rel_rms(g_from_m1[live], g[live]) < 1e-3
+    assert rel_rms(m2_g[live], m2_o[live]) < 1e-3
+    assert rel_rms((th_g - vec32)[live], (th_o - vec32)[live]) < 1e-3
+    assert np.all(th_g[mask] == 0.0)

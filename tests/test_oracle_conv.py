@@ -85,3 +85,30 @@ def test_flatten_roundtrip():
     back = oc.unflatten(vec)
     for (w, b), (w2, b2) in zip(params, back):
         assert np.allclose(w.astype(np.float32), w2) and np.allclose(b, b2)
+
+
+def test_adam_constant_gradient_closed_form():
+    # with a constant gradient the bias-corrected moments are exactly g and
+    # g^2, so every step moves theta by lr g / (|g| + eps)
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    th, m1, m2 = np.zeros(4), np.zeros(4), np.zeros(4)
+    lr, eps = 1e-2, 1e-8
+    for t in range(1, 6):
+        th, m1, m2 = oc.adam(th, g, m1, m2, t, lr, eps=eps)
+        assert np.allclose(th, -t * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_keeps_frozen_parameters_zero():
+    mask = oc.frozen_mask()
+    assert mask.size == 5 * (27 * 256 + 16)
+    per = 27 * 256 + 16
+    w0 = mask[:27 * 256].reshape(27, 16, 16)
+    assert w0[:, 3:, :].all() and not w0[:, :3, :].any()
+    w4 = mask[4 * per:4 * per + 27 * 256].reshape(27, 16, 16)
+    assert w4[:, :, 1:].all() and not w4[:, :, 0].any()
+    rng = np.random.Generator(np.random.PCG64(0))
+    th = rng.normal(size=mask.size)
+    m1, m2 = rng.normal(size=mask.size), rng.uniform(size=mask.size)
+    th2, m1b, m2b = oc.adam(th, rng.normal(size=mask.size), m1, m2, 3, 1e-3, frozen=mask)
+    assert np.all(th2[mask] == 0.0) and np.array_equal(m1b[mask], m1[mask])
+    assert np.array_equal(m2b[mask], m2[mask])
