@@ -125,7 +125,7 @@ def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, 
     ng, box = args.ng, args.box
     n = x.shape[0]
     cfg = P.config_default(ng, box, c_grav=-1.0, shrink=1, precision=precision, n_initial=n,
-                           sort_every=args.sort_every,
+                           sort_every=args.sort_every, sort_shift=args.sort_shift,
                            warm_start=(P.SDPM_WS_PREV if weights is None else
                                        P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
                            | (P.SDPM_WS_EXTRAP if extrap else 0))
@@ -190,7 +190,7 @@ def shrink_phase(P, torch, ics, args):
     x, p, ids = ics
     n = x.shape[0]
     cfg = P.config_default(args.ng, args.box, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED,
-                           n_initial=n, sort_every=args.sort_every)
+                           n_initial=n, sort_every=args.sort_every, sort_shift=args.sort_shift)
     sim = P.Simulation(cfg, n)
     sim.bind(x, p, ids)
     sim.set_lightcone(n)
@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-shift", type=int, default=4,
+                    help="Morton key of cell blocks of 2^shift cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--shrink-from", type=int, default=160)

@@ -98,7 +98,9 @@ typedef struct sdpm_config {
   int32_t warm_start;    /* SDPM_WS_PREV, SDPM_WS_LEARNED(_GATED), | EXTRAP    */
   int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
   int32_t sort_every;    /* Morton re-sort before every k-th step (0: never)   */
-  int32_t sort_shift;    /* sort key: cells grouped in blocks of 2^shift       */
+  int32_t sort_shift;    /* sort key: Morton order of cell blocks of 2^shift
+                            cells per axis (stable: particles keep their
+                            order inside a block); default 4 for ng >= 64    */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,

@@ -731,7 +731,7 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->warm_start = SDPM_WS_PREV;
   cfg->n_initial = (int64_t)ng * ng * ng;
   cfg->sort_every = 0;
-  cfg->sort_shift = 0;
+  cfg->sort_shift = ng >= 64 ? 4 : 0;   // Morton order of 16^3-cell blocks
   return SDPM_OK;
 }
 

@@ -331,7 +331,12 @@ k_smooth_color(T* __restrict__ e, const T* __restrict__ r, int n, Box b, int col
 // neighbours and r one vector load each.  Vectors start at multiples of 4
 // (the box's first half-row index rounded down; n / 2 is a multiple of 4, so
 // a vector never leaves its row) and cells outside the box are masked.
-// Tiles are 4 TXV half-row entries x 256 / TXV rows x kBoxKz planes.
+// Tiles are 4 TXV half-row entries x 256 / TXV rows x kVecKz planes.
+#ifndef SDPM_VEC_KZ
+#define SDPM_VEC_KZ 4
+#endif
+constexpr int kVecKz = SDPM_VEC_KZ;           // planes per thread of the vector colour kernels
+
 template <typename T, bool FIRST, int TXV>
 __global__ void __launch_bounds__(256)
 k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restrict__ ro, int n,
@@ -344,8 +349,8 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
   const int h0 = hb + (tl.bx * TXV + threadIdx.x) * 4;
   if (j > b.hi[1] || h0 > hhi) return;
   const int m = n - 1, hn = n >> 1;
-  const int k0 = b.lo[2] + tl.bz * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int k0 = b.lo[2] + tl.bz * kVecKz;
+  const int k1 = min(k0 + kVecKz - 1, b.hi[2]);
   const int jp = (j + 1) & m, jm = (j - 1) & m;
 #pragma unroll 2
   for (int k = k0; k <= k1; ++k) {
@@ -401,8 +406,8 @@ k_resid_red_v4(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__
   if (j > b.hi[1] || h0 > hhi) return;
   const int m = n - 1, hn = n >> 1;
   const int64_t oth = half_cells(n);
-  const int k0 = b.lo[2] + tl.bz * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int k0 = b.lo[2] + tl.bz * kVecKz;
+  const int k1 = min(k0 + kVecKz - 1, b.hi[2]);
   const int jp = (j + 1) & m, jm = (j - 1) & m;
   for (int k = k0; k <= k1; ++k) {
     const int p = (j + k) & 1;
@@ -933,13 +938,13 @@ inline dim3 v4_grid(const Box& b, int txv) {
   const int ty = 256 / txv;
   const int gx = ((b.hi[0] >> 1) - ((b.lo[0] >> 1) & ~3) + 4 * txv) / (4 * txv);
   const int gy = (b.hi[1] - b.lo[1] + ty) / ty;
-  const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
+  const int gz = (b.hi[2] - b.lo[2] + kVecKz) / kVecKz;
   return dim3((unsigned)gx * gy * gz);
 }
 
 template <typename T>
-static void smooth_color(T* e, const T* r, const Level& L, int color, bool first, T scale,
-                         T inv_diag, hipStream_t st) {
+static void smooth_color(T* e, const T* r, const Level& L, int level, int color, bool first,
+                         T scale, T inv_diag, hipStream_t st) {
   const Box& b = L.box;
   const int txv = sizeof(T) == 4 ? v4_threads(b) : 0;   // FP64 levels: the scalar kernel is faster
   prof_begin(st);
@@ -983,7 +988,8 @@ static void smooth_color(T* e, const T* r, const Level& L, int color, bool first
   // first (red, zero guess): r + e of the colour; otherwise e of the other
   // colour + r and e of this colour: half the cells each
   const double cells = (double)box_cells(b);
-  prof_end(st, first ? K_SMOOTH_FIRST : K_SMOOTH, (first ? 1.0 : 1.5) * sizeof(T) * cells);
+  prof_end(st, first ? K_SMOOTH_FIRST : level == 0 ? K_SMOOTH : K_SMOOTH_COARSE,
+           (first ? 1.0 : 1.5) * sizeof(T) * cells);
 }
 
 template <typename T>
@@ -1020,8 +1026,8 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     T* e = (T*)L.e;
     const T* r = (const T*)L.r;
     for (int s = 0; s < pre; ++s) {
-      smooth_color<T>(e, r, L, 0, s == 0, scale, inv_diag, st);
-      smooth_color<T>(e, r, L, 1, false, scale, inv_diag, st);
+      smooth_color<T>(e, r, L, l, 0, s == 0, scale, inv_diag, st);
+      smooth_color<T>(e, r, L, l, 1, false, scale, inv_diag, st);
     }
     resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
@@ -1062,8 +1068,8 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     } else {
       // large degenerate Dirichlet box: sweeps through global memory
       for (int s = 0; s < sweeps; ++s) {
-        smooth_color<T>((T*)L.e, (const T*)L.r, L, 0, s == 0, scale, inv_diag, st);
-        smooth_color<T>((T*)L.e, (const T*)L.r, L, 1, false, scale, inv_diag, st);
+        smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 0, s == 0, scale, inv_diag, st);
+        smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 1, false, scale, inv_diag, st);
       }
     }
   }
@@ -1078,8 +1084,8 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
                        L.n, L.box, post > 0 ? 0 : 1);
     prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
     for (int s = 0; s < post; ++s) {
-      smooth_color<T>((T*)L.e, (const T*)L.r, L, 0, false, scale, inv_diag, st);
-      smooth_color<T>((T*)L.e, (const T*)L.r, L, 1, false, scale, inv_diag, st);
+      smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 0, false, scale, inv_diag, st);
+      smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 1, false, scale, inv_diag, st);
     }
   }
   return (const T*)lv[0].e;

@@ -139,9 +139,10 @@ def test_deposit_in_dirichlet_box_and_domain_error():
     sim2.close()
 
 
-def _morton_key(x, ng, box):
-    """Independent Morton code of each particle's cell (bit loop)."""
-    c = np.clip(np.floor(x * (ng / box)), 0, ng - 1).astype(np.int64)
+def _morton_key(x, ng, box, shift=0):
+    """Independent Morton code of each particle's cell block (cells >> shift;
+    bit loop)."""
+    c = np.clip(np.floor(x * (ng / box)), 0, ng - 1).astype(np.int64) >> shift
     key = np.zeros(x.shape[0], dtype=np.int64)
     for b in range(11):
         for d in range(3):
@@ -149,17 +150,17 @@ def _morton_key(x, ng, box):
     return key
 
 
-@pytest.mark.parametrize("ng,n,prec", [(64, 100003, 0), (32, 5000, 1)])
-def test_morton_sort_permutes_and_orders(ng, n, prec):
+@pytest.mark.parametrize("ng,n,prec,shift", [(64, 100003, 0, 0), (64, 100003, 0, 4), (32, 5000, 1, 2)])
+def test_morton_sort_permutes_and_orders(ng, n, prec, shift):
     box = 500.0
-    cfg = lib_config(ng, box, precision=prec, sort_every=1, n_initial=n)
+    cfg = lib_config(ng, box, precision=prec, sort_every=1, sort_shift=shift, n_initial=n)
     x, p, ids = uniform_particles(n, box, 77)
     log(f"morton sort ng={ng} n={n}")
     sim = make_sim(cfg, n)
     sim.bind(x, p, ids)
     sim.sort()
     gx, gp, gid = sim.particles()
-    key = _morton_key(gx, ng, box)
+    key = _morton_key(gx, ng, box, shift)
     assert np.all(np.diff(key) >= 0)
     order = np.argsort(gid)
     assert np.array_equal(gid[order], ids)
