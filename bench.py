@@ -51,7 +51,7 @@ def log(msg):
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
 # Valid only for the kernel source it was measured on.
-MEASURED_TRAFFIC = {"smooth_color": 197.3e6}
+MEASURED_TRAFFIC = {}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
