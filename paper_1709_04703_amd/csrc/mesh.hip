@@ -331,9 +331,11 @@ k_smooth_color(T* __restrict__ e, const T* __restrict__ r, int n, Box b, int col
 // neighbours and r one vector load each.  Vectors start at multiples of 4
 // (the box's first half-row index rounded down; n / 2 is a multiple of 4, so
 // a vector never leaves its row) and cells outside the box are masked.
-// Tiles are 4 TXV half-row entries x 256 / TXV rows x kVecKz planes.
+// Tiles are 4 TXV half-row entries x 256 / TXV rows x kVecKz planes (one plane
+// per thread measured fastest on the 512^3 mesh: more planes cut the grid
+// below what hides the HBM latency).
 #ifndef SDPM_VEC_KZ
-#define SDPM_VEC_KZ 4
+#define SDPM_VEC_KZ 1
 #endif
 constexpr int kVecKz = SDPM_VEC_KZ;           // planes per thread of the vector colour kernels
 
