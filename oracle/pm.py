@@ -20,7 +20,8 @@ Conventions
 Readings of the paper where it is silent or garbled (each also listed in the
 design notes):
 * Gravity (Sec. 2.1 Eq. 4) is advanced by one backward-Euler step per half
-  sub-step (the paper names implicit solvers as the intended route, Sec. 3.1.1):
+  sub-step (the paper names implicit solvers as the intended route, Sec. 3.1.1;
+  Config.solver = "ade" takes the paper's own ADE sweeps instead, oracle/ade.py):
   3 calH (Phi+ - Phi-)/(dtau/2) - c^2 Lap Phi+ = -c^2 S delta, i.e.
   (Lap - kappa) Phi+ = S delta - kappa Phi-,  kappa = 3 calH / (c^2 dtau/2).
   kappa = 0 is Poisson (Eq. 3).  Both half sub-steps (Table 2) reuse the
@@ -48,6 +49,7 @@ import math
 import numpy as np
 import scipy.fft as sfft
 
+from . import ade
 from . import cosmology as cosmo
 
 
@@ -68,6 +70,7 @@ class Config:
     align: int = 1               # planes next to the box at multiples of this
     frac_bits: int = 14
     n_initial: int = 0
+    solver: str = "implicit"     # "implicit": backward Euler; "ade": the paper's ADE sweeps
 
     def observer(self) -> np.ndarray:
         if self.x_obs is None:
@@ -384,6 +387,16 @@ def solve(phi: np.ndarray, rhs: np.ndarray, state: State, kappa_h2: float) -> np
     return solve_box(phi, rhs, state.lo, state.hi, kappa_h2)
 
 
+def ade_sweep(phi: np.ndarray, f: np.ndarray, state: State, kappa_h2: float,
+              forward: bool) -> np.ndarray:
+    """One ADE sweep (oracle/ade.py) of a half sub-step over the active box,
+    lam = 1 / (kappa h^2)."""
+    n = phi.shape[0]
+    if state.periodic:
+        return ade.sweep(phi, f, 1.0 / kappa_h2, (0, 0, 0), (n - 1,) * 3, True, forward)
+    return ade.sweep(phi, f, 1.0 / kappa_h2, tuple(state.lo), tuple(state.hi), False, forward)
+
+
 def init_state(x, p, ids, cfg: Config, a: float) -> State:
     """Bind particles at scale factor a, apply the lightcone at a, and set the
     field from linear theory by one static (kappa = 0) solve of the initial
@@ -426,7 +439,12 @@ def step(state: State, cfg: Config, da: float, diag: dict | None = None) -> Stat
     f = source(counts, cfg.n_initial, cfg.frac_bits, sc["s_half"], h, st.periodic)
     # Phi from t to t + dt/2
     k1 = sc["kappa1_h2"]
-    phi_half = solve(st.phi, f - k1 * st.phi, st, k1)
+    if cfg.solver == "ade":
+        if not k1 > 0.0:
+            raise ValueError("the ADE integrator needs a finite gravity speed")
+        phi_half = ade_sweep(st.phi, f, st, k1, True)
+    else:
+        phi_half = solve(st.phi, f - k1 * st.phi, st, k1)
     # grad Phi, interpolation, kick with a(t + dt/2)  (Eq. 8)
     g = force_mesh(phi_half, h)
     gp = interpolate(x, g, cfg.ng, cfg.box, cfg.frac_bits, st.periodic)
@@ -437,7 +455,9 @@ def step(state: State, cfg: Config, da: float, diag: dict | None = None) -> Stat
         x = _wrap(x, cfg.box)
     # Phi from t + dt/2 to t + dt (same density); static gravity: unchanged
     k2 = sc["kappa2_h2"]
-    if k2 > 0.0:
+    if cfg.solver == "ade":
+        phi_new = ade_sweep(phi_half, f, st, k2, False)
+    elif k2 > 0.0:
         phi_new = solve(phi_half, f - k2 * phi_half, st, k2)
     else:
         phi_new = phi_half
