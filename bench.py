@@ -15,7 +15,12 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
   learned: extrap, plus the conv-net warm start, gated: the library keeps the
            net only while the outer iterations it saves outweigh its measured
            cost (the headline value);
-  learned_always: extrap, plus the conv-net guess tried before every solve.
+  learned_always: extrap, plus the conv-net guess tried before every solve;
+  ade:     the paper's own gravity integrator instead of the implicit solve
+           (one alternating-direction explicit sweep per half sub-step, FP64
+           mesh, FP32 momenta): a different discretisation in time, so it is
+           not held to the residual; its potential and momenta after the timed
+           steps are compared with those of the implicit modes (ade_vs_implicit).
 The net is trained once before the timed regions, on the GPU, on solves
 recorded (with the extrapolated start) from 128^3 runs of the same schedule
 with other seeds.
@@ -122,7 +127,8 @@ def train_net(P, torch, args):
     return w, info
 
 
-def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, extrap=False):
+def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, extrap=False,
+             solver=0, keep=False):
     x, p, ids = ics
     ng, box = args.ng, args.box
     n = x.shape[0]
@@ -130,7 +136,7 @@ def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, 
                            sort_every=args.sort_every, sort_shift=args.sort_shift,
                            warm_start=(P.SDPM_WS_PREV if weights is None else
                                        P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
-                           | (P.SDPM_WS_EXTRAP if extrap else 0))
+                           | (P.SDPM_WS_EXTRAP if extrap else 0), solver=solver)
     sim = P.Simulation(cfg, n)
     if weights is not None:
         sim.set_warmstart_weights(weights)
@@ -160,11 +166,17 @@ def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = sim.profile_read() if profile else None
+    kept = None
+    if keep:
+        # final potential and momenta (ordered by particle id), left on the GPU
+        k = sim.n_active
+        order = torch.argsort(sim.ids[:k].to(torch.int64) & 0xFFFFFFFF)
+        kept = (sim.phi.clone(), sim.p[:, :k][:, order].to(torch.float64))
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return dict(seconds=dt, updates=updates, vcycles=vcyc, solve_ms=solve_ms, iters=iters,
-                stats=stats, prof=prof, cfg=cfg, warm_used=used)
+                stats=stats, prof=prof, cfg=cfg, warm_used=used, kept=kept)
 
 
 def copy_bandwidth(torch, mib=2048, reps=5):
@@ -293,7 +305,7 @@ def main():
     ap.add_argument("--z-init", type=float, default=49.0)
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
-    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always")
+    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade")
     ap.add_argument("--train-ng", type=int, default=128)
     ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
     ap.add_argument("--train-pairs", type=int, default=400)
@@ -344,12 +356,27 @@ def main():
                 net_weights, net_info = train_net(P, torch, args)
             weights = net_weights
         r = run_mode(P, torch, ics, args, prec, profile=True, weights=weights,
-                     gated=(mode != "learned_always"), extrap=(mode != "plain" and mode != "mixed"))
+                     gated=(mode != "learned_always"),
+                     extrap=mode not in ("plain", "mixed", "ade"),
+                     solver=P.SDPM_SOLVER_ADE if mode == "ade" else P.SDPM_SOLVER_IMPLICIT,
+                     keep=mode in ("ade", "extrap", "mixed"))
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
-    head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always")
+    head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always", "ade")
                      if m in results)
+    ade_cmp = None
+    ref_mode = next((m for m in ("extrap", "mixed") if m in results), None)
+    if "ade" in results and ref_mode:
+        (pa, ma), (pr, mr) = results["ade"]["kept"], results[ref_mode]["kept"]
+        rr = lambda u, v: float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(v))
+        ade_cmp = {"reference_mode": ref_mode, "after_step": args.warmup + args.steps,
+                   "phi_rel_rms": rr(pa, pr),
+                   "p_rel_rms": rr(ma, mr) if ma.shape == mr.shape else None}
+        log(f"ade vs {ref_mode}: {ade_cmp}")
+    for r in results.values():
+        r["kept"] = None
+    torch.cuda.empty_cache()
     head = results[head_mode]
     value = head["updates"] / head["seconds"]
     modes = {}
@@ -359,7 +386,8 @@ def main():
             "vcycles_per_s": r["vcycles"] / (r["solve_ms"] / 1e3) if r["solve_ms"] > 0 else None,
             "ms_per_step": 1e3 * r["seconds"] / args.steps,
             "outer_iters_per_solve": float(np.mean([sum(i) / 2 for i in r["iters"]])),
-            "final_residual_max": max(max(s["res"]) for s in r["stats"]),
+            "final_residual_max": (max(max(s["res"]) for s in r["stats"])
+                                   if mode != "ade" else None),
             "kappa_h2": r["stats"][0]["kappa_h2"][0],
             "warm_starts_used": r["warm_used"],
             "net_calls": (r["prof"].get("conv3d_mfma", {}).get("launches", 0) // 5
@@ -405,7 +433,8 @@ def main():
         "dtype": {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
                   "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
                   "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
-                  "extrap": "f32 V-cycles in f64 defect correction"}[head_mode],
+                  "extrap": "f32 V-cycles in f64 defect correction",
+                  "ade": "f64 ADE sweeps"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
@@ -421,6 +450,7 @@ def main():
         "roofline": roofline,
         "hbm_copy_GBps": copy_gbs,
         "shrink_phase": shrink,
+        "ade_vs_implicit": ade_cmp,
         "roofline_learned": learned_roofline,
         "net": net_info,
         "cpu_baseline": cpu,

@@ -70,6 +70,15 @@ enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1, SDPM_WS_LEARNED_GATED = 2 };
  * the previous potential).  Costs two passes over the active box per solve
  * (an FP32 copy of the start, then the change) and three FP32 meshes.      */
 enum { SDPM_WS_EXTRAP = 4 };
+/* sdpm_config.solver: how each half sub-step advances the potential by the
+ * diffusion equation of Sec. 2.1 Eq. 4.  SDPM_SOLVER_IMPLICIT: one backward-
+ * Euler step solved by multigrid to tol.  SDPM_SOLVER_ADE: the paper's own
+ * alternating-direction explicit integrator (Sec. 2.3): one Saul'yev sweep
+ * per half sub-step, forward for the first and backward for the second (see
+ * sdpm_ade_sweep); needs a finite gravity speed (c_grav != 0) and
+ * warm_start == SDPM_WS_PREV, and leaves the step's outer_iters and
+ * residuals at 0.  The initial static solve is multigrid in both cases.    */
+enum { SDPM_SOLVER_IMPLICIT = 0, SDPM_SOLVER_ADE = 1 };
 
 typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
 
@@ -101,6 +110,7 @@ typedef struct sdpm_config {
   int32_t sort_shift;    /* sort key: Morton order of cell blocks of 2^shift
                             cells per axis (stable: particles keep their
                             order inside a block); default 4 for ng >= 64    */
+  int32_t solver;        /* SDPM_SOLVER_IMPLICIT (default) or SDPM_SOLVER_ADE */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,
@@ -237,6 +247,17 @@ int sdpm_deposit(sdpm_ctx* ctx);
 /* rhs = h^2 S (counts / (n0/ng^3 2^3B) - 1) [- mean, periodic] - kappa h^2 phi,
  * then solve (Lap_h - kappa h^2) phi = rhs on the active box, phi as guess. */
 int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_stats* out);
+/* One ADE sweep (Sec. 2.3) of fields->phi in place over the active box with
+ * fields->rhs as the source f = S h^2 delta (the caller's values; sdpm_step
+ * assembles it):  (1 + 3 lam) phi_c' = (1 - 3 lam) phi_c + lam (S6 - f_c),
+ * S6 the six neighbours' current values, cells visited in lexicographic order
+ * (forward != 0: z, y, x increasing; 0: decreasing), so neighbours visited
+ * earlier enter with their new values.  Periodic wrap while the mesh is
+ * periodic; frozen exterior otherwise.  lam = D dt / h^2 > 0 (sdpm_step uses
+ * 1 / kappa_h2 of the half sub-step).  Runs on the context's stream, one
+ * launch per diagonal of rows (ny + nz - 1 launches).  SDPM_EINVAL for lam
+ * not finite and positive.                                                  */
+int sdpm_ade_sweep(sdpm_ctx* ctx, double lam, int forward);
 /* Morton re-sort of the active particles (all SoA arrays permuted together
  * by the Morton code of their cell, stable LSD radix sort).  Results of the
  * step do not depend on particle order; the sort improves locality.       */

@@ -19,6 +19,7 @@ SDPM_OK, SDPM_EINVAL, SDPM_ENOMEM, SDPM_EHIP = 0, -1, -2, -3
 SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6, -7, -8
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
 SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED, SDPM_WS_EXTRAP = 0, 1, 2, 4
+SDPM_SOLVER_IMPLICIT, SDPM_SOLVER_ADE = 0, 1
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",
@@ -35,6 +36,7 @@ EXPORTS = [
     "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
     "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
+    "sdpm_ade_sweep",
 ]
 NET_PARAMS = 5 * (27 * 16 * 16 + 16)
 CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
@@ -52,6 +54,7 @@ class Config(ctypes.Structure):
         ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
         ("warm_start", ctypes.c_int32), ("n_initial", ctypes.c_int64),
         ("sort_every", ctypes.c_int32), ("sort_shift", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -150,6 +153,7 @@ def library() -> ctypes.CDLL:
         "sdpm_destroy": [vp],
         "sdpm_set_lightcone": [vp, P(Lightcone)],
         "sdpm_lightcone_count": [vp, P(i64)],
+        "sdpm_ade_sweep": [vp, dbl, i32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -382,6 +386,10 @@ class Simulation:
         st = StepStats()
         self._check(self.lib.sdpm_solve(self.ctx, kappa_h2, s_source, ctypes.byref(st)))
         return st.as_dict()
+
+    def ade_sweep(self, lam: float, forward: bool = True):
+        """One ADE sweep of phi in place with rhs as the source."""
+        self._check(self.lib.sdpm_ade_sweep(self.ctx, lam, 1 if forward else 0))
 
     def sort(self):
         self._check(self.lib.sdpm_sort(self.ctx))

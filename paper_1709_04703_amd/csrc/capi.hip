@@ -152,6 +152,11 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
   if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
     return snprintf(msg, len, "sort_every and sort_shift must be >= 0, ng >> sort_shift >= 1"), SDPM_EINVAL;
+  if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE)
+    return snprintf(msg, len, "unknown solver %d", c->solver), SDPM_EINVAL;
+  if (c->solver == SDPM_SOLVER_ADE && (c->c_grav == 0.0 || c->warm_start != SDPM_WS_PREV))
+    return snprintf(msg, len, "the ADE solver needs c_grav != 0 and warm_start SDPM_WS_PREV"),
+           SDPM_EINVAL;
   return SDPM_OK;
 }
 
@@ -732,6 +737,7 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->n_initial = (int64_t)ng * ng * ng;
   cfg->sort_every = 0;
   cfg->sort_shift = ng >= 64 ? 4 : 0;   // Morton order of 16^3-cell blocks
+  cfg->solver = SDPM_SOLVER_IMPLICIT;
   return SDPM_OK;
 }
 
@@ -920,12 +926,20 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   deposit(c, 0.5 * sc.dtau / a, 1);
   HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
   // Phi from t to t + dt/2                              (row 3)
-  assemble_rhs(c, sc.s_half, sc.kappa1_h2);
+  const bool ade = g.solver == SDPM_SOLVER_ADE;
+  assemble_rhs(c, sc.s_half, ade ? 0.0 : sc.kappa1_h2);
   HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
   const StepDtau step_dtau(c, sc.dtau);
   SolveOut s1;
-  const int src1 = solve(c, sc.kappa1_h2, 0, &s1);
-  if (src1 && src1 != SDPM_ENOCONV) return src1;
+  int src1 = SDPM_OK;
+  if (ade) {
+    // the paper's ADE: a forward sweep with the mid-step source f = rhs
+    launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
+                     1.0 / sc.kappa1_h2, true, c->st);
+  } else {
+    src1 = solve(c, sc.kappa1_h2, 0, &s1);
+    if (src1 && src1 != SDPM_ENOCONV) return src1;
+  }
   HIP_TRY(c, hipEventRecord(c->ev[3], c->st));
   // grad Phi, CIC interpolation, kick with a(t+dt/2), drift with a(t+dt)  (rows 4-6)
   const bool removal = g.shrink && c->n_active > 0 &&
@@ -950,7 +964,11 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   // Phi from t + dt/2 to t + dt with the same density    (row 7)
   SolveOut s2;
   int src2 = SDPM_OK;
-  if (sc.kappa2_h2 > 0.0) {
+  if (ade) {
+    // the same source, the sweep in the other direction
+    launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
+                     1.0 / sc.kappa2_h2, false, c->st);
+  } else if (sc.kappa2_h2 > 0.0) {
     assemble_rhs(c, sc.s_half, sc.kappa2_h2);
     src2 = solve(c, sc.kappa2_h2, 1, &s2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
@@ -1094,6 +1112,19 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
     fill_state(c, out);
   }
   return rc;
+}
+
+int sdpm_ade_sweep(sdpm_ctx* c, double lam, int forward) {
+  ProfScope prof_scope(c);
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!(lam > 0.0) || !std::isfinite(lam))
+    return fail(c, SDPM_EINVAL, "lam must be finite and > 0");
+  launch_ade_sweep(c->fields.phi, c->fields.rhs, c->cfg.ng, c->lv[0].box, c->periodic != 0, lam,
+                   forward != 0, c->st);
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  return SDPM_OK;
 }
 
 int sdpm_sort(sdpm_ctx* c) {

@@ -108,6 +108,9 @@ void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int
 void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st);
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
                          hipStream_t st);
+// One ADE sweep of phi over box b with source f (ade.hip).
+void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool periodic, double lam,
+                      bool forward, hipStream_t st);
 // One V-cycle for A_0 e = r_0; returns the level-0 buffer holding e.
 template <typename T>
 const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
@@ -227,7 +230,7 @@ enum KernelId : int {
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE, K_EXTRAP,
-  K_SMOOTH_COARSE,
+  K_SMOOTH_COARSE, K_ADE,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

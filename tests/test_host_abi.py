@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(P):
 
 
 def test_struct_sizes_match_header_layout(P):
-    assert ctypes.sizeof(P.Config) == 136
+    assert ctypes.sizeof(P.Config) == 144   # ..., sort_every, sort_shift, solver (+4 padding)
     assert ctypes.sizeof(P.StepStats) == 8 * 2 + 4 * 4 + 8 * 4 + 8 * 5 + 4 * 7 + 4 * 8 + 4 + 16
 
 
@@ -79,6 +79,18 @@ def test_config_validation_errors(P):
         P.workspace_bytes(P.config_default(64, 10.0, warm_start=7), 10)
     with pytest.raises(P.SdpmError):
         P.step_scalars(P.config_default(64, 10.0), 0.5, -0.1)
+
+
+def test_ade_solver_config_validation(P):
+    # the ADE integrator needs a finite gravity speed and has no solve to warm-start
+    ok = P.config_default(64, 100.0, c_grav=-1.0, solver=P.SDPM_SOLVER_ADE)
+    assert P.workspace_bytes(ok, 10) > 0
+    for bad in (dict(c_grav=0.0, solver=P.SDPM_SOLVER_ADE),
+                dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE, warm_start=P.SDPM_WS_EXTRAP),
+                dict(c_grav=-1.0, solver=2)):
+        with pytest.raises(P.SdpmError, match="EINVAL"):
+            P.workspace_bytes(P.config_default(64, 100.0, **bad), 10)
+    assert P.config_default(64, 100.0).solver == P.SDPM_SOLVER_IMPLICIT
 
 
 def test_workspace_grows_with_capacity_and_precision(P):
