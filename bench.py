@@ -20,7 +20,10 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
            (one alternating-direction explicit sweep per half sub-step, FP64
            mesh, FP32 momenta): a different discretisation in time, so it is
            not held to the residual; its potential and momenta after the timed
-           steps are compared with those of the implicit modes (ade_vs_implicit).
+           steps are compared with those of the implicit modes (ade_vs_implicit);
+  fft:     the implicit step solved exactly by FP64 FFT while the mesh is
+           periodic (the standard particle-mesh solver), FP32 momenta; compared
+           with the implicit modes like ade (fft_vs_implicit).
 The net is trained once before the timed regions, on the GPU, on solves
 recorded (with the extrapolated start) from 128^3 runs of the same schedule
 with other seeds.
@@ -305,7 +308,7 @@ def main():
     ap.add_argument("--z-init", type=float, default=49.0)
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
-    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade")
+    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade,fft")
     ap.add_argument("--train-ng", type=int, default=128)
     ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
     ap.add_argument("--train-pairs", type=int, default=400)
@@ -357,23 +360,25 @@ def main():
             weights = net_weights
         r = run_mode(P, torch, ics, args, prec, profile=True, weights=weights,
                      gated=(mode != "learned_always"),
-                     extrap=mode not in ("plain", "mixed", "ade"),
-                     solver=P.SDPM_SOLVER_ADE if mode == "ade" else P.SDPM_SOLVER_IMPLICIT,
-                     keep=mode in ("ade", "extrap", "mixed"))
+                     extrap=mode not in ("plain", "mixed", "ade", "fft"),
+                     solver={"ade": P.SDPM_SOLVER_ADE, "fft": P.SDPM_SOLVER_FFT}.get(
+                         mode, P.SDPM_SOLVER_IMPLICIT),
+                     keep=mode in ("ade", "fft", "extrap", "mixed"))
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
-    head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always", "ade")
-                     if m in results)
-    ade_cmp = None
+    head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always", "ade",
+                                 "fft") if m in results)
+    cmp = {}
     ref_mode = next((m for m in ("extrap", "mixed") if m in results), None)
-    if "ade" in results and ref_mode:
-        (pa, ma), (pr, mr) = results["ade"]["kept"], results[ref_mode]["kept"]
-        rr = lambda u, v: float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(v))
-        ade_cmp = {"reference_mode": ref_mode, "after_step": args.warmup + args.steps,
-                   "phi_rel_rms": rr(pa, pr),
-                   "p_rel_rms": rr(ma, mr) if ma.shape == mr.shape else None}
-        log(f"ade vs {ref_mode}: {ade_cmp}")
+    for other in ("ade", "fft"):
+        if other in results and ref_mode:
+            (pa, ma), (pr, mr) = results[other]["kept"], results[ref_mode]["kept"]
+            rr = lambda u, v: float(torch.linalg.vector_norm(u - v) / torch.linalg.vector_norm(v))
+            cmp[other] = {"reference_mode": ref_mode, "after_step": args.warmup + args.steps,
+                          "phi_rel_rms": rr(pa, pr),
+                          "p_rel_rms": rr(ma, mr) if ma.shape == mr.shape else None}
+            log(f"{other} vs {ref_mode}: {cmp[other]}")
     for r in results.values():
         r["kept"] = None
     torch.cuda.empty_cache()
@@ -387,7 +392,7 @@ def main():
             "ms_per_step": 1e3 * r["seconds"] / args.steps,
             "outer_iters_per_solve": float(np.mean([sum(i) / 2 for i in r["iters"]])),
             "final_residual_max": (max(max(s["res"]) for s in r["stats"])
-                                   if mode != "ade" else None),
+                                   if mode not in ("ade", "fft") else None),
             "kappa_h2": r["stats"][0]["kappa_h2"][0],
             "warm_starts_used": r["warm_used"],
             "net_calls": (r["prof"].get("conv3d_mfma", {}).get("launches", 0) // 5
@@ -434,7 +439,7 @@ def main():
                   "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
                   "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
                   "extrap": "f32 V-cycles in f64 defect correction",
-                  "ade": "f64 ADE sweeps"}[head_mode],
+                  "ade": "f64 ADE sweeps", "fft": "f64 FFT solves"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
@@ -450,7 +455,8 @@ def main():
         "roofline": roofline,
         "hbm_copy_GBps": copy_gbs,
         "shrink_phase": shrink,
-        "ade_vs_implicit": ade_cmp,
+        "ade_vs_implicit": cmp.get("ade"),
+        "fft_vs_implicit": cmp.get("fft"),
         "roofline_learned": learned_roofline,
         "net": net_info,
         "cpu_baseline": cpu,

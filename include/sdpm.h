@@ -78,7 +78,13 @@ enum { SDPM_WS_EXTRAP = 4 };
  * sdpm_ade_sweep); needs a finite gravity speed (c_grav != 0) and
  * warm_start == SDPM_WS_PREV, and leaves the step's outer_iters and
  * residuals at 0.  The initial static solve is multigrid in both cases.    */
-enum { SDPM_SOLVER_IMPLICIT = 0, SDPM_SOLVER_ADE = 1 };
+/* SDPM_SOLVER_FFT: the implicit step (and the initial static solve) solved
+ * exactly by FFT while the mesh is periodic (the standard particle-mesh
+ * solver the paper compares against, Sec. 2.4, with the 7-point symbol),
+ * multigrid once the domain has a frozen exterior; FP64 hipFFT transforms
+ * with their work area in the workspace; needs warm_start == SDPM_WS_PREV;
+ * reports 0 iterations and residual 0 for FFT solves.                      */
+enum { SDPM_SOLVER_IMPLICIT = 0, SDPM_SOLVER_ADE = 1, SDPM_SOLVER_FFT = 2 };
 
 typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
 
@@ -110,7 +116,7 @@ typedef struct sdpm_config {
   int32_t sort_shift;    /* sort key: Morton order of cell blocks of 2^shift
                             cells per axis (stable: particles keep their
                             order inside a block); default 4 for ng >= 64    */
-  int32_t solver;        /* SDPM_SOLVER_IMPLICIT (default) or SDPM_SOLVER_ADE */
+  int32_t solver;        /* SDPM_SOLVER_IMPLICIT (default), _ADE or _FFT        */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,

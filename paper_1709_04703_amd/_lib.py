@@ -19,7 +19,7 @@ SDPM_OK, SDPM_EINVAL, SDPM_ENOMEM, SDPM_EHIP = 0, -1, -2, -3
 SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6, -7, -8
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
 SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED, SDPM_WS_EXTRAP = 0, 1, 2, 4
-SDPM_SOLVER_IMPLICIT, SDPM_SOLVER_ADE = 0, 1
+SDPM_SOLVER_IMPLICIT, SDPM_SOLVER_ADE, SDPM_SOLVER_FFT = 0, 1, 2
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdpm.so")
-SOURCES = ["capi.hip", "mesh.hip", "ade.hip", "particles.hip", "sort.hip", "net.hip", "cosmology.cpp", "profiler.cpp"]
+SOURCES = ["capi.hip", "mesh.hip", "ade.hip", "fft.hip", "particles.hip", "sort.hip", "net.hip", "cosmology.cpp", "profiler.cpp"]
 ARCH = os.environ.get("SDPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -21,6 +21,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+LIBS = ["-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def hipcc() -> str:
@@ -36,7 +37,7 @@ def build(verbose: bool = False) -> str:
         p = os.path.join(CSRC, s)
         srcs += ["-x", "hip", p]
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + srcs + ["-o", tmp]
+    cmd = [hipcc()] + FLAGS + srcs + LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

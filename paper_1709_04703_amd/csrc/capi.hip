@@ -29,6 +29,9 @@ struct sdpm_ctx {
   void* scratch = nullptr;
   void* sort_scratch = nullptr;
   float* gmesh = nullptr;       // FP32 force mesh (mixed precision)
+  FftPlan fft;                  // periodic FFT solver (SDPM_SOLVER_FFT)
+  void* fft_work = nullptr;
+  size_t fft_work_bytes = 0;
   // learned warm start
   float* net_params = nullptr;
   uint16_t* net_act0 = nullptr;
@@ -152,8 +155,11 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->n_initial < 1) return snprintf(msg, len, "n_initial must be >= 1"), SDPM_EINVAL;
   if (c->sort_every < 0 || c->sort_shift < 0 || (c->ng >> c->sort_shift) < 1)
     return snprintf(msg, len, "sort_every and sort_shift must be >= 0, ng >> sort_shift >= 1"), SDPM_EINVAL;
-  if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE)
+  if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE &&
+      c->solver != SDPM_SOLVER_FFT)
     return snprintf(msg, len, "unknown solver %d", c->solver), SDPM_EINVAL;
+  if (c->solver == SDPM_SOLVER_FFT && c->warm_start != SDPM_WS_PREV)
+    return snprintf(msg, len, "the FFT solver takes warm_start SDPM_WS_PREV"), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_ADE && (c->c_grav == 0.0 || c->warm_start != SDPM_WS_PREV))
     return snprintf(msg, len, "the ADE solver needs c_grav != 0 and warm_start SDPM_WS_PREV"),
            SDPM_EINVAL;
@@ -201,6 +207,20 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   // FP32 force mesh of the mixed-precision step (3 values per cell)
   float* g3 = c.precision == SDPM_MIXED ? (float*)take((size_t)c.ng * c.ng * c.ng * 3 * sizeof(float))
                                         : nullptr;
+  if (c.solver == SDPM_SOLVER_FFT) {
+    // half spectrum, the transforms' work area (at most the spectrum's size)
+    // and the symbol table
+    const size_t cb = fft_complex_bytes(c.ng);
+    void* cbuf = take(cb);
+    void* work = take(cb);
+    double* sym = (double*)take((size_t)c.ng * sizeof(double));
+    if (ctx) {
+      ctx->fft.c = cbuf;
+      ctx->fft.sym = sym;
+      ctx->fft_work = work;
+      ctx->fft_work_bytes = cb;
+    }
+  }
   if (c.warm_start & SDPM_WS_EXTRAP) {
     const size_t V = (size_t)c.ng * c.ng * c.ng;
     float* d0 = (float*)take(V * sizeof(float));
@@ -583,6 +603,12 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
 }
 
 int solve(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
+  if (c->cfg.solver == SDPM_SOLVER_FFT && c->periodic) {
+    // exact: no iterations, residual at rounding level (reported as 0)
+    *so = SolveOut{};
+    const int rc = fft_solve(c->fft, c->fields.rhs, c->fields.phi, kappa, c->st);
+    return rc ? fail(c, rc, "hipFFT execution failed") : SDPM_OK;
+  }
   return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, slot, so)
                                         : solve_impl<double>(c, kappa, slot, so);
 }
@@ -838,6 +864,18 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
     }
   }
   clear_all_levels(c);
+  if (cfg->solver == SDPM_SOLVER_FFT) {
+    char msg[256];
+    const int frc = fft_init(&c->fft, cfg->ng, c->fft.c, c->fft_work, c->fft_work_bytes, c->fft.sym,
+                             c->st, msg, sizeof msg);
+    if (frc) {
+      fft_destroy(&c->fft);
+      for (auto& e : c->ev) (void)hipEventDestroy(e);
+      delete[] c->hpin;
+      delete c;
+      return fail(nullptr, frc, "%s", msg);
+    }
+  }
   *out = c;
   return SDPM_OK;
 }
@@ -1283,6 +1321,7 @@ int sdpm_destroy(sdpm_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
   c->prof.release();
+  fft_destroy(&c->fft);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete[] c->hpin;

@@ -108,6 +108,21 @@ void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int
 void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st);
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
                          hipStream_t st);
+// Exact periodic FFT solve of (Lap_h - kappa h^2) phi = rhs (fft.hip): FP64
+// real-to-complex / complex-to-real plans on an n^3 mesh, half-spectrum
+// buffer c, the 1-D symbol table sym (n values) on the device.
+struct FftPlan {
+  int n = 0;
+  void* fwd = nullptr;
+  void* inv = nullptr;
+  void* c = nullptr;
+  double* sym = nullptr;
+};
+size_t fft_complex_bytes(int n);
+int fft_init(FftPlan* p, int n, void* complex_buf, void* work, size_t work_bytes, double* sym_dev,
+             hipStream_t st, char* msg, size_t len);
+void fft_destroy(FftPlan* p);
+int fft_solve(const FftPlan& p, const double* rhs, double* phi, double kappa_h2, hipStream_t st);
 // One ADE sweep of phi over box b with source f (ade.hip).
 void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool periodic, double lam,
                       bool forward, hipStream_t st);
@@ -230,7 +245,7 @@ enum KernelId : int {
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE, K_EXTRAP,
-  K_SMOOTH_COARSE, K_ADE,
+  K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

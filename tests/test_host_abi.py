@@ -81,16 +81,22 @@ def test_config_validation_errors(P):
         P.step_scalars(P.config_default(64, 10.0), 0.5, -0.1)
 
 
-def test_ade_solver_config_validation(P):
-    # the ADE integrator needs a finite gravity speed and has no solve to warm-start
+def test_solver_config_validation(P):
+    # the ADE integrator needs a finite gravity speed; neither it nor the FFT
+    # solve has an iteration to warm-start
     ok = P.config_default(64, 100.0, c_grav=-1.0, solver=P.SDPM_SOLVER_ADE)
     assert P.workspace_bytes(ok, 10) > 0
     for bad in (dict(c_grav=0.0, solver=P.SDPM_SOLVER_ADE),
                 dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE, warm_start=P.SDPM_WS_EXTRAP),
-                dict(c_grav=-1.0, solver=2)):
+                dict(c_grav=-1.0, solver=3),
+                dict(solver=P.SDPM_SOLVER_FFT, warm_start=P.SDPM_WS_EXTRAP)):
         with pytest.raises(P.SdpmError, match="EINVAL"):
             P.workspace_bytes(P.config_default(64, 100.0, **bad), 10)
     assert P.config_default(64, 100.0).solver == P.SDPM_SOLVER_IMPLICIT
+    # the FFT solver's half spectrum and work area come from the workspace
+    fft = P.config_default(64, 100.0, solver=P.SDPM_SOLVER_FFT)
+    assert (P.workspace_bytes(fft, 10) - P.workspace_bytes(P.config_default(64, 100.0), 10)
+            >= 2 * 64 * 64 * 33 * 16)
 
 
 def test_workspace_grows_with_capacity_and_precision(P):
