@@ -272,6 +272,36 @@ int sdpm_sort(sdpm_ctx* ctx);
  * with the deposit's CIC weights; g_dev[3]: device FP64 arrays (n_active). */
 int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);
 
+/* Power spectrum ------------------------------------------------------------
+ * The accuracy metric the paper compares runs with (Sec. 3.1, Sec. 3.2: 3D
+ * spectra of the lightcone in a cubical box of the original size), with the
+ * discreteness corrections of Jing (2005) that the paper names for its
+ * spectrum tool (Sec. 2.4).  Standalone: no context.
+ * x_dev[3]: device FP64 positions of n particles, each in [0, box] (box is
+ * the periodic image of 0, as in the step's deposit); ng: mesh
+ * of the estimate, a power of two in [8, 1024].  delta from the fixed-point
+ * CIC counts (B = 14), one FP64 FFT, shells b = rint(|f|) = 1 .. ng/2 of the
+ * signed integer frequency f (k = f 2 pi / box).  Per shell (host arrays of
+ * ng/2): k = mean |k| of its modes [h/Mpc], modes, p_raw = mean of
+ * box^3 |delta_k|^2 (delta_k = FFT / ng^3), and p:
+ *   p_raw - shot <C1>              without SDPM_PK_JING,
+ *   (p_raw - shot <C1>) / <S>      with it (Jing's alias correction),
+ * shot = box^3 / n with SDPM_PK_SHOT, else 0; C1(f) = prod_d (1 - 2/3
+ * sin^2(pi f_d / ng)); S(f) = sum over images m in [-2, 2]^3 of
+ * prod_d sinc^4(pi (f_d + ng m_d) / ng) (|f + ng m| / |f|)^neff, neff the
+ * shell's local log-log slope of p, starting at 0 and re-estimated three
+ * times (central differences of neighbouring shells, one-sided at the ends,
+ * clamped to [-4, 4], 0 where a neighbour is not positive).
+ * workspace: device memory of sdpm_pk_workspace_bytes(ng); runs on
+ * hip_stream and returns when the results are on the host (the FFT plan is
+ * made per call).  Errors: SDPM_EINVAL (arguments), SDPM_ENOMEM (workspace
+ * too small), SDPM_EDOMAIN (a position outside [0, box]), SDPM_EHIP.     */
+enum { SDPM_PK_SHOT = 1, SDPM_PK_JING = 2 };
+int sdpm_pk_workspace_bytes(int32_t ng, int64_t* bytes);
+int sdpm_power_spectrum(const double* const x_dev[3], int64_t n, double box, int32_t ng,
+                        int32_t flags, void* workspace, int64_t ws_bytes, void* hip_stream,
+                        double* k, double* p, double* p_raw, int64_t* modes);
+
 /* Learned warm start ------------------------------------------------------
  * Not in the paper: a learned initial guess for the multigrid solve of each
  * implicit gravity sub-step.  A 5-layer 3x3x3 convolution net, 16 channels,

@@ -20,6 +20,7 @@ SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
 SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED, SDPM_WS_EXTRAP = 0, 1, 2, 4
 SDPM_SOLVER_IMPLICIT, SDPM_SOLVER_ADE, SDPM_SOLVER_FFT = 0, 1, 2
+SDPM_PK_SHOT, SDPM_PK_JING = 1, 2
 
 ERROR_NAMES = {
     SDPM_EINVAL: "EINVAL", SDPM_ENOMEM: "ENOMEM", SDPM_EHIP: "EHIP",
@@ -36,7 +37,7 @@ EXPORTS = [
     "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
     "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
-    "sdpm_ade_sweep",
+    "sdpm_ade_sweep", "sdpm_pk_workspace_bytes", "sdpm_power_spectrum",
 ]
 NET_PARAMS = 5 * (27 * 16 * 16 + 16)
 CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
@@ -154,6 +155,9 @@ def library() -> ctypes.CDLL:
         "sdpm_set_lightcone": [vp, P(Lightcone)],
         "sdpm_lightcone_count": [vp, P(i64)],
         "sdpm_ade_sweep": [vp, dbl, i32],
+        "sdpm_pk_workspace_bytes": [i32, P(i64)],
+        "sdpm_power_spectrum": [P(vp), i64, dbl, i32, i32, vp, i64, vp, P(dbl), P(dbl), P(dbl),
+                                P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -230,6 +234,37 @@ def conv3d(n, inp, w, bias, flags, mask, out):
     """One convolution layer (see sdpm_conv3d); torch device tensors."""
     check(library().sdpm_conv3d(n, _ptr(inp), _ptr(w), _ptr(bias), flags, _ptr(mask), _ptr(out),
                                 _stream()))
+
+
+def pk_workspace_bytes(ng: int) -> int:
+    b = ctypes.c_int64()
+    check(library().sdpm_pk_workspace_bytes(ng, ctypes.byref(b)))
+    return b.value
+
+
+def power_spectrum(x, box: float, ng: int, shot: bool = True, jing: bool = True) -> dict:
+    """P(k) of positions x (a (3, n) FP64 device tensor, or three (n,)
+    tensors, each in [0, box]) on an ng^3 mesh (see sdpm_power_spectrum);
+    returns numpy arrays k, p, p_raw, modes over the ng/2 shells."""
+    import torch
+    xs = [x[d] for d in range(3)]
+    for v in xs:
+        if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
+            raise ValueError("positions must be contiguous FP64 device tensors")
+    n = int(xs[0].numel())
+    ws = torch.empty(pk_workspace_bytes(ng), dtype=torch.uint8, device=xs[0].device)
+    nb = ng // 2
+    k, p, praw = (np.zeros(nb) for _ in range(3))
+    modes = np.zeros(nb, dtype=np.int64)
+    arr = (ctypes.c_void_p * 3)(*(v.data_ptr() for v in xs))
+    flags = (SDPM_PK_SHOT if shot else 0) | (SDPM_PK_JING if jing else 0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(library().sdpm_power_spectrum(arr, n, box, ng, flags, _ptr(ws), ws.numel(), _stream(),
+                                        k.ctypes.data_as(dp), p.ctypes.data_as(dp),
+                                        praw.ctypes.data_as(dp),
+                                        modes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    del ws
+    return {"k": k, "p": p, "p_raw": praw, "modes": modes}
 
 
 def net_scratch_bytes(n: int) -> int:

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdpm.so")
-SOURCES = ["capi.hip", "mesh.hip", "ade.hip", "fft.hip", "particles.hip", "sort.hip", "net.hip", "cosmology.cpp", "profiler.cpp"]
+SOURCES = ["capi.hip", "mesh.hip", "ade.hip", "fft.hip", "pk.hip", "particles.hip", "sort.hip", "net.hip", "cosmology.cpp", "profiler.cpp"]
 ARCH = os.environ.get("SDPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

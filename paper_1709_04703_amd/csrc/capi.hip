@@ -1245,6 +1245,31 @@ int sdpm_conv3d(int32_t n, const void* in_bf16, const float* w, const float* bia
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "conv3d launch failed");
 }
 
+int sdpm_pk_workspace_bytes(int32_t ng, int64_t* bytes) {
+  if (ng < 8 || ng > 1024 || (ng & (ng - 1)) || !bytes)
+    return fail(nullptr, SDPM_EINVAL, "ng must be a power of two in [8, 1024]");
+  *bytes = (int64_t)pk_workspace_bytes(ng);
+  return SDPM_OK;
+}
+
+int sdpm_power_spectrum(const double* const x_dev[3], int64_t n, double box, int32_t ng,
+                        int32_t flags, void* workspace, int64_t ws_bytes, void* hip_stream,
+                        double* k, double* p, double* p_raw, int64_t* modes) {
+  if (ng < 8 || ng > 1024 || (ng & (ng - 1)) || n <= 0 || !(box > 0.0) || !std::isfinite(box) ||
+      !x_dev || !x_dev[0] || !x_dev[1] || !x_dev[2] || !workspace || !k || !p || !modes ||
+      (flags & ~(SDPM_PK_SHOT | SDPM_PK_JING)))
+    return fail(nullptr, SDPM_EINVAL,
+                "power_spectrum: ng a power of two in [8, 1024], n > 0, box > 0, known flags, "
+                "non-NULL pointers");
+  if ((size_t)ws_bytes < pk_workspace_bytes(ng))
+    return fail(nullptr, SDPM_ENOMEM, "power_spectrum: workspace of %lld bytes < %zu required",
+                (long long)ws_bytes, pk_workspace_bytes(ng));
+  char msg[256] = {0};
+  const int rc = power_spectrum(x_dev, n, box, ng, flags, workspace, (hipStream_t)hip_stream, k, p,
+                                p_raw, modes, msg, sizeof msg);
+  return rc ? fail(nullptr, rc, "power_spectrum: %s", msg) : SDPM_OK;
+}
+
 int sdpm_net_scratch_bytes(int32_t n, int64_t* bytes) {
   if (!net_size_ok(n) || !bytes) return fail(nullptr, SDPM_EINVAL, "n must be a power of two >= 16");
   *bytes = (int64_t)net_train_scratch_bytes(n);

@@ -123,6 +123,11 @@ int fft_init(FftPlan* p, int n, void* complex_buf, void* work, size_t work_bytes
              hipStream_t st, char* msg, size_t len);
 void fft_destroy(FftPlan* p);
 int fft_solve(const FftPlan& p, const double* rhs, double* phi, double kappa_h2, hipStream_t st);
+// Power spectrum of particle positions (pk.hip; see sdpm_power_spectrum).
+size_t pk_workspace_bytes(int n);
+int power_spectrum(const double* const x[3], int64_t npart, double box, int n, int flags,
+                   void* ws, hipStream_t st, double* k_out, double* p_out, double* praw_out,
+                   int64_t* modes_out, char* msg, size_t len);
 // One ADE sweep of phi over box b with source f (ade.hip).
 void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool periodic, double lam,
                       bool forward, hipStream_t st);
@@ -245,7 +250,7 @@ enum KernelId : int {
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE, K_EXTRAP,
-  K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE,
+  K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK,
   K_NKERNELS
 };
 extern const char* const kKernelNames[K_NKERNELS];

@@ -99,6 +99,14 @@ def test_solver_config_validation(P):
             >= 2 * 64 * 64 * 33 * 16)
 
 
+def test_power_spectrum_workspace(P):
+    # mesh, half spectrum and FFT work area at least
+    assert P.pk_workspace_bytes(64) >= 8 * 64**3 + 2 * 64 * 64 * 33 * 16
+    for bad in (12, 4, 2048):
+        with pytest.raises(P.SdpmError, match="EINVAL"):
+            P.pk_workspace_bytes(bad)
+
+
 def test_workspace_grows_with_capacity_and_precision(P):
     cfg = P.config_default(64, 100.0)
     a = P.workspace_bytes(cfg, 0)
