@@ -31,6 +31,14 @@ The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
+Two accuracy experiments of the paper, on synthetic 128^3 inputs (experiments):
+  lightcone: the 3D power spectrum of the lightcone recorded by a shrinking run
+    and by a run on the fixed periodic domain (same diffusion gravity), in a
+    cubical box of the original size (2000 Mpc/h, z = 49 -> 0 in 100 steps);
+  solvers: the z = 0 power spectrum of a 500 Mpc/h box (fixed domain) with
+    static Poisson gravity (FFT) against the diffusion equation advanced
+    implicitly (multigrid) and by the paper's ADE sweeps (also with 4x the
+    steps: its small-scale modes relax only when lam k^2 h^2 is small).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -200,6 +208,108 @@ def copy_bandwidth(torch, mib=2048, reps=5):
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def _run_to_end(P, ics, ng, box, z_init, steps, lightcone=False, **cfg_kw):
+    """One 128^3-scale run z_init -> 0; returns (sim, n) with the run done."""
+    x, p, ids = ics
+    n = x.shape[0]
+    cfg = P.config_default(ng, box, n_initial=n, **cfg_kw)
+    sim = P.Simulation(cfg, n)
+    sim.bind(x, p, ids)
+    if lightcone:
+        sim.set_lightcone(n)
+    a0 = 1.0 / (1.0 + z_init)
+    edges = np.linspace(a0, 1.0, steps + 1)
+    sim.init_potential(a0)
+    for s_ in range(steps):
+        sim.step(edges[s_], edges[s_ + 1] - edges[s_])
+    return sim, n
+
+
+def _pk(P, torch, x, box, ng):
+    """P(k) of host positions (n, 3), wrapped into the periodic box; the raw
+    shell spectrum (p_raw) is the one compared between runs (the particles
+    come from a displaced lattice, so Poisson shot-noise subtraction does not
+    apply), the Jing-corrected one is reported beside it."""
+    xw = np.mod(x, box)
+    xw[xw >= box] = 0.0
+    return P.power_spectrum(torch.as_tensor(np.ascontiguousarray(xw.T)).cuda(), box, ng,
+                            shot=False, jing=True)
+
+
+def _rel(pa, pb, modes, min_modes=20):
+    sel = modes >= min_modes
+    return float(np.max(np.abs(pa[sel] / pb[sel] - 1.0)))
+
+
+def _rel_curve(pa, pb, every=8):
+    return [round(float(v), 5) for v in (pa / pb - 1.0)[::every]]
+
+
+def experiments(P, torch, args):
+    """The paper's two accuracy comparisons on synthetic inputs (module notes)."""
+    from synth import zeldovich_ics
+    t0 = time.perf_counter()
+    ng, steps, z0 = args.exp_ng, args.exp_steps, args.z_init
+    out = {}
+    # lightcone: shrinking vs fixed domain
+    box = 2000.0
+    ics = zeldovich_ics(ng, box, 1.0 / (1.0 + z0), args.seed + 1)
+    recs = {}
+    for shrink in (1, 0):
+        sim, n = _run_to_end(P, ics, ng, box, z0, steps, lightcone=True, c_grav=-1.0,
+                             shrink=shrink, sort_every=args.sort_every)
+        gid, _, gx, _ = sim.lightcone_records()
+        recs[shrink] = (gid, gx)
+        sim.close()
+    same = np.array_equal(np.sort(recs[1][0]), np.sort(recs[0][0]))
+    dx = None
+    if same:
+        xa = recs[1][1][np.argsort(recs[1][0])]
+        xb = recs[0][1][np.argsort(recs[0][0])]
+        d = np.abs(xa - xb)
+        d = np.minimum(d, box - d)
+        dx = float(d.max() / (box / ng))
+    pks = {s_: _pk(P, torch, recs[s_][1], box, ng) for s_ in (1, 0)}
+    out["lightcone"] = {
+        "box": box, "particles": ng**3, "steps": steps,
+        "records": [int(len(recs[1][0])), int(len(recs[0][0]))], "same_particles": bool(same),
+        "max_position_diff_cells": dx,
+        "pk_raw_max_rel_diff_shrink_vs_fixed": _rel(pks[1]["p_raw"], pks[0]["p_raw"],
+                                                    pks[0]["modes"]),
+        "pk_raw_rel_diff_shrink_vs_fixed": _rel_curve(pks[1]["p_raw"], pks[0]["p_raw"]),
+        "k": [round(float(v), 5) for v in pks[0]["k"][::8]],
+        "pk_raw_fixed": [float(v) for v in pks[0]["p_raw"][::8]],
+        "pk_jing_fixed": [float(v) for v in pks[0]["p"][::8]],
+    }
+    # solvers: static Poisson (FFT) vs diffusion (implicit, ADE), fixed domain
+    box = 500.0
+    ics = zeldovich_ics(ng, box, 1.0 / (1.0 + z0), args.seed + 2)
+    final = {}
+    for name, kw, nst in (("static_fft", dict(c_grav=0.0, solver=P.SDPM_SOLVER_FFT), steps),
+                          ("diffusion_implicit", dict(c_grav=-1.0), steps),
+                          ("diffusion_ade", dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE), steps),
+                          ("diffusion_ade_4x_steps", dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE),
+                           4 * steps)):
+        sim, n = _run_to_end(P, ics, ng, box, z0, nst, shrink=0, sort_every=args.sort_every,
+                             precision=P.SDPM_PLAIN_FP64, **kw)
+        x, _, _ = sim.particles()
+        final[name] = _pk(P, torch, x, box, ng)
+        sim.close()
+    ref = final["static_fft"]
+    out["solvers"] = {
+        "box": box, "particles": ng**3, "steps": steps,
+        "pk_raw_max_rel_diff_vs_static": {k: _rel(v["p_raw"], ref["p_raw"], ref["modes"])
+                                          for k, v in final.items() if k != "static_fft"},
+        "k": [round(float(v), 5) for v in ref["k"][::8]],
+        "pk_raw_rel_diff_vs_static": {k: _rel_curve(v["p_raw"], ref["p_raw"])
+                                      for k, v in final.items() if k != "static_fft"},
+        "pk_raw_static": [float(v) for v in ref["p_raw"][::8]],
+    }
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    log(f"experiments: {json.dumps(out)[:400]}")
+    return out
+
+
 def shrink_phase(P, torch, ics, args):
     """The shrinking phase of the same run: steps 0 .. shrink_from - 1 untimed,
     then shrink_steps steps timed with lightcone removal, the frozen-exterior
@@ -322,6 +432,9 @@ def main():
     ap.add_argument("--shrink-from", type=int, default=160)
     ap.add_argument("--shrink-steps", type=int, default=5)
     ap.add_argument("--no-shrink-phase", action="store_true")
+    ap.add_argument("--no-experiments", action="store_true")
+    ap.add_argument("--exp-ng", type=int, default=128)
+    ap.add_argument("--exp-steps", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this size (a "
                          "known-size kernel that scales hardware byte counters)")
@@ -419,6 +532,7 @@ def main():
     shrink = None
     if not args.no_shrink_phase and args.shrink_from + args.shrink_steps <= args.schedule:
         shrink = shrink_phase(P, torch, ics, args)
+    exps = None if args.no_experiments else experiments(P, torch, args)
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -457,6 +571,7 @@ def main():
         "shrink_phase": shrink,
         "ade_vs_implicit": cmp.get("ade"),
         "fft_vs_implicit": cmp.get("fft"),
+        "experiments": exps,
         "roofline_learned": learned_roofline,
         "net": net_info,
         "cpu_baseline": cpu,

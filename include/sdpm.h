@@ -230,7 +230,14 @@ int sdpm_shrink_radius(sdpm_ctx* ctx, double r, int64_t* n_removed,
  * at u = 0; sdpm_shrink_radius records nothing.  Records are appended in
  * removal order (the order of the stable partition); once `capacity` is
  * reached later records are dropped and the call returns SDPM_EFULL after
- * completing its work.  Device arrays of `capacity` entries, caller-owned.  */
+ * completing its work.  Device arrays of `capacity` entries, caller-owned.
+ * On a fixed domain (shrink == 0) nothing is removed: sdpm_step records the
+ * particles that cross the lightcone during the step, those outside at its
+ * end (the removal test with r_lc(a + da)) that were inside at its start
+ * (the same test with the previous step's end radius, or r_lc(a) for the
+ * first step), with the same crossing formula; they stay in the simulation
+ * and the records of one step come in no particular order.  This is the
+ * lightcone of the run without shrinking that the paper compares against. */
 typedef struct sdpm_lightcone {
   uint32_t* id;
   double* a;

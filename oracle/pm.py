@@ -280,6 +280,14 @@ def outside_lightcone(x: np.ndarray, x_obs: np.ndarray, r_lc: float) -> np.ndarr
     return d2 > r_lc * r_lc
 
 
+def lightcone_crossed(x_start: np.ndarray, x_end: np.ndarray, x_obs: np.ndarray, r_start: float,
+                      r_end: float) -> np.ndarray:
+    """Fixed domain (nothing removed): the particles that cross the lightcone
+    during a step, outside at its end and not outside at its start, each by
+    the removal predicate with that instant's radius."""
+    return outside_lightcone(x_end, x_obs, r_end) & ~outside_lightcone(x_start, x_obs, r_start)
+
+
 def lightcone_crossing(x1: np.ndarray, p1: np.ndarray, x_obs: np.ndarray, r1: float,
                        light: float, disp: float, a1: float, da: float):
     """Where removed particles crossed the lightcone during their last step

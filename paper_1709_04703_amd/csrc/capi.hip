@@ -61,6 +61,11 @@ struct sdpm_ctx {
   sdpm_lightcone lc{};
   bool lc_on = false;
   int64_t lc_count = 0;
+  // fixed domain (shrink == 0): per-particle "outside at the step's start",
+  // the record counter, and the radius at the end of the previous step
+  uint8_t* lc_mark = nullptr;
+  unsigned long long* lc_counter = nullptr;
+  double lc_prev_r = -1.0;
   // solve recording
   float* rec_buf = nullptr;
   int64_t rec_max = 0, rec_count = 0;
@@ -199,6 +204,8 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   double* dscal = (double*)take(64 * sizeof(double));
   uint32_t* dflags = (uint32_t*)take(16 * sizeof(uint32_t));
   uint64_t* dkept = (uint64_t*)take(2 * sizeof(uint64_t));
+  unsigned long long* lcc = (unsigned long long*)take(sizeof(unsigned long long));
+  uint8_t* lcm = (uint8_t*)take((size_t)capacity);
   const size_t nb = (size_t)((capacity + kChunk - 1) / kChunk) + 1;
   uint32_t* bc = (uint32_t*)take(nb * sizeof(uint32_t));
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
@@ -256,6 +263,8 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
     ctx->dscal = dscal;
     ctx->dflags = dflags;
     ctx->dkept = dkept;
+    ctx->lc_counter = lcc;
+    ctx->lc_mark = lcm;
     ctx->bcounts = bc;
     ctx->boffsets = bo;
     ctx->scratch = scr;
@@ -960,6 +969,14 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   HIP_TRY(c, hipEventRecord(c->ev[0], c->st));
   if (g.sort_every > 0 && c->steps_done % g.sort_every == 0) sort_particles(c);
   ++c->steps_done;
+  // lightcone output on a fixed domain: who is outside at the step's start
+  // (the radius at the end of the previous step, or at a for the first)
+  const bool lc_fixed = !g.shrink && c->lc_on && c->n_active > 0;
+  if (lc_fixed) {
+    const double r0 = c->lc_prev_r > 0.0 ? c->lc_prev_r
+                                          : lightcone_radius(a, g.omega_m, g.omega_l, g.c_light);
+    launch_lc_mark(particle_args(c), g.x_obs, r0 * r0, c->lc_mark, c->st);
+  }
   // drift dtau/2 with a(t), then density at t + dt/2   (Table 2 rows 1-2)
   deposit(c, 0.5 * sc.dtau / a, 1);
   HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
@@ -1012,8 +1029,37 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     if (src2 && src2 != SDPM_ENOCONV) return src2;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], c->st));
+  if (lc_fixed) {
+    // record the particles that crossed the lightcone during the step
+    HIP_TRY(c, hipMemsetAsync(c->lc_counter, 0, sizeof(unsigned long long), c->st));
+    LcArgs out;
+    out.id = c->lc.id;
+    out.a = c->lc.a;
+    for (int d = 0; d < 3; ++d) {
+      out.x[d] = c->lc.x[d];
+      out.p[d] = c->lc.p[d];
+    }
+    const double r1 = sc.r_lc_end;
+    if (g.precision == SDPM_MIXED)
+      launch_lc_cross<float>(particle_args(c), g.x_obs, r1 * r1, r1, g.c_light * sc.dtau,
+                             sc.dtau / (a + da), a + da, da, c->lc_mark, out, c->lc_count,
+                             c->lc.capacity, c->lc_counter, c->st);
+    else
+      launch_lc_cross<double>(particle_args(c), g.x_obs, r1 * r1, r1, g.c_light * sc.dtau,
+                              sc.dtau / (a + da), a + da, da, c->lc_mark, out, c->lc_count,
+                              c->lc.capacity, c->lc_counter, c->st);
+    HIP_TRY(c, hipMemcpyAsync(c->hpin + kHostLcCount, c->lc_counter, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->st));
+  }
+  c->lc_prev_r = sc.r_lc_end;
   rc = sync_scalars(c, 1);
   if (rc) return rc;
+  int lc_full = SDPM_OK;
+  if (lc_fixed) {
+    const int64_t crossed = (int64_t)((const unsigned long long*)(c->hpin + kHostLcCount))[0];
+    if (c->lc_count + crossed > c->lc.capacity) lc_full = SDPM_EFULL;
+    c->lc_count = std::min(c->lc_count + crossed, (int64_t)c->lc.capacity);
+  }
   const int ferr = flags_error(c);
   // lightcone at t + dt: eliminate particles and cells  (last row)
   int64_t removed = 0;
@@ -1053,7 +1099,8 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   if (out) *out = st;
   if (ferr) return ferr;
   if (src1) return src1;
-  return src2 ? src2 : full;
+  if (src2) return src2;
+  return full ? full : lc_full;
 }
 
 int sdpm_shrink_radius(sdpm_ctx* c, double r, int64_t* n_removed, uint32_t* removed_ids_dev) {

@@ -21,6 +21,7 @@ constexpr int kNormSlot = 16, kNormRing = 32, kHostNorm = 64, kHostScalars = 128
 // and only while the predicted norm exceeds kAheadMargin * threshold
 constexpr int kMaxAhead = 16;
 constexpr double kAheadMargin = 10.0;
+constexpr int kHostLcCount = 120;      // host slot of the fixed-domain lightcone counter
 constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
 constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
 constexpr int kBoxTy = 4;
@@ -173,6 +174,16 @@ template <typename PT>
 void launch_lightcone(const ParticleArgs& pa, int64_t first, int64_t count, const double* x_obs,
                       double r1, double light, double disp, double a1, double da, const LcArgs& out,
                       int64_t out_first, hipStream_t st);
+// Lightcone output on a fixed domain: marks of the particles outside radius
+// sqrt(r2) at a step's start, then records of those outside at its end and
+// not marked, in slots base + atomic counter (below capacity).
+void launch_lc_mark(const ParticleArgs& pa, const double* x_obs, double r2, uint8_t* mark,
+                    hipStream_t st);
+template <typename PT>
+void launch_lc_cross(const ParticleArgs& pa, const double* x_obs, double r2, double r,
+                     double light, double disp, double a1, double da, const uint8_t* mark,
+                     const LcArgs& out, int64_t base, int64_t capacity,
+                     unsigned long long* counter, hipStream_t st);
 // With g3 != nullptr the force is interpolated from that mesh (made by
 // launch_force_mesh), else from phi directly (FP64 differences).
 template <typename PT>

@@ -332,15 +332,12 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
 // (d = x1 - x_obs, w = p1 dtau / a1, L = c dtau): |d - u w| = r + u L.  For
 // |w| < L (A < 0) and C > 0 there is one positive root, 2 C / (-B + sqrt(D)),
 // the cancellation-free form.
+// The lightcone record of particle i at out slot j (the crossing root u of
+// |x1 - u w - x_obs| = r + u light, w = p1 disp, clamped to [0, 1]).
 template <typename PT>
-__global__ void __launch_bounds__(256)
-k_lightcone(ParticleArgs pa, int64_t first, int64_t count, double o0, double o1, double o2,
-            double r, double light, double disp, double a1, double da, LcArgs out,
-            int64_t out_first) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= count) return;
-  const int64_t i = first + q;
-  const double o[3] = {o0, o1, o2};
+__device__ inline void lc_record(const ParticleArgs& pa, int64_t i, const double o[3], double r,
+                                 double light, double disp, double a1, double da,
+                                 const LcArgs& out, int64_t j) {
   double d[3], w[3], p[3];
   for (int k = 0; k < 3; ++k) {
     p[k] = (double)((const PT*)pa.p[k])[i];
@@ -355,13 +352,48 @@ k_lightcone(ParticleArgs pa, int64_t first, int64_t count, double o0, double o1,
     const double den = -B + sqrt(fmax(B * B - 4.0 * A * C, 0.0));
     u = den > 0.0 ? fmin(2.0 * C / den, 1.0) : 1.0;
   }
-  const int64_t j = out_first + q;
   out.id[j] = pa.id[i];
   out.a[j] = a1 - u * da;
   for (int k = 0; k < 3; ++k) {
     out.x[k][j] = pa.x[k][i] - u * w[k];
     out.p[k][j] = p[k];
   }
+}
+
+template <typename PT>
+__global__ void __launch_bounds__(256)
+k_lightcone(ParticleArgs pa, int64_t first, int64_t count, double o0, double o1, double o2,
+            double r, double light, double disp, double a1, double da, LcArgs out,
+            int64_t out_first) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= count) return;
+  const double o[3] = {o0, o1, o2};
+  lc_record<PT>(pa, first + q, o, r, light, disp, a1, da, out, out_first + q);
+}
+
+// Fixed domain: mark[i] = particle i outside the lightcone at the step's
+// start (the removal predicate with the previous step's end radius).
+__global__ void __launch_bounds__(256)
+k_lc_mark(ParticleArgs pa, double o0, double o1, double o2, double r2, uint8_t* __restrict__ mark) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= pa.n) return;
+  mark[i] = dist2_nofma(pa.x[0][i], pa.x[1][i], pa.x[2][i], o0, o1, o2) > r2 ? 1 : 0;
+}
+
+// Fixed domain: record the particles outside at the step's end that were
+// inside at its start, in slots base + (atomic counter), below capacity.
+template <typename PT>
+__global__ void __launch_bounds__(256)
+k_lc_cross(ParticleArgs pa, double o0, double o1, double o2, double r2, double r, double light,
+           double disp, double a1, double da, const uint8_t* __restrict__ mark, LcArgs out,
+           int64_t base, int64_t capacity, unsigned long long* __restrict__ counter) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= pa.n || mark[i]) return;
+  if (!(dist2_nofma(pa.x[0][i], pa.x[1][i], pa.x[2][i], o0, o1, o2) > r2)) return;
+  const int64_t j = base + (int64_t)atomicAdd(counter, 1ull);
+  if (j >= capacity) return;
+  const double o[3] = {o0, o1, o2};
+  lc_record<PT>(pa, i, o, r, light, disp, a1, da, out, j);
 }
 
 __global__ void __launch_bounds__(256)
@@ -577,6 +609,35 @@ template void launch_lightcone<float>(const ParticleArgs&, int64_t, int64_t, con
 template void launch_lightcone<double>(const ParticleArgs&, int64_t, int64_t, const double*, double,
                                        double, double, double, double, const LcArgs&, int64_t,
                                        hipStream_t);
+
+void launch_lc_mark(const ParticleArgs& pa, const double* x_obs, double r2, uint8_t* mark,
+                    hipStream_t st) {
+  if (pa.n <= 0) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_lc_mark, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
+                     x_obs[2], r2, mark);
+  prof_end(st, K_LIGHTCONE, 25.0 * pa.n);
+}
+
+template <typename PT>
+void launch_lc_cross(const ParticleArgs& pa, const double* x_obs, double r2, double r,
+                     double light, double disp, double a1, double da, const uint8_t* mark,
+                     const LcArgs& out, int64_t base, int64_t capacity,
+                     unsigned long long* counter, hipStream_t st) {
+  if (pa.n <= 0) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(k_lc_cross<PT>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, x_obs[0],
+                     x_obs[1], x_obs[2], r2, r, light, disp, a1, da, mark, out, base, capacity,
+                     counter);
+  // positions and marks of all active particles (records: a small fraction)
+  prof_end(st, K_LIGHTCONE, 25.0 * pa.n);
+}
+template void launch_lc_cross<float>(const ParticleArgs&, const double*, double, double, double,
+                                     double, double, double, const uint8_t*, const LcArgs&,
+                                     int64_t, int64_t, unsigned long long*, hipStream_t);
+template void launch_lc_cross<double>(const ParticleArgs&, const double*, double, double, double,
+                                      double, double, double, const uint8_t*, const LcArgs&,
+                                      int64_t, int64_t, unsigned long long*, hipStream_t);
 
 template <typename PT>
 void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
