@@ -31,6 +31,9 @@ The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
+With --table4 N the paper's Table 4 comparison runs as well: whole runs
+z = 40 -> 0 of N^3 particles in the paper's three boxes, shrinking vs fixed
+domain, timed (opt-in: at N = 512 and 1000 steps it takes a few minutes).
 Two accuracy experiments of the paper, on synthetic 128^3 inputs (experiments):
   lightcone: the 3D power spectrum of the lightcone recorded by a shrinking run
     and by a run on the fixed periodic domain (same diffusion gravity), in a
@@ -310,6 +313,49 @@ def experiments(P, torch, args):
     return out
 
 
+def table4(P, torch, args):
+    """The paper's performance comparison (Table 4): whole runs from z = 40 to
+    0 in `table4_steps` steps uniform in a, with the shrinking domain and on
+    the fixed periodic domain (same diffusion gravity, mixed precision with the
+    extrapolated start), in the paper's three boxes; wall time of the steps
+    and its ratio, beside the ratio of particle updates."""
+    from synth import zeldovich_ics
+    ng, steps, z0 = args.table4, args.table4_steps, 40.0
+    a0 = 1.0 / (1.0 + z0)
+    edges = np.linspace(a0, 1.0, steps + 1)
+    rows = []
+    for box in (512.0, 2048.0, 8192.0):
+        ics = zeldovich_ics(ng, box, a0, args.seed + 3)
+        x, p, ids = ics
+        n = x.shape[0]
+        t, upd = {}, {}
+        for shrink in (0, 1):
+            cfg = P.config_default(ng, box, c_grav=-1.0, shrink=shrink, precision=P.SDPM_MIXED,
+                                   n_initial=n, sort_every=args.sort_every,
+                                   sort_shift=args.sort_shift, warm_start=P.SDPM_WS_EXTRAP)
+            sim = P.Simulation(cfg, n)
+            sim.bind(x, p, ids)
+            sim.init_potential(a0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u = 0
+            for q in range(steps):
+                u += sim.n_active
+                sim.step(edges[q], edges[q + 1] - edges[q])
+            torch.cuda.synchronize()
+            t[shrink], upd[shrink] = time.perf_counter() - t0, u
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            log(f"table4 box {box:g}: shrink={shrink} {t[shrink]:.2f} s")
+        rows.append({"box": box, "seconds_fixed": round(t[0], 3), "seconds_shrink": round(t[1], 3),
+                     "speedup": round(t[0] / t[1], 3),
+                     "particle_update_ratio": round(upd[0] / upd[1], 3)})
+        del ics, x, p, ids
+    return {"particles": ng**3, "steps": steps, "z_init": z0, "rows": rows,
+            "paper_speedups_512^3_1000_steps": {"512": 1.08, "2048": 1.44, "8192": 3.02}}
+
+
 def shrink_phase(P, torch, ics, args):
     """The shrinking phase of the same run: steps 0 .. shrink_from - 1 untimed,
     then shrink_steps steps timed with lightcone removal, the frozen-exterior
@@ -433,6 +479,9 @@ def main():
     ap.add_argument("--shrink-steps", type=int, default=5)
     ap.add_argument("--no-shrink-phase", action="store_true")
     ap.add_argument("--no-experiments", action="store_true")
+    ap.add_argument("--table4", type=int, default=0,
+                    help="mesh/particles per axis for the Table 4 runs (0: skip)")
+    ap.add_argument("--table4-steps", type=int, default=1000)
     ap.add_argument("--exp-ng", type=int, default=128)
     ap.add_argument("--exp-steps", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -533,6 +582,7 @@ def main():
     if not args.no_shrink_phase and args.shrink_from + args.shrink_steps <= args.schedule:
         shrink = shrink_phase(P, torch, ics, args)
     exps = None if args.no_experiments else experiments(P, torch, args)
+    t4 = table4(P, torch, args) if args.table4 else None
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -572,6 +622,7 @@ def main():
         "ade_vs_implicit": cmp.get("ade"),
         "fft_vs_implicit": cmp.get("fft"),
         "experiments": exps,
+        "table4": t4,
         "roofline_learned": learned_roofline,
         "net": net_info,
         "cpu_baseline": cpu,
