@@ -68,7 +68,10 @@ enum { SDPM_WS_PREV = 0, SDPM_WS_LEARNED = 1, SDPM_WS_LEARNED_GATED = 2 };
  * half-step) made in the previous step, scaled by the ratio of the conformal
  * steps (linear extrapolation in time; the first step of a run starts from
  * the previous potential).  Costs two passes over the active box per solve
- * (an FP32 copy of the start, then the change) and three FP32 meshes.      */
+ * (an FP32 copy of the start, then the change) and three FP32 meshes.
+ * Applied while the mesh is periodic; on the frozen-exterior box solves
+ * start from the previous potential (the extrapolation saved no iteration
+ * there).                                                                  */
 enum { SDPM_WS_EXTRAP = 4 };
 /* sdpm_config.solver: how each half sub-step advances the potential by the
  * diffusion equation of Sec. 2.1 Eq. 4.  SDPM_SOLVER_IMPLICIT: one backward-
