@@ -168,16 +168,17 @@ k_residual(const double* __restrict__ phi, const double* __restrict__ rhs, T* __
 // k_residual with 4 consecutive cells per thread (vector loads of phi and
 // rhs, two 2-wide stores per colour of r).  Vectors start at multiples of 4
 // (the box's first x index rounded down); cells outside the box are masked.
-// A tile is 256 x kBoxTy cells x kBoxKz planes.
-template <typename T>
+// A tile is 4 TXV cells x 256 / TXV rows x kBoxKz planes.
+template <typename T, int TXV>
 __global__ void __launch_bounds__(256)
 k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T* __restrict__ rout,
               int n, Box b, double kappa, double* __restrict__ partial) {
   __shared__ double sh[4];
+  constexpr int TY = 256 / TXV;
   const int ib = b.lo[0] & ~3;
-  const Tile tl = tile_of((b.hi[0] - ib + 256) / 256, (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
-  const int i0 = ib + (tl.bx * kBoxTx + threadIdx.x) * 4;
-  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  const Tile tl = tile_of((b.hi[0] - ib + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int i0 = ib + (tl.bx * TXV + threadIdx.x) * 4;
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
   const int m = n - 1;
   double acc = 0.0;
   if (i0 <= b.hi[0] && j <= b.hi[1]) {
@@ -804,18 +805,50 @@ void launch_rhs(const uint64_t* counts, const double* phi, double* rhs, int n, c
   prof_end(st, K_RHS, 24.0 * box_cells(b));
 }
 
+// Threads across a tile row (64, 32 or 16, 4 entries each) for a row of
+// `ext` entries: the width that maximises the share of lanes holding row
+// entries (the last tile of a row is partly empty) times the rate each width
+// reaches on full rows (measured on the 512^3 finest level: 4.77, 4.38 and
+// 4.07 TB/s for 64, 32 and 16 threads), so that a box row of 190 entries
+// takes three 64-entry tiles rather than two of 128.
+inline int tile_threads(int ext) {
+  const int widths[3] = {64, 32, 16};
+  const double rate[3] = {1.0, 0.92, 0.85};
+  int best = 16;
+  double score = -1.0;
+  for (int q = 0; q < 3; ++q) {
+    const int w = 4 * widths[q];
+    const double s = (double)ext / (double)(((ext + w - 1) / w) * w) * rate[q];
+    if (s > score) {
+      score = s;
+      best = widths[q];
+    }
+  }
+  return best;
+}
+
 template <typename T>
 void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
                      double kappa, double* partial, int* nblocks, hipStream_t st) {
   const int ib = b.lo[0] & ~3;
   prof_begin(st);
   if (b.hi[0] - ib + 1 >= 64) {
-    const unsigned gx = (unsigned)((b.hi[0] - ib + 256) / 256);
-    const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy);
+    // tile width as for the colour sweeps (the extent here in cells, 4 per thread)
+    const int txv = tile_threads(b.hi[0] - ib + 1);
+    const unsigned gx = (unsigned)((b.hi[0] - ib + 4 * txv) / (4 * txv));
+    const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + 256 / txv) / (256 / txv));
     const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz);
     *nblocks = (int)(gx * gy * gz);
-    hipLaunchKernelGGL(k_residual_v4<T>, dim3(gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st, phi, rhs,
-                       r_out, n, b, kappa, partial);
+    const dim3 g(gx * gy * gz), blk(txv, 256 / txv);
+    if (txv == 64)
+      hipLaunchKernelGGL((k_residual_v4<T, 64>), g, blk, 0, st, phi, rhs, r_out, n, b, kappa,
+                         partial);
+    else if (txv == 32)
+      hipLaunchKernelGGL((k_residual_v4<T, 32>), g, blk, 0, st, phi, rhs, r_out, n, b, kappa,
+                         partial);
+    else
+      hipLaunchKernelGGL((k_residual_v4<T, 16>), g, blk, 0, st, phi, rhs, r_out, n, b, kappa,
+                         partial);
   } else {
     const dim3 g = box_grid(b);
     *nblocks = (int)(g.x * g.y * g.z);
@@ -928,29 +961,11 @@ void launch_record_accum(const T* e_split, int n, const Box& b, float* dphi, hip
 template void launch_record_accum<float>(const float*, int, const Box&, float*, hipStream_t);
 template void launch_record_accum<double>(const double*, int, const Box&, float*, hipStream_t);
 
-// Vector width of the colour kernels for a level box: 4 cells per thread
-// with 64, 32 or 16 threads across a tile row, 0 (the scalar kernels) for
-// rows under 32 half-row entries.  The width maximises the share of lanes
-// that hold box cells (the last tile of a row is partly empty) times the
-// rate each width reaches on full rows (measured on the 512^3 finest level:
-// 4.77, 4.38 and 4.07 TB/s for 64, 32 and 16 threads), so that a box row of
-// 190 entries takes three 64-entry tiles rather than two of 128.
+// Vector width of the colour kernels for a level box (half-row entries);
+// 0 (the scalar kernels) for rows under 32 entries.
 inline int v4_threads(const Box& b) {
   const int ext = (b.hi[0] >> 1) - ((b.lo[0] >> 1) & ~3) + 1;
-  if (ext < 32) return 0;
-  const int widths[3] = {64, 32, 16};
-  const double rate[3] = {1.0, 0.92, 0.85};
-  int best = 16;
-  double score = -1.0;
-  for (int q = 0; q < 3; ++q) {
-    const int w = 4 * widths[q];
-    const double s = (double)ext / (double)(((ext + w - 1) / w) * w) * rate[q];
-    if (s > score) {
-      score = s;
-      best = widths[q];
-    }
-  }
-  return best;
+  return ext < 32 ? 0 : tile_threads(ext);
 }
 
 inline dim3 v4_grid(const Box& b, int txv) {
