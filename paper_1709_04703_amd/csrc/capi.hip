@@ -933,6 +933,7 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   const LcStep at_a{0.0, 0.0, a, 0.0};
   rc = shrink_impl(c, r, -1, &removed, nullptr, &at_a);
   const int full = rc == SDPM_EFULL ? rc : SDPM_OK;
+  c->lc_prev_r = r;   // the first step's start radius (fixed-domain lightcone)
   if (rc && !full) return rc;
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, full_box(c->cfg.ng), 0ull, c->st);

@@ -51,11 +51,15 @@ int fft_init(FftPlan* p, int n, void* complex_buf, void* work, size_t work_bytes
   p->sym = sym_dev;
   size_t ws_fwd = 0, ws_inv = 0;
   hipfftHandle fwd = 0, inv = 0;
-  if (hipfftCreate(&fwd) != HIPFFT_SUCCESS || hipfftCreate(&inv) != HIPFFT_SUCCESS) {
+  if (hipfftCreate(&fwd) != HIPFFT_SUCCESS) {
     snprintf(msg, len, "hipfftCreate failed");
     return SDPM_EHIP;
   }
-  p->fwd = (void*)fwd;
+  p->fwd = (void*)fwd;   // released by fft_destroy on every later failure
+  if (hipfftCreate(&inv) != HIPFFT_SUCCESS) {
+    snprintf(msg, len, "hipfftCreate failed");
+    return SDPM_EHIP;
+  }
   p->inv = (void*)inv;
   if (hipfftSetAutoAllocation(fwd, 0) != HIPFFT_SUCCESS ||
       hipfftSetAutoAllocation(inv, 0) != HIPFFT_SUCCESS ||
