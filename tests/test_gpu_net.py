@@ -203,8 +203,13 @@ def test_learned_warm_start_trains_and_falls_back():
         sim.close()
     assert res["nan"][1] == 0
     assert np.array_equal(res["nan"][0], res["prev"][0])
-    # every accepted guess lowered the residual; the converged fields agree
+    # every accepted guess lowered the residual; the trained net never costs
+    # iterations (it gains few at this size: 2 of 132 when measured, its 11^3
+    # receptive field reaching about half of the weight of the step's Green's
+    # function); the converged fields agree
     iters_l, used_l, g_l, r_l, phi_l = res["learned"]
+    log(f"  outer iterations over 12 steps: prev {res['prev'][0].sum()}, learned {iters_l.sum()}")
+    assert iters_l.sum() <= res["prev"][0].sum()
     assert np.all(g_l <= r_l)
     assert rel_rms(phi_l, res["prev"][4]) < 1e-5
     assert net_calls["prev"] == 0 and net_calls["learned"] >= 12
