@@ -442,9 +442,16 @@ def cpu_baseline(ics, args):
     t_int = time.perf_counter() - t2
     del phi, phi2, g, f, c
     t_step = t_mesh + (t_dep + t_int) * (n / m)
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                             None)
+    except OSError:
+        pass
     return {
         "value": n / t_step, "unit": "particle-updates/s", "cores": os.cpu_count(),
-        "kind": "oracle",
+        "kind": "oracle", "cpu_model": cpu_model,
         "sample": (f"one {ng}^3 step of the same workload: both FP64 FFT solves and the force "
                    f"mesh timed at full size ({t_mesh:.1f} s), deposit + interpolation + "
                    f"leapfrog timed on the first {m} of {n} particles ({t_dep + t_int:.1f} s) "
@@ -553,6 +560,8 @@ def main():
             "vcycles_per_s": r["vcycles"] / (r["solve_ms"] / 1e3) if r["solve_ms"] > 0 else None,
             "ms_per_step": 1e3 * r["seconds"] / args.steps,
             "outer_iters_per_solve": float(np.mean([sum(i) / 2 for i in r["iters"]])),
+            # wall time of a solve from the step's HIP events (the second with its rhs)
+            "ms_per_solve": r["solve_ms"] / (2.0 * args.steps),
             "final_residual_max": (max(max(s["res"]) for s in r["stats"])
                                    if mode not in ("ade", "fft") else None),
             "kappa_h2": r["stats"][0]["kappa_h2"][0],
