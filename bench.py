@@ -70,9 +70,9 @@ def log(msg):
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
 # Valid only for the kernel source it was measured on: smooth_color is the finest-level
-# non-first sweep, 266435.2 KiB fetched (x 2.0 for the copy's 524310 KiB per GiB) and
-# 262148.7 KiB written per dispatch.
-MEASURED_TRAFFIC = {"smooth_color": 814076663}
+# non-first sweep, 266260.0 KiB fetched (x 2.0 for the copy's 524308 KiB per GiB) and
+# 262144.0 KiB written per dispatch.
+MEASURED_TRAFFIC = {"smooth_color": 813715135}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0

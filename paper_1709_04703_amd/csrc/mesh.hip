@@ -60,6 +60,29 @@ struct alignas(4 * sizeof(T)) Vec4 {
   T v[4];
 };
 
+// Streamed 4-wide loads and stores with the non-temporal hint: for arrays
+// read or written once per pass and far larger than L2, so that they do not
+// displace the data a pass does re-read (stencil neighbours).
+template <typename T>
+__device__ inline Vec4<T> ld_stream4(const T* p) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const v4 t = __builtin_nontemporal_load((const v4*)p);
+  Vec4<T> r;
+  r.v[0] = t.x, r.v[1] = t.y, r.v[2] = t.z, r.v[3] = t.w;
+  return r;
+}
+template <typename T>
+__device__ inline T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ inline void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+template <typename T>
+__device__ inline void st_stream4(T* p, const Vec4<T>& v) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  v4 t;
+  t.x = v.v[0], t.y = v.v[1], t.z = v.v[2], t.w = v.v[3];
+  __builtin_nontemporal_store(t, (v4*)p);
+}
+
 __device__ inline int block_linear() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
@@ -122,8 +145,8 @@ k_rhs(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
     const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
     for (int k = k0; k <= k1; ++k) {
       const int64_t c = lin(i, j, k, n);
-      const double v = (double)counts[c] * c_scale - c_off - kappa * phi[c];
-      rhs[c] = v;
+      const double v = (double)ld_stream(counts + c) * c_scale - c_off - kappa * phi[c];
+      st_stream(rhs + c, v);
       acc += v * v;
     }
   }
@@ -194,6 +217,8 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
       const Vec4<double> above = *(const Vec4<double>*)(phi + lin(i0, j, (k + 1) & m, n));
       const Vec4<double> ym = *(const Vec4<double>*)(phi + lin(i0, jm, k, n));
       const Vec4<double> yp = *(const Vec4<double>*)(phi + lin(i0, jp, k, n));
+      // (the hint measured slower here: the rhs rows are read while the
+      // neighbouring phi rows are still being reused)
       const Vec4<double> rv = *(const Vec4<double>*)(rhs + lin(i0, j, k, n));
       const double xl = phi[lin(il, j, k, n)], xr = phi[lin(ir, j, k, n)];
       double res[4];
@@ -246,7 +271,7 @@ k_correct(double* __restrict__ phi, const T* __restrict__ e, int n, Box b) {
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) {
     const int64_t c = lin(i, j, k, n);
-    phi[c] += (double)e[sidx(i, j, k, n)];
+    phi[c] += (double)ld_stream(e + sidx(i, j, k, n));
   }
 }
 
@@ -359,7 +384,9 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
   for (int k = k0; k <= k1; ++k) {
     const int p = (color + j + k) & 1;          // cell q of the vector: i = 2 (h0 + q) + p
     const int64_t row = ((int64_t)k * n + j) * hn;
-    const Vec4<T> rv = *(const Vec4<T>*)(ro + row + h0);
+    // this colour's r and e are streamed once per sweep; the other colour's e
+    // is what the neighbours re-read, so only it is left to the caches
+    const Vec4<T> rv = FIRST ? *(const Vec4<T>*)(ro + row + h0) : ld_stream4(ro + row + h0);
     T out[4];
     if (FIRST) {
 #pragma unroll
@@ -385,7 +412,10 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
       Vec4<T> o;
 #pragma unroll
       for (int q = 0; q < 4; ++q) o.v[q] = out[q];
-      *(Vec4<T>*)(eo + row + h0) = o;
+      if (FIRST)
+        *(Vec4<T>*)(eo + row + h0) = o;
+      else
+        st_stream4(eo + row + h0, o);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -416,8 +446,8 @@ k_resid_red_v4(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__
     const int p = (j + k) & 1;
     const int kp = (k + 1) & m, km = (k - 1) & m;
     const int64_t row = ((int64_t)k * n + j) * hn;
-    const Vec4<T> ctr = *(const Vec4<T>*)(e + row + h0);
-    const Vec4<T> rv = *(const Vec4<T>*)(r + row + h0);
+    const Vec4<T> ctr = ld_stream4(e + row + h0);
+    const Vec4<T> rv = ld_stream4(r + row + h0);
     const Vec4<T> xc = *(const Vec4<T>*)(e + oth + row + h0);
     const Vec4<T> ym = *(const Vec4<T>*)(e + oth + ((int64_t)k * n + jm) * hn + h0);
     const Vec4<T> yp = *(const Vec4<T>*)(e + oth + ((int64_t)k * n + jp) * hn + h0);

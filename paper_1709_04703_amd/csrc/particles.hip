@@ -115,14 +115,14 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     if (i >= pa.n) continue;
     double x[3];
     for (int d = 0; d < 3; ++d) {
-      double v = pa.x[d][i];
+      double v = __builtin_nontemporal_load(pa.x[d] + i);
       if (DRIFT) {
-        v = drift_nofma(v, (double)((const PT*)pa.p[d])[i], coef);
+        v = drift_nofma(v, (double)__builtin_nontemporal_load((const PT*)pa.p[d] + i), coef);
         if (mm.periodic) {
           if (v < 0.0) v += mm.box;
           if (v >= mm.box) v -= mm.box;
         }
-        pa.x[d][i] = v;
+        __builtin_nontemporal_store(v, pa.x[d] + i);
       }
       x[d] = v;
     }
@@ -295,7 +295,8 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool out = false;
   if (i < pa.n) {
-    double x[3] = {pa.x[0][i], pa.x[1][i], pa.x[2][i]};
+    double x[3] = {__builtin_nontemporal_load(pa.x[0] + i), __builtin_nontemporal_load(pa.x[1] + i),
+                   __builtin_nontemporal_load(pa.x[2] + i)};
     Cic c;
     const uint32_t bad = cic_setup(x, mm, c);
     if (bad) {
@@ -308,14 +309,14 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
         interp_g(phi, mm, c, inv2h, g);
       for (int d = 0; d < 3; ++d) {
         PT* p = (PT*)pa.p[d];
-        const PT pn = (PT)((double)p[i] + g[d] * kick_coef);
-        p[i] = pn;
+        const PT pn = (PT)((double)__builtin_nontemporal_load(p + i) + g[d] * kick_coef);
+        __builtin_nontemporal_store(pn, p + i);
         double v = drift_nofma(x[d], (double)pn, drift_coef);
         if (mm.periodic) {
           if (v < 0.0) v += mm.box;
           if (v >= mm.box) v -= mm.box;
         }
-        pa.x[d][i] = v;
+        __builtin_nontemporal_store(v, pa.x[d] + i);
         x[d] = v;
       }
       if (count_removed) out = dist2_nofma(x[0], x[1], x[2], o0, o1, o2) > r2;
