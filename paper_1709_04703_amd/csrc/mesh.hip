@@ -239,8 +239,13 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
         a.v[1] = (T)res[2];
         bb.v[0] = (T)res[1];
         bb.v[1] = (T)res[3];
-        *(Vec2<T>*)(rout + (int64_t)c0 * hc + row) = a;
-        *(Vec2<T>*)(rout + (int64_t)(c0 ^ 1) * hc + row) = bb;
+        {
+          typedef T v2 __attribute__((ext_vector_type(2)));
+          v2 ta, tb;
+          ta.x = a.v[0], ta.y = a.v[1], tb.x = bb.v[0], tb.y = bb.v[1];
+          __builtin_nontemporal_store(ta, (v2*)(rout + (int64_t)c0 * hc + row));
+          __builtin_nontemporal_store(tb, (v2*)(rout + (int64_t)(c0 ^ 1) * hc + row));
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc += res[q] * res[q];
       } else {
