@@ -150,7 +150,8 @@ def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, 
                            sort_every=args.sort_every, sort_shift=args.sort_shift,
                            warm_start=(P.SDPM_WS_PREV if weights is None else
                                        P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
-                           | (P.SDPM_WS_EXTRAP if extrap else 0), solver=solver)
+                           | (P.SDPM_WS_EXTRAP if extrap else 0), solver=solver,
+                           cycles_per_outer=args.cycles_per_outer)
     sim = P.Simulation(cfg, n)
     if weights is not None:
         sim.set_warmstart_weights(weights)
@@ -477,6 +478,8 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=400)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--cycles-per-outer", type=int, default=2, choices=(1, 2),
+                    help="V-cycles per FP64 defect-correction iteration, at most")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--sort-shift", type=int, default=4,
                     help="Morton key of cell blocks of 2^shift cells per axis")
@@ -560,6 +563,7 @@ def main():
             "vcycles_per_s": r["vcycles"] / (r["solve_ms"] / 1e3) if r["solve_ms"] > 0 else None,
             "ms_per_step": 1e3 * r["seconds"] / args.steps,
             "outer_iters_per_solve": float(np.mean([sum(i) / 2 for i in r["iters"]])),
+            "vcycles_per_solve": r["vcycles"] / (2.0 * args.steps),
             # wall time of a solve from the step's HIP events (the second with its rhs)
             "ms_per_solve": r["solve_ms"] / (2.0 * args.steps),
             "final_residual_max": (max(max(s["res"]) for s in r["stats"])

@@ -55,7 +55,7 @@ class Config(ctypes.Structure):
         ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
         ("warm_start", ctypes.c_int32), ("n_initial", ctypes.c_int64),
         ("sort_every", ctypes.c_int32), ("sort_shift", ctypes.c_int32),
-        ("solver", ctypes.c_int32),
+        ("solver", ctypes.c_int32), ("cycles_per_outer", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

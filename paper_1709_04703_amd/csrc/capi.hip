@@ -54,8 +54,8 @@ struct sdpm_ctx {
   bool ex_have[2] = {false, false};
   double ex_dtau[2] = {0.0, 0.0};
   double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
-  // residual reduction per outer iteration of the last solve (geometric
-  // mean), used to run ahead of the host without a sync per iteration
+  // residual reduction per V-cycle of the last solve (geometric mean), used
+  // to run ahead of the host without a sync per iteration and to pair cycles
   double rho_est = 0.1;
   // lightcone output
   sdpm_lightcone lc{};
@@ -163,6 +163,8 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE &&
       c->solver != SDPM_SOLVER_FFT)
     return snprintf(msg, len, "unknown solver %d", c->solver), SDPM_EINVAL;
+  if (c->cycles_per_outer != 1 && c->cycles_per_outer != 2)
+    return snprintf(msg, len, "cycles_per_outer must be 1 or 2"), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_FFT && c->warm_start != SDPM_WS_PREV)
     return snprintf(msg, len, "the FFT solver takes warm_start SDPM_WS_PREV"), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_ADE && (c->c_grav == 0.0 || c->warm_start != SDPM_WS_PREV))
@@ -527,20 +529,29 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     }
   }
   so->res_guess = rn / denom;
-  int it = 0;
+  int it = 0, cyc = 0;
   const double rn_start = rn;
   // Outer iterations are enqueued without waiting for their residual norm
   // while the norm predicted from the last known one and the convergence
-  // factor of the previous solve stays well above the threshold; then the
-  // host waits and reads the norms.  A wrong prediction can only add
+  // factor per V-cycle of the previous solve stays well above the threshold;
+  // then the host waits and reads the norms.  A wrong prediction can only add
   // iterations (the residual keeps falling), never stop early.
+  // An outer iteration runs two V-cycles on its defect equation when one is
+  // predicted, with margin, to leave the norm above the threshold: the second
+  // cycle reduces the error as a further outer iteration would (the working
+  // precision's rounding floor lies far below the factor of two cycles) and
+  // saves that iteration's FP64 correction and residual passes.
   double rn_known = rn;
-  int it_known = 0;
+  int it_known = 0, cyc_known = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
     const bool time_it = gated && it == 0;
+    const double pred_now = rn_known * std::pow(c->rho_est, cyc - cyc_known);
+    const int ncyc = (g.cycles_per_outer == 2 && pred_now * c->rho_est > kPairMargin * thresh) ? 2 : 1;
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
-    const T* e0 =
-        vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0, c->st);
+    const T* e0 = nullptr;
+    for (int q = 0; q < ncyc; ++q)
+      e0 = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
+                     q > 0, c->st);
     launch_correct<T>(c->fields.phi, e0, g.ng, b, c->st);
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
@@ -548,36 +559,41 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     launch_reduce_final(c->partial, nb, 1, c->dscal + kNormSlot + (it % kNormRing), c->st);
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
     ++it;
-    const int ahead = it - it_known;
-    const double pred = rn_known * std::pow(c->rho_est, ahead);
-    if (!time_it && it < g.max_outer && ahead < kMaxAhead && pred > kAheadMargin * thresh) continue;
+    cyc += ncyc;
+    const double pred = rn_known * std::pow(c->rho_est, cyc - cyc_known);
+    if (!time_it && it < g.max_outer && it - it_known < kMaxAhead && pred > kAheadMargin * thresh)
+      continue;
     rc = sync_norms(c);
     if (rc) return rc;
     if (time_it) {
+      // cost of one V-cycle with its share of the outer iteration's passes
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess)
-        c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + ms) : ms;
+      if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess) {
+        const double per = ms / ncyc;
+        c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + per) : per;
+      }
     }
     rn = std::sqrt(c->hpin[kHostNorm + (it - 1) % kNormRing]);
     rn_known = rn;
     it_known = it;
+    cyc_known = cyc;
   }
-  if (it > 0 && rn > 0.0 && rn_start > 0.0 && std::isfinite(rn)) {
-    const double rho = std::pow(rn / rn_start, 1.0 / it);
+  if (cyc > 0 && rn > 0.0 && rn_start > 0.0 && std::isfinite(rn)) {
+    const double rho = std::pow(rn / rn_start, 1.0 / cyc);
     if (rho > 0.0 && rho < 1.0) c->rho_est = std::min(std::max(rho, 1e-3), 0.9);
   }
   if (gated && net_ran) {
-    // outer iterations the guess saved: its residual reduction measured in
-    // this solve's own convergence factor per iteration; keep the net for
+    // V-cycles the guess saved: its residual reduction measured in this
+    // solve's own convergence factor per cycle; keep the net for
     // this sub-step kind while that exceeds its cost in iterations, else skip
     // it for a number of solves that doubles with every failed try and scales
     // with how far the net is from paying (cost / saving)
     double saved = 0.0;
     if (so->warm) {
-      if (it == 0) {
+      if (cyc == 0) {
         saved = 1e30;
       } else if (rn > 0.0 && rn_start > 0.0) {
-        const double rho = std::pow(rn / rn_start, 1.0 / it);
+        const double rho = std::pow(rn / rn_start, 1.0 / cyc);
         if (rho > 0.0 && rho < 1.0) saved = std::log(rn_prev / rn_start) / std::log(1.0 / rho);
       }
     }
@@ -593,7 +609,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     }
   }
   so->iters = it;
-  so->vcycles = it;
+  so->vcycles = cyc;
   so->res = rn / denom;
   if (c->periodic && kappa == 0.0) {
     // zero-mean gauge of the singular periodic Poisson problem
@@ -776,6 +792,7 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->sort_every = 0;
   cfg->sort_shift = ng >= 64 ? 4 : 0;   // Morton order of 16^3-cell blocks
   cfg->solver = SDPM_SOLVER_IMPLICIT;
+  cfg->cycles_per_outer = 2;
   return SDPM_OK;
 }
 

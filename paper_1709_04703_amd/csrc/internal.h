@@ -21,6 +21,10 @@ constexpr int kNormSlot = 16, kNormRing = 32, kHostNorm = 64, kHostScalars = 128
 // and only while the predicted norm exceeds kAheadMargin * threshold
 constexpr int kMaxAhead = 16;
 constexpr double kAheadMargin = 10.0;
+// two V-cycles per outer iteration only while one is predicted to leave the
+// norm above kPairMargin * threshold (a needless second cycle costs about
+// twice what a further outer iteration's FP64 passes do)
+constexpr double kPairMargin = 2.0;
 constexpr int kHostLcCount = 120;      // host slot of the fixed-domain lightcone counter
 constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
 constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
@@ -132,10 +136,12 @@ int power_spectrum(const double* const x[3], int64_t npart, double box, int n, i
 // One ADE sweep of phi over box b with source f (ade.hip).
 void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool periodic, double lam,
                       bool forward, hipStream_t st);
-// One V-cycle for A_0 e = r_0; returns the level-0 buffer holding e.
+// One V-cycle for A_0 e = r_0; returns the level-0 buffer holding e.  With
+// fine_start the cycle improves the e already on level 0 (a further cycle on
+// the same r_0), else it starts from e = 0.
 template <typename T>
 const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
-                bool periodic, hipStream_t st);
+                bool periodic, bool fine_start, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Launchers, particle kernels (particles.hip).

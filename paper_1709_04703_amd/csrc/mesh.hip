@@ -1084,7 +1084,7 @@ static void resid_red(const T* e, const T* r, T* t, const Level& L, T inv_scale,
 
 template <typename T>
 const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
-                bool periodic, hipStream_t st) {
+                bool periodic, bool fine_start, hipStream_t st) {
   const dim3 blk(kBoxTx, kBoxTy);
   const double es = sizeof(T);
   for (int l = 0; l < nlev - 1; ++l) {
@@ -1095,7 +1095,10 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     T* e = (T*)L.e;
     const T* r = (const T*)L.r;
     for (int s = 0; s < pre; ++s) {
-      smooth_color<T>(e, r, L, l, 0, s == 0, scale, inv_diag, st);
+      // the first red pass assumes e = 0, except on the finest level when
+      // the cycle continues from the correction already there
+      const bool zero_guess = s == 0 && !(l == 0 && fine_start);
+      smooth_color<T>(e, r, L, l, 0, zero_guess, scale, inv_diag, st);
       smooth_color<T>(e, r, L, l, 1, false, scale, inv_diag, st);
     }
     resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
@@ -1159,7 +1162,9 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
   }
   return (const T*)lv[0].e;
 }
-template const float* vcycle<float>(const Level*, int, double, int, int, int, bool, hipStream_t);
-template const double* vcycle<double>(const Level*, int, double, int, int, int, bool, hipStream_t);
+template const float* vcycle<float>(const Level*, int, double, int, int, int, bool, bool,
+                                    hipStream_t);
+template const double* vcycle<double>(const Level*, int, double, int, int, int, bool, bool,
+                                      hipStream_t);
 
 }  // namespace sdpm

@@ -191,24 +191,24 @@ def test_learned_warm_start_trains_and_falls_back():
         for s in range(12):
             st = sim.step(edges[s], edges[s + 1] - edges[s])
             assert max(st["res"]) <= cfg.tol
-            iters.append(sum(st["outer_iters"]))
+            iters.append(st["vcycles"])
             used += st["warm_used"]
             g0.append(st["res_guess"][0])
             r0.append(st["res0"][0])
         res[mode] = (np.array(iters), used, np.array(g0), np.array(r0), sim.phi_numpy().copy())
         net_calls[mode] = sim.profile_read().get("conv3d_mfma", {}).get("launches", 0) // 5
-        log(f"  {mode}: iterations {iters} guesses used {used} "
+        log(f"  {mode}: V-cycles {iters} guesses used {used} "
             f"median res0 {np.median(r0):.2e} -> guess {np.median(g0):.2e} "
             f"net calls {net_calls[mode]}")
         sim.close()
     assert res["nan"][1] == 0
     assert np.array_equal(res["nan"][0], res["prev"][0])
     # every accepted guess lowered the residual; the trained net never costs
-    # iterations (it gains few at this size: 2 of 132 when measured, its 11^3
+    # V-cycles (it gains few at this size: 2 of 132 when measured, its 11^3
     # receptive field reaching about half of the weight of the step's Green's
     # function); the converged fields agree
     iters_l, used_l, g_l, r_l, phi_l = res["learned"]
-    log(f"  outer iterations over 12 steps: prev {res['prev'][0].sum()}, learned {iters_l.sum()}")
+    log(f"  V-cycles over 12 steps: prev {res['prev'][0].sum()}, learned {iters_l.sum()}")
     assert iters_l.sum() <= res["prev"][0].sum()
     assert np.all(g_l <= r_l)
     assert rel_rms(phi_l, res["prev"][4]) < 1e-5

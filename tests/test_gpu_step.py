@@ -159,7 +159,7 @@ def test_step_argument_errors():
 def test_extrapolated_start_same_solution_fewer_iterations():
     """SDPM_WS_EXTRAP: every solve still reaches tol, the run ends in the same
     state as with the previous-potential start (to the solve tolerance), and
-    the extrapolated start needs fewer outer iterations."""
+    the extrapolated start needs fewer V-cycles."""
     import paper_1709_04703_amd as P
     ng, box, a0, nsteps = 64, 2000.0, 1.0 / 50.0, 40
     x, p, ids = zeldovich_ics(ng, box, a0, 21)
@@ -174,13 +174,51 @@ def test_extrapolated_start_same_solution_fewer_iterations():
         for s in range(12):
             st = sim.step(edges[s], edges[s + 1] - edges[s])
             assert max(st["res"]) <= cfg.tol
-            iters.append(st["outer_iters"])
+            iters.append(st["vcycles"])
         gx, gp, gid = sim.particles()
         out[name] = (iters, sim.phi_numpy().copy(), _by_id(gx, gid))
         sim.close()
-        log(f"  {name}: outer iterations {iters}")
-    tot = {k: sum(sum(i) for i in v[0]) for k, v in out.items()}
+        log(f"  {name}: V-cycles {iters}")
+    tot = {k: sum(v[0]) for k, v in out.items()}
     assert tot["extrap"] < tot["prev"]
     assert rel_rms(out["extrap"][1], out["prev"][1]) < 1e-5
     dx = periodic_delta(out["extrap"][2], out["prev"][2], box)
+    assert np.abs(dx).max() < 1e-5 * box / ng
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paired_cycles_same_state_fewer_outer_iterations(prec):
+    """cycles_per_outer = 2 (two V-cycles on one defect equation) against 1:
+    every solve reaches tol, the runs end in the same state to the solve
+    tolerance, the V-cycle count is the same up to one needless second cycle
+    per solve (a wrong prediction of the factor per cycle), and the outer
+    iterations (FP64 correction and residual passes) are fewer."""
+    ng, box, a0, nsteps = 64, 2000.0, 1.0 / 50.0, 40
+    x, p, ids = zeldovich_ics(ng, box, a0, 33)
+    edges = np.linspace(a0, 1.0, nsteps + 1)
+    out = {}
+    for cpo in (1, 2):
+        cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3, precision=prec,
+                         cycles_per_outer=cpo)
+        sim = make_sim(cfg, ng**3)
+        sim.bind(x, p, ids)
+        sim.init_potential(a0)
+        outer, cyc = 0, 0
+        for s in range(12):
+            st = sim.step(edges[s], edges[s + 1] - edges[s])
+            assert max(st["res"]) <= cfg.tol
+            outer += sum(st["outer_iters"])
+            cyc += st["vcycles"]
+            if cpo == 1:
+                assert st["vcycles"] == sum(st["outer_iters"])
+            else:
+                assert sum(st["outer_iters"]) <= st["vcycles"] <= 2 * sum(st["outer_iters"])
+        gx, gp, gid = sim.particles()
+        out[cpo] = (outer, cyc, sim.phi_numpy().copy(), _by_id(gx, gid))
+        sim.close()
+        log(f"  precision={prec} cycles_per_outer={cpo}: outer iterations {outer}, V-cycles {cyc}")
+    assert out[2][0] < out[1][0]
+    assert out[2][1] <= out[1][1] + 24          # 12 steps x 2 solves
+    assert rel_rms(out[2][2], out[1][2]) < 1e-5
+    dx = periodic_delta(out[2][3], out[1][3], box)
     assert np.abs(dx).max() < 1e-5 * box / ng
