@@ -478,7 +478,7 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=400)
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
-    ap.add_argument("--cycles-per-outer", type=int, default=2, choices=(1, 2),
+    ap.add_argument("--cycles-per-outer", type=int, default=4, choices=(1, 2, 3, 4),
                     help="V-cycles per FP64 defect-correction iteration, at most")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--sort-shift", type=int, default=4,

@@ -120,11 +120,14 @@ typedef struct sdpm_config {
                             cells per axis (stable: particles keep their
                             order inside a block); default 4 for ng >= 64    */
   int32_t solver;        /* SDPM_SOLVER_IMPLICIT (default), _ADE or _FFT        */
-  int32_t cycles_per_outer; /* V-cycles per defect-correction iteration, at most:
-                            1, or 2 (default): two cycles on the same defect
-                            equation whenever one is predicted (from the last
-                            solve's factor per cycle) to leave the residual
-                            above tol; the result meets tol either way        */
+  int32_t cycles_per_outer; /* V-cycles per defect-correction iteration, at most
+                            (1..4, default 4): further cycles on the same
+                            defect equation while fewer are predicted (from
+                            the last solve's factor per cycle) to leave the
+                            residual above tol and their combined factor
+                            stays well above the rounding floor of the
+                            stored correction; the result meets tol either
+                            way                                              */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <vector>
 #include <utility>
 
@@ -163,8 +164,8 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE &&
       c->solver != SDPM_SOLVER_FFT)
     return snprintf(msg, len, "unknown solver %d", c->solver), SDPM_EINVAL;
-  if (c->cycles_per_outer != 1 && c->cycles_per_outer != 2)
-    return snprintf(msg, len, "cycles_per_outer must be 1 or 2"), SDPM_EINVAL;
+  if (c->cycles_per_outer < 1 || c->cycles_per_outer > kMaxCyclesPerOuter)
+    return snprintf(msg, len, "cycles_per_outer must be in 1..%d", kMaxCyclesPerOuter), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_FFT && c->warm_start != SDPM_WS_PREV)
     return snprintf(msg, len, "the FFT solver takes warm_start SDPM_WS_PREV"), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_ADE && (c->c_grav == 0.0 || c->warm_start != SDPM_WS_PREV))
@@ -536,17 +537,43 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   // factor per V-cycle of the previous solve stays well above the threshold;
   // then the host waits and reads the norms.  A wrong prediction can only add
   // iterations (the residual keeps falling), never stop early.
-  // An outer iteration runs two V-cycles on its defect equation when one is
-  // predicted, with margin, to leave the norm above the threshold: the second
-  // cycle reduces the error as a further outer iteration would (the working
-  // precision's rounding floor lies far below the factor of two cycles) and
-  // saves that iteration's FP64 correction and residual passes.
+  // An outer iteration runs further V-cycles on its defect equation (up to
+  // cycles_per_outer) while fewer are predicted, with margin, to leave the
+  // norm above the threshold: each further cycle reduces the error as a
+  // further outer iteration would (the working precision's rounding floor
+  // lies far below the factor of four cycles) and saves that iteration's FP64
+  // correction and residual passes.
+  // The cycles of one outer iteration cannot take the defect below the
+  // rounding of the correction they store in T: |A de| <= (12 + kappa h^2)
+  // (eps_T / 2) |e| with |e| <= |r| / (kappa h^2 + lambda_min), the extreme
+  // eigenvalues of the 7-point operator, lambda_min that of the domain's
+  // lowest mode (non-constant when periodic; a lower bound, the Dirichlet
+  // mode of the box's longest side, otherwise).  Further cycles are added
+  // only while their combined factor stays above that worst-case floor: at
+  // kappa h^2 = 0.113 in FP32 (floor 6.4e-6) it allows four cycles of factor
+  // above 0.05, for the 512^3 Poisson solve (kappa = 0, floor 4.8e-3) two of
+  // factor above 0.07.
+  double lam_min;
+  {
+    const int ext = std::max(b.hi[0] - b.lo[0], std::max(b.hi[1] - b.lo[1], b.hi[2] - b.lo[2])) + 1;
+    const double sn = c->periodic ? std::sin(M_PI / g.ng) : std::sin(M_PI / (2.0 * (ext + 1)));
+    lam_min = 4.0 * sn * sn;
+  }
+  const double floor_rel =
+      0.5 * (double)std::numeric_limits<T>::epsilon() * (12.0 + kappa) / (kappa + lam_min);
   double rn_known = rn;
   int it_known = 0, cyc_known = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
     const bool time_it = gated && it == 0;
-    const double pred_now = rn_known * std::pow(c->rho_est, cyc - cyc_known);
-    const int ncyc = (g.cycles_per_outer == 2 && pred_now * c->rho_est > kPairMargin * thresh) ? 2 : 1;
+    double pred_next = rn_known * std::pow(c->rho_est, cyc - cyc_known + 1);
+    double factor = c->rho_est;
+    int ncyc = 1;
+    while (ncyc < g.cycles_per_outer && pred_next > kPairMargin * thresh &&
+           factor * c->rho_est > kFloorMargin * floor_rel) {
+      ++ncyc;
+      pred_next *= c->rho_est;
+      factor *= c->rho_est;
+    }
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
     const T* e0 = nullptr;
     for (int q = 0; q < ncyc; ++q)
@@ -792,7 +819,7 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->sort_every = 0;
   cfg->sort_shift = ng >= 64 ? 4 : 0;   // Morton order of 16^3-cell blocks
   cfg->solver = SDPM_SOLVER_IMPLICIT;
-  cfg->cycles_per_outer = 2;
+  cfg->cycles_per_outer = 4;
   return SDPM_OK;
 }
 

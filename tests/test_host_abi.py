@@ -90,12 +90,13 @@ def test_solver_config_validation(P):
                 dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE, warm_start=P.SDPM_WS_EXTRAP),
                 dict(c_grav=-1.0, solver=3),
                 dict(solver=P.SDPM_SOLVER_FFT, warm_start=P.SDPM_WS_EXTRAP),
-                dict(cycles_per_outer=0), dict(cycles_per_outer=3)):
+                dict(cycles_per_outer=0), dict(cycles_per_outer=5)):
         with pytest.raises(P.SdpmError, match="EINVAL"):
             P.workspace_bytes(P.config_default(64, 100.0, **bad), 10)
     assert P.config_default(64, 100.0).solver == P.SDPM_SOLVER_IMPLICIT
-    assert P.config_default(64, 100.0).cycles_per_outer == 2
-    assert P.workspace_bytes(P.config_default(64, 100.0, cycles_per_outer=1), 10) > 0
+    assert P.config_default(64, 100.0).cycles_per_outer == 4
+    for cpo in (1, 4):
+        assert P.workspace_bytes(P.config_default(64, 100.0, cycles_per_outer=cpo), 10) > 0
     # the FFT solver's half spectrum and work area come from the workspace
     fft = P.config_default(64, 100.0, solver=P.SDPM_SOLVER_FFT)
     assert (P.workspace_bytes(fft, 10) - P.workspace_bytes(P.config_default(64, 100.0), 10)
