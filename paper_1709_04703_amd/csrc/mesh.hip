@@ -587,6 +587,138 @@ k_prolong(const T* __restrict__ ec, T* __restrict__ ef, int nc, int nf, Box bf, 
   }
 }
 
+// FP32 forms of the restriction and of the black-cell prolongation with 4
+// cells per thread in the tiles of k_smooth_color_v4 (256 threads, TXV
+// across a row), so that the fine level is read and written in aligned
+// 16-byte vectors.  They need n_fine / 2 and n_coarse / 2 to be multiples of
+// 4 and 2 (the host takes them for fine boxes of at least 64 cells a row).
+//
+// Restriction of 4 coarse cells I0 .. I0 + 3 (I0 a multiple of 4): the red
+// fine cells of k_restrict's stencil lie at half index I in the rows whose
+// offsets (o_y, o_z) are both even or both odd (the centre and the four
+// diagonal rows) and at half indices I - 1 and I in the other four rows, so
+// each fine row is one vector (plus the value before it).  The coarse cells
+// alternate colours: I0 and I0 + 2 are one aligned pair of one colour's half,
+// I0 + 1 and I0 + 3 the pair at the same offset in the other half.
+template <int TXV>
+__global__ void __launch_bounds__(256)
+k_restrict_v4(const float* __restrict__ tf, float* __restrict__ rc, int nf, int nc, Box bc) {
+  constexpr int TY = 256 / TXV;
+  const int ib = bc.lo[0] & ~3;
+  const Tile tl = tile_of((bc.hi[0] - ib + 4 * TXV) / (4 * TXV), (bc.hi[1] - bc.lo[1] + TY) / TY);
+  const int J = bc.lo[1] + tl.by * TY + threadIdx.y;
+  const int I0 = ib + (tl.bx * TXV + threadIdx.x) * 4;
+  if (J > bc.hi[1] || I0 > bc.hi[0]) return;
+  const int m = nf - 1, hn = nf >> 1, hnc = nc >> 1;
+  const int64_t hcc = half_cells(nc);
+  const int K0 = bc.lo[2] + tl.bz * kVecKz;
+  const int K1 = min(K0 + kVecKz - 1, bc.hi[2]);
+  const int j = 2 * J, jm = (j - 1) & m, jp = (j + 1) & m;
+  const int before = (I0 - 1) & (hn - 1);
+  for (int K = K0; K <= K1; ++K) {
+    const int k = 2 * K, km = (k - 1) & m, kp = (k + 1) & m;
+    auto row = [&](int y, int z) { return tf + ((int64_t)z * nf + y) * hn; };
+    const Vec4<float> centre = *(const Vec4<float>*)(row(j, k) + I0);
+    float edges[4] = {0.f, 0.f, 0.f, 0.f};
+    const int pr[4][2] = {{jm, k}, {jp, k}, {j, km}, {j, kp}};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float* rp = row(pr[t][0], pr[t][1]);
+      const Vec4<float> v = *(const Vec4<float>*)(rp + I0);
+      const float b = rp[before];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) edges[q] += (q == 0 ? b : v.v[q - 1]) + v.v[q];
+    }
+    const int dg[4][2] = {{jm, km}, {jp, km}, {jm, kp}, {jp, kp}};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const Vec4<float> v = *(const Vec4<float>*)(row(dg[t][0], dg[t][1]) + I0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) edges[q] += v.v[q];
+    }
+    float out[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = 0.125f * centre.v[q] + 0.03125f * edges[q];
+    const int s = (J + K) & 1;                  // colour of coarse cell I0
+    const int64_t crow = ((int64_t)K * nc + J) * hnc + (I0 >> 1);
+    if (I0 >= bc.lo[0] && I0 + 3 <= bc.hi[0]) {
+      Vec2<float> a, b;
+      a.v[0] = out[0], a.v[1] = out[2];
+      b.v[0] = out[1], b.v[1] = out[3];
+      *(Vec2<float>*)(rc + s * hcc + crow) = a;
+      *(Vec2<float>*)(rc + (s ^ 1) * hcc + crow) = b;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (I0 + q >= bc.lo[0] && I0 + q <= bc.hi[0])
+          rc[((s + q) & 1) * hcc + crow + (q >> 1)] = out[q];
+    }
+  }
+}
+
+// Black-cell prolongation (k_prolong without all_cells) for the 4 black
+// cells 2 (h0 + q) + p of a fine row: cell q takes coarse x h0 + q and
+// h0 + q + p, so the row needs coarse x h0 .. h0 + 4 from each coarse row
+// (Y, Z) it draws on: two aligned pairs (one per colour half) and one more
+// value.  Rows coinciding with a coarse row (even j or k) are summed once
+// and weighted twice.
+template <int TXV>
+__global__ void __launch_bounds__(256)
+k_prolong_black_v4(const float* __restrict__ ec, float* __restrict__ ef, int nc, int nf, Box bf) {
+  constexpr int TY = 256 / TXV;
+  const int hb = (bf.lo[0] >> 1) & ~3, hhi = bf.hi[0] >> 1;
+  const Tile tl = tile_of((hhi - hb + 4 * TXV) / (4 * TXV), (bf.hi[1] - bf.lo[1] + TY) / TY);
+  const int j = bf.lo[1] + tl.by * TY + threadIdx.y;
+  const int h0 = hb + (tl.bx * TXV + threadIdx.x) * 4;
+  if (j > bf.hi[1] || h0 > hhi) return;
+  const int mc = nc - 1, hnf = nf >> 1, hnc = nc >> 1;
+  const int64_t hcf = half_cells(nf), hcc = half_cells(nc);
+  const int k0 = bf.lo[2] + tl.bz * kVecKz;
+  const int k1 = min(k0 + kVecKz - 1, bf.hi[2]);
+  const int ny = 1 + (j & 1);
+  const int Ys[2] = {j >> 1, ((j >> 1) + 1) & mc};
+  const int c0 = h0 >> 1;                       // coarse half index of x = h0 (h0 even)
+  const int c4 = ((h0 + 4) & mc) >> 1;          // ... of x = h0 + 4 (even, same colour)
+  for (int k = k0; k <= k1; ++k) {
+    const int p = (1 + j + k) & 1;
+    const int nz = 1 + (k & 1);
+    const int Zs[2] = {k >> 1, ((k >> 1) + 1) & mc};
+    float L[5] = {0.f, 0.f, 0.f, 0.f, 0.f};   // summed coarse rows at x = h0 + q
+    for (int zz = 0; zz < nz; ++zz) {
+      for (int yy = 0; yy < ny; ++yy) {
+        const int Y = Ys[yy], Z = Zs[zz];
+        const int s = (Y + Z) & 1;             // colour of coarse x = h0
+        const float* crow = ec + ((int64_t)Z * nc + Y) * hnc;
+        const Vec2<float> ev = *(const Vec2<float>*)(crow + s * hcc + c0);        // x = h0, h0 + 2
+        const Vec2<float> od = *(const Vec2<float>*)(crow + (s ^ 1) * hcc + c0);  // h0 + 1, h0 + 3
+        L[0] += ev.v[0];
+        L[1] += od.v[0];
+        L[2] += ev.v[1];
+        L[3] += od.v[1];
+        L[4] += crow[s * hcc + c4];
+      }
+    }
+    const float w = 0.125f * (float)((3 - ny) * (3 - nz));
+    const int64_t frow = hcf + ((int64_t)k * nf + j) * hnf + h0;
+    const Vec4<float> e = *(const Vec4<float>*)(ef + frow);
+    float out[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = e.v[q] + w * (L[q] + (p ? L[q + 1] : L[q]));
+    if (2 * h0 + p >= bf.lo[0] && 2 * h0 + 6 + p <= bf.hi[0]) {
+      Vec4<float> o;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o.v[q] = out[q];
+      *(Vec4<float>*)(ef + frow) = o;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 2 * (h0 + q) + p;
+        if (i >= bf.lo[0] && i <= bf.hi[0]) ef[frow + q] = out[q];
+      }
+    }
+  }
+}
+
 // Coarsest level: one workgroup; e lives in LDS on a box-local array of at
 // most kCoarseMax^3 entries: the whole (periodic) level, or the box plus a
 // one-cell ring of zeros (Dirichlet).  Each thread owns up to kCoarseMax^3 /
@@ -1082,6 +1214,57 @@ static void resid_red(const T* e, const T* r, T* t, const Level& L, T inv_scale,
   prof_end(st, K_RESID_LEVEL, 2.0 * sizeof(T) * (double)box_cells(b));
 }
 
+// r_C = restriction of L's red residual t; the vector form for FP32 levels
+// whose fine box takes the vector sweeps.
+template <typename T>
+static void restrict_level(const Level& L, const Level& C, hipStream_t st) {
+  const Box& bc = C.box;
+  if constexpr (sizeof(T) == 4) {
+    if (v4_threads(L.box)) {
+      const int txv = tile_threads(bc.hi[0] - (bc.lo[0] & ~3) + 1);
+      const int ty = 256 / txv;
+      const unsigned gx = (unsigned)((bc.hi[0] - (bc.lo[0] & ~3) + 4 * txv) / (4 * txv));
+      const unsigned gy = (unsigned)((bc.hi[1] - bc.lo[1] + ty) / ty);
+      const unsigned gz = (unsigned)((bc.hi[2] - bc.lo[2] + kVecKz) / kVecKz);
+      const dim3 g(gx * gy * gz), blk(txv, ty);
+      const float* t = (const float*)L.t;
+      float* r = (float*)C.r;
+      if (txv == 64)
+        hipLaunchKernelGGL(k_restrict_v4<64>, g, blk, 0, st, t, r, L.n, C.n, bc);
+      else if (txv == 32)
+        hipLaunchKernelGGL(k_restrict_v4<32>, g, blk, 0, st, t, r, L.n, C.n, bc);
+      else
+        hipLaunchKernelGGL(k_restrict_v4<16>, g, blk, 0, st, t, r, L.n, C.n, bc);
+      return;
+    }
+  }
+  hipLaunchKernelGGL(k_restrict<T>, box_grid(bc), dim3(kBoxTx, kBoxTy), 0, st, (const T*)L.t,
+                     (T*)C.r, L.n, C.n, bc);
+}
+
+// e_L += prolongation of e_C on L's black cells (all cells with all_cells);
+// the vector form for the black cells of FP32 levels with vector sweeps.
+template <typename T>
+static void prolong_level(const Level& L, const Level& C, bool all_cells, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    const int txv = v4_threads(L.box);
+    if (txv && !all_cells) {
+      const dim3 g = v4_grid(L.box, txv), blk(txv, 256 / txv);
+      const float* ec = (const float*)C.e;
+      float* ef = (float*)L.e;
+      if (txv == 64)
+        hipLaunchKernelGGL(k_prolong_black_v4<64>, g, blk, 0, st, ec, ef, C.n, L.n, L.box);
+      else if (txv == 32)
+        hipLaunchKernelGGL(k_prolong_black_v4<32>, g, blk, 0, st, ec, ef, C.n, L.n, L.box);
+      else
+        hipLaunchKernelGGL(k_prolong_black_v4<16>, g, blk, 0, st, ec, ef, C.n, L.n, L.box);
+      return;
+    }
+  }
+  hipLaunchKernelGGL(k_prolong<T>, half_grid(L.box), dim3(kBoxTx, kBoxTy), 0, st, (const T*)C.e,
+                     (T*)L.e, C.n, L.n, L.box, all_cells ? 1 : 0);
+}
+
 template <typename T>
 const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
                 bool periodic, bool fine_start, hipStream_t st) {
@@ -1104,8 +1287,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
     prof_begin(st);
-    hipLaunchKernelGGL(k_restrict<T>, box_grid(C.box), blk, 0, st, (const T*)L.t, (T*)C.r, L.n,
-                       C.n, C.box);
+    restrict_level<T>(L, C, st);
     prof_end(st, K_RESTRICT, es * (cells / 2 + (double)box_cells(C.box)));
   }
   {
@@ -1152,8 +1334,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     const T scale = (T)std::ldexp(1.0, 2 * l);
     const T inv_diag = (T)(1.0 / (6.0 + std::ldexp(1.0, 2 * l) * kappa));
     prof_begin(st);
-    hipLaunchKernelGGL(k_prolong<T>, half_grid(L.box), blk, 0, st, (const T*)C.e, (T*)L.e, C.n,
-                       L.n, L.box, post > 0 ? 0 : 1);
+    prolong_level<T>(L, C, post == 0, st);
     prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
     for (int s = 0; s < post; ++s) {
       smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 0, false, scale, inv_diag, st);
