@@ -49,9 +49,8 @@ struct sdpm_ctx {
   int gate_skip[2] = {0, 0};
   int gate_backoff[2] = {kGateProbe, kGateProbe};
   // extrapolated start (SDPM_WS_EXTRAP): per solve kind the FP32 change of
-  // the last solve and its conformal step; the FP32 copy of a solve's start
+  // the last solve (accumulated while it runs) and its conformal step
   float* ex_d[2] = {nullptr, nullptr};
-  float* ex_start = nullptr;
   bool ex_have[2] = {false, false};
   double ex_dtau[2] = {0.0, 0.0};
   double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
@@ -235,11 +234,9 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
     const size_t V = (size_t)c.ng * c.ng * c.ng;
     float* d0 = (float*)take(V * sizeof(float));
     float* d1 = (float*)take(V * sizeof(float));
-    float* s0 = (float*)take(V * sizeof(float));
     if (ctx) {
       ctx->ex_d[0] = d0;
       ctx->ex_d[1] = d1;
-      ctx->ex_start = s0;
     }
   }
   if ((c.warm_start & ~SDPM_WS_EXTRAP) != SDPM_WS_PREV) {
@@ -423,19 +420,34 @@ int flags_error(sdpm_ctx* c) {
   return SDPM_OK;
 }
 
+// Extrapolated start (steps only): the solve of kind `slot` starts from
+// phi += (dtau / dtau_prev) (change of the same solve kind in the previous
+// step); periodic phase only (on the frozen-exterior box the start saved no
+// iteration at 512^3).
+bool extrap_active(const sdpm_ctx* c, int slot) {
+  return slot >= 0 && (c->cfg.warm_start & SDPM_WS_EXTRAP) && c->cur_dtau > 0.0 && c->ex_d[slot] &&
+         c->periodic;
+}
+
 // rhs = S h^2 (C / (n0/ng^3 2^3B) - ratio) - kappa phi over the box, with
 // ratio = n_active / n0 on a periodic mesh (subtracts the exact mean, since
-// sum C = n_active 2^3B) and 1 otherwise.  ||rhs||^2 -> dscal[0].
-void assemble_rhs(sdpm_ctx* c, double s_source, double kappa) {
+// sum C = n_active 2^3B) and 1 otherwise.  ||rhs||^2 -> dscal[0].  When the
+// solve of kind `slot` (-1: none) extrapolates, the same pass applies the
+// extrapolated start after reading phi_old for the rhs and starts the running
+// change ex_d[slot] that the solve's later updates of phi add to.
+void assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot) {
   const sdpm_config& g = c->cfg;
   const double h = g.box / g.ng;
   const double nbar = (double)g.n_initial / ((double)g.ng * g.ng * g.ng);
   const double c_scale = s_source * h * h / (nbar * std::ldexp(1.0, 3 * g.frac_bits));
   const double ratio = c->periodic ? (double)c->n_active / (double)g.n_initial : 1.0;
   const double c_off = s_source * h * h * ratio;
+  const bool extrap = extrap_active(c, slot);
+  const bool apply = extrap && c->ex_have[slot] && c->ex_dtau[slot] > 0.0;
   int nb = 0;
   launch_rhs(c->fields.counts, c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c_scale, c_off,
-             kappa, c->partial, &nb, c->st);
+             kappa, extrap ? c->ex_d[slot] : nullptr, apply ? c->cur_dtau / c->ex_dtau[slot] : 0.0,
+             apply, c->partial, &nb, c->st);
   launch_reduce_final(c->partial, nb, 1, c->dscal, c->st);
 }
 
@@ -451,17 +463,10 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   const sdpm_config& g = c->cfg;
   const Box& b = c->lv[0].box;
   int nb = 0;
-  // extrapolated start (steps only): phi += (dtau / dtau_prev) (change of the
-  // same solve kind in the previous step); the rhs already holds phi_old
-  // (periodic phase only: on the frozen-exterior box the start saved no
-  // iteration at 512^3 and its two passes cost ~0.45 ms per solve)
-  const bool extrap = (g.warm_start & SDPM_WS_EXTRAP) && c->cur_dtau > 0.0 && c->ex_start &&
-                      c->periodic;
-  if (extrap) {
-    const bool apply = c->ex_have[slot] && c->ex_dtau[slot] > 0.0;
-    launch_extrap_begin(c->fields.phi, c->ex_d[slot], apply ? c->cur_dtau / c->ex_dtau[slot] : 0.0,
-                        apply ? 1 : 0, c->ex_start, g.ng, b, c->st);
-  }
+  // extrapolated start: applied by assemble_rhs; every later update of phi
+  // in this solve is added to the running change chg as well
+  const bool extrap = extrap_active(c, slot);
+  float* chg = extrap ? c->ex_d[slot] : nullptr;
   launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial, &nb,
                      c->st);
   launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
@@ -523,7 +528,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     }
     const double rg = std::sqrt(c->hpin[1]);
     if (std::isfinite(rg) && rg < rn) {
-      launch_apply_guess(c->fields.phi, c->net_out, rms_r, g.ng, b, c->st);
+      launch_apply_guess(c->fields.phi, c->net_out, rms_r, chg, g.ng, b, c->st);
       std::swap(c->lv[0].r, c->r_alt);
       rn = rg;
       so->warm = 1;
@@ -579,7 +584,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     for (int q = 0; q < ncyc; ++q)
       e0 = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
                      q > 0, c->st);
-    launch_correct<T>(c->fields.phi, e0, g.ng, b, c->st);
+    launch_correct<T>(c->fields.phi, e0, chg, g.ng, b, c->st);
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
@@ -644,10 +649,9 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     launch_reduce_final(c->partial, nb, 1, c->dscal + 2, c->st);
     rc = sync_scalars(c, 3);
     if (rc) return rc;
-    launch_add_const(c->fields.phi, g.ng, b, -c->hpin[2] / (double)box_cells(b), c->st);
+    launch_add_const(c->fields.phi, chg, g.ng, b, -c->hpin[2] / (double)box_cells(b), c->st);
   }
   if (extrap) {
-    launch_extrap_end(c->fields.phi, c->ex_start, c->ex_d[slot], g.ng, b, c->st);
     c->ex_have[slot] = true;
     c->ex_dtau[slot] = c->cur_dtau;
   }
@@ -982,7 +986,7 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, full_box(c->cfg.ng), 0ull, c->st);
   deposit(c, 0.0, 0);
-  assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0);
+  assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0, 0);
   SolveOut so;
   const int src = solve(c, 0.0, 0, &so);
   rc = flags_error(c);
@@ -1030,9 +1034,9 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
   // Phi from t to t + dt/2                              (row 3)
   const bool ade = g.solver == SDPM_SOLVER_ADE;
-  assemble_rhs(c, sc.s_half, ade ? 0.0 : sc.kappa1_h2);
-  HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
   const StepDtau step_dtau(c, sc.dtau);
+  assemble_rhs(c, sc.s_half, ade ? 0.0 : sc.kappa1_h2, 0);
+  HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
   SolveOut s1;
   int src1 = SDPM_OK;
   if (ade) {
@@ -1072,7 +1076,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
                      1.0 / sc.kappa2_h2, false, c->st);
   } else if (sc.kappa2_h2 > 0.0) {
-    assemble_rhs(c, sc.s_half, sc.kappa2_h2);
+    assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1);
     src2 = solve(c, sc.kappa2_h2, 1, &s2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
   }
@@ -1230,7 +1234,7 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
   if (rc) return rc;
   if (!(kappa_h2 >= 0.0) || !std::isfinite(s_source))
     return fail(c, SDPM_EINVAL, "kappa_h2 must be >= 0 and s finite");
-  assemble_rhs(c, s_source, kappa_h2);
+  assemble_rhs(c, s_source, kappa_h2, 0);
   SolveOut so;
   rc = solve(c, kappa_h2, 0, &so);
   if (out) {

@@ -103,18 +103,22 @@ StepScalars step_scalars(const sdpm_config& cfg, double a, double da);
 // Launchers, mesh kernels (mesh.hip).  All enqueue on `st`.
 // ---------------------------------------------------------------------------
 template <typename T> void launch_fill(T* a, int n, const Box& b, T v, hipStream_t st);
-void launch_rhs(const uint64_t* counts, const double* phi, double* rhs, int n, const Box& b,
-                double c_scale, double c_off, double kappa, double* partial, int* nblocks,
-                hipStream_t st);
+// rhs = c_scale counts - c_off - kappa phi, ||rhs||^2 partials.  With chg
+// (the extrapolated start): chg = apply ? (float)(chg_scale chg) : 0 and
+// phi += chg, so chg then holds the change of phi since the rhs was formed.
+void launch_rhs(const uint64_t* counts, double* phi, double* rhs, int n, const Box& b,
+                double c_scale, double c_off, double kappa, float* chg, double chg_scale,
+                bool apply, double* partial, int* nblocks, hipStream_t st);
 template <typename T>
 void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
                      double kappa, double* partial, int* nblocks, hipStream_t st);
+// phi += e (colour-split e); chg += e as well when chg is given.
 template <typename T>
-void launch_correct(double* phi, const T* e, int n, const Box& b, hipStream_t st);
+void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st);
-void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st);
+void launch_add_const(double* phi, float* chg, int n, const Box& b, double v, hipStream_t st);
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
                          hipStream_t st);
 // Exact periodic FFT solve of (Lap_h - kappa h^2) phi = rhs (fft.hip): FP64
@@ -241,14 +245,8 @@ template <typename T>
 void launch_residual_guess(const double* phi, const float* d, double scale, const double* rhs,
                            T* r_out, int n, const Box& b, double kappa, double* partial,
                            int* nblocks, hipStream_t st);
-// Extrapolated start of a solve (start = (float) phi, then phi += scale d
-// when apply) and, after it, the change it made (d = phi - start).
-void launch_extrap_begin(double* phi, const float* d, double scale, int apply, float* start, int n,
-                         const Box& b, hipStream_t st);
-void launch_extrap_end(const double* phi, const float* start, float* d, int n, const Box& b,
-                       hipStream_t st);
-void launch_apply_guess(double* phi, const float* d, double scale, int n, const Box& b,
-                        hipStream_t st);
+void launch_apply_guess(double* phi, const float* d, double scale, float* chg, int n,
+                        const Box& b, hipStream_t st);
 void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                    hipStream_t st);
 template <typename T>
@@ -270,7 +268,7 @@ enum KernelId : int {
   K_FILL, K_DEPOSIT, K_RHS, K_RESIDUAL, K_CORRECT, K_REDUCE, K_SUM_PHI, K_ADD_CONST,
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
-  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE, K_EXTRAP,
+  K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
   K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK,
   K_NKERNELS
 };

@@ -131,10 +131,11 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ a, int n, Box b, T
 
 // ----------------------------------------------------------- FP64 kernels
 // rhs = C * c_scale - c_off - kappa phi ; partial sum of rhs^2.
+template <bool CHG>
 __global__ void __launch_bounds__(256)
-k_rhs(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
-      double* __restrict__ rhs, int n, Box b, double c_scale, double c_off, double kappa,
-      double* __restrict__ partial) {
+k_rhs(const uint64_t* __restrict__ counts, double* __restrict__ phi, double* __restrict__ rhs,
+      int n, Box b, double c_scale, double c_off, double kappa, float* __restrict__ chg,
+      double chg_scale, int apply, double* __restrict__ partial) {
   __shared__ double sh[4];
   const Tile tl = tile_box(b);
   const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
@@ -145,9 +146,17 @@ k_rhs(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
     const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
     for (int k = k0; k <= k1; ++k) {
       const int64_t c = lin(i, j, k, n);
-      const double v = (double)ld_stream(counts + c) * c_scale - c_off - kappa * phi[c];
+      const double old = phi[c];
+      const double v = (double)ld_stream(counts + c) * c_scale - c_off - kappa * old;
       st_stream(rhs + c, v);
       acc += v * v;
+      if (CHG) {
+        // extrapolated start: phi += the scaled change of the previous solve,
+        // which also starts this solve's running change
+        const float dv = apply ? (float)(chg_scale * (double)ld_stream(chg + c)) : 0.f;
+        if (apply) phi[c] = old + (double)dv;
+        st_stream(chg + c, dv);
+      }
     }
   }
   const double s = block_sum<256>(acc, sh);
@@ -265,9 +274,10 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
-template <typename T>
+// phi += e; with CHG the same increment is added to the running change.
+template <typename T, bool CHG>
 __global__ void __launch_bounds__(256)
-k_correct(double* __restrict__ phi, const T* __restrict__ e, int n, Box b) {
+k_correct(double* __restrict__ phi, const T* __restrict__ e, float* __restrict__ chg, int n, Box b) {
   const Tile tl = tile_box(b);
   const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
   const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
@@ -276,7 +286,9 @@ k_correct(double* __restrict__ phi, const T* __restrict__ e, int n, Box b) {
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) {
     const int64_t c = lin(i, j, k, n);
-    phi[c] += (double)ld_stream(e + sidx(i, j, k, n));
+    const T ev = ld_stream(e + sidx(i, j, k, n));
+    phi[c] += (double)ev;
+    if (CHG) st_stream(chg + c, ld_stream(chg + c) + (float)ev);
   }
 }
 
@@ -296,14 +308,20 @@ k_sum_phi(const double* __restrict__ phi, int n, Box b, double* __restrict__ par
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
-__global__ void __launch_bounds__(256) k_add_const(double* __restrict__ phi, int n, Box b, double v) {
+// phi += v (and chg += v when given).
+__global__ void __launch_bounds__(256)
+k_add_const(double* __restrict__ phi, float* __restrict__ chg, int n, Box b, double v) {
   const Tile tl = tile_box(b);
   const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
   const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
   if (i > b.hi[0] || j > b.hi[1]) return;
   const int k0 = b.lo[2] + tl.bz * kBoxKz;
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  for (int k = k0; k <= k1; ++k) phi[lin(i, j, k, n)] += v;
+  for (int k = k0; k <= k1; ++k) {
+    const int64_t c = lin(i, j, k, n);
+    phi[c] += v;
+    if (chg) chg[c] += (float)v;
+  }
 }
 
 // out[s] = sum of partial[s * nblocks + 0 .. nblocks), fixed order.
@@ -852,8 +870,10 @@ k_residual_guess(const double* __restrict__ phi, const float* __restrict__ d, do
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
+// phi += scale d (and chg += the same increment when given).
 __global__ void __launch_bounds__(256)
-k_apply_guess(double* __restrict__ phi, const float* __restrict__ d, double scale, int n, Box b) {
+k_apply_guess(double* __restrict__ phi, const float* __restrict__ d, double scale,
+              float* __restrict__ chg, int n, Box b) {
   const Tile tl = tile_box(b);
   const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
   const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
@@ -862,41 +882,9 @@ k_apply_guess(double* __restrict__ phi, const float* __restrict__ d, double scal
   const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
   for (int k = k0; k <= k1; ++k) {
     const int64_t c = lin(i, j, k, n);
-    phi[c] += scale * (double)d[c];
-  }
-}
-
-// Extrapolated start of a solve: start = (float) phi; phi += scale d.
-__global__ void __launch_bounds__(256)
-k_extrap_begin(double* __restrict__ phi, const float* __restrict__ d, double scale, int apply,
-               float* __restrict__ start, int n, Box b) {
-  const Tile tl = tile_box(b);
-  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
-  if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + tl.bz * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  for (int k = k0; k <= k1; ++k) {
-    const int64_t c = lin(i, j, k, n);
-    const double v = phi[c];
-    start[c] = (float)v;
-    if (apply) phi[c] = v + scale * (double)d[c];
-  }
-}
-
-// The change the solve made: d = phi - start.
-__global__ void __launch_bounds__(256)
-k_extrap_end(const double* __restrict__ phi, const float* __restrict__ start, float* __restrict__ d,
-             int n, Box b) {
-  const Tile tl = tile_box(b);
-  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
-  if (i > b.hi[0] || j > b.hi[1]) return;
-  const int k0 = b.lo[2] + tl.bz * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  for (int k = k0; k <= k1; ++k) {
-    const int64_t c = lin(i, j, k, n);
-    d[c] = (float)(phi[c] - (double)start[c]);
+    const double inc = scale * (double)d[c];
+    phi[c] += inc;
+    if (chg) chg[c] += (float)inc;
   }
 }
 
@@ -961,15 +949,19 @@ template void launch_fill<float>(float*, int, const Box&, float, hipStream_t);
 template void launch_fill<double>(double*, int, const Box&, double, hipStream_t);
 template void launch_fill<uint64_t>(uint64_t*, int, const Box&, uint64_t, hipStream_t);
 
-void launch_rhs(const uint64_t* counts, const double* phi, double* rhs, int n, const Box& b,
-                double c_scale, double c_off, double kappa, double* partial, int* nblocks,
-                hipStream_t st) {
+void launch_rhs(const uint64_t* counts, double* phi, double* rhs, int n, const Box& b,
+                double c_scale, double c_off, double kappa, float* chg, double chg_scale,
+                bool apply, double* partial, int* nblocks, hipStream_t st) {
   const dim3 g = box_grid(b);
   *nblocks = (int)(g.x * g.y * g.z);
   prof_begin(st);
-  hipLaunchKernelGGL(k_rhs, g, dim3(kBoxTx, kBoxTy), 0, st, counts, phi, rhs, n, b, c_scale,
-                     c_off, kappa, partial);
-  prof_end(st, K_RHS, 24.0 * box_cells(b));
+  if (chg)
+    hipLaunchKernelGGL(k_rhs<true>, g, dim3(kBoxTx, kBoxTy), 0, st, counts, phi, rhs, n, b,
+                       c_scale, c_off, kappa, chg, chg_scale, apply ? 1 : 0, partial);
+  else
+    hipLaunchKernelGGL(k_rhs<false>, g, dim3(kBoxTx, kBoxTy), 0, st, counts, phi, rhs, n, b,
+                       c_scale, c_off, kappa, nullptr, 0.0, 0, partial);
+  prof_end(st, K_RHS, (24.0 + (chg ? (apply ? 16.0 : 4.0) : 0.0)) * box_cells(b));
 }
 
 // Threads across a tile row (64, 32 or 16, 4 entries each) for a row of
@@ -1030,13 +1022,18 @@ template void launch_residual<double>(const double*, const double*, double*, int
                                       double, double*, int*, hipStream_t);
 
 template <typename T>
-void launch_correct(double* phi, const T* e, int n, const Box& b, hipStream_t st) {
+void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st) {
   prof_begin(st);
-  hipLaunchKernelGGL(k_correct<T>, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e, n, b);
-  prof_end(st, K_CORRECT, (16.0 + sizeof(T)) * box_cells(b));
+  if (chg)
+    hipLaunchKernelGGL((k_correct<T, true>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e, chg,
+                       n, b);
+  else
+    hipLaunchKernelGGL((k_correct<T, false>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e,
+                       nullptr, n, b);
+  prof_end(st, K_CORRECT, (16.0 + sizeof(T) + (chg ? 8.0 : 0.0)) * box_cells(b));
 }
-template void launch_correct<float>(double*, const float*, int, const Box&, hipStream_t);
-template void launch_correct<double>(double*, const double*, int, const Box&, hipStream_t);
+template void launch_correct<float>(double*, const float*, float*, int, const Box&, hipStream_t);
+template void launch_correct<double>(double*, const double*, float*, int, const Box&, hipStream_t);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st) {
@@ -1047,10 +1044,10 @@ void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int
   prof_end(st, K_SUM_PHI, 8.0 * box_cells(b));
 }
 
-void launch_add_const(double* phi, int n, const Box& b, double v, hipStream_t st) {
+void launch_add_const(double* phi, float* chg, int n, const Box& b, double v, hipStream_t st) {
   prof_begin(st);
-  hipLaunchKernelGGL(k_add_const, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, n, b, v);
-  prof_end(st, K_ADD_CONST, 16.0 * box_cells(b));
+  hipLaunchKernelGGL(k_add_const, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, chg, n, b, v);
+  prof_end(st, K_ADD_CONST, (16.0 + (chg ? 8.0 : 0.0)) * box_cells(b));
 }
 
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
@@ -1079,27 +1076,14 @@ template void launch_residual_guess<double>(const double*, const float*, double,
                                             double*, int, const Box&, double, double*, int*,
                                             hipStream_t);
 
-void launch_apply_guess(double* phi, const float* d, double scale, int n, const Box& b,
-                        hipStream_t st) {
+void launch_apply_guess(double* phi, const float* d, double scale, float* chg, int n,
+                        const Box& b, hipStream_t st) {
   prof_begin(st);
-  hipLaunchKernelGGL(k_apply_guess, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, n, b);
-  prof_end(st, K_NET_MISC, 20.0 * box_cells(b));
+  hipLaunchKernelGGL(k_apply_guess, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, chg,
+                     n, b);
+  prof_end(st, K_NET_MISC, (20.0 + (chg ? 8.0 : 0.0)) * box_cells(b));
 }
 
-void launch_extrap_begin(double* phi, const float* d, double scale, int apply, float* start, int n,
-                         const Box& b, hipStream_t st) {
-  prof_begin(st);
-  hipLaunchKernelGGL(k_extrap_begin, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, apply,
-                     start, n, b);
-  prof_end(st, K_EXTRAP, (apply ? 24.0 : 12.0) * box_cells(b));
-}
-
-void launch_extrap_end(const double* phi, const float* start, float* d, int n, const Box& b,
-                       hipStream_t st) {
-  prof_begin(st);
-  hipLaunchKernelGGL(k_extrap_end, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, start, d, n, b);
-  prof_end(st, K_EXTRAP, 16.0 * box_cells(b));
-}
 
 void launch_sum_sq(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                    hipStream_t st) {

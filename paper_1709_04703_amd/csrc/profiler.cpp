@@ -7,7 +7,7 @@ const char* const kKernelNames[K_NKERNELS] = {
     "fill", "drift_deposit", "rhs", "residual_fp64", "correct", "reduce_final", "sum_phi",
     "add_const", "smooth_red_zero_guess", "smooth_color", "resid_red", "restrict_fw", "prolong_black",
     "coarse_lds", "interp_kick_drift", "interp_force", "count_kept", "scan_counts", "scatter",
-    "copy_back", "morton_radix_sort", "gather", "conv3d_mfma", "conv3d_wgrad_mfma", "net_misc", "force_mesh", "lightcone", "extrapolate",
+    "copy_back", "morton_radix_sort", "gather", "conv3d_mfma", "conv3d_wgrad_mfma", "net_misc", "force_mesh", "lightcone",
     "smooth_color_coarse", "ade_sweep", "fft_3d", "fft_divide", "power_spectrum",
 };
 

@@ -103,6 +103,14 @@ def test_solver_config_validation(P):
             >= 2 * 64 * 64 * 33 * 16)
 
 
+def test_extrapolated_start_workspace(P):
+    # two FP32 change meshes, one per solve kind (the running change is kept
+    # in place; no copy of the start)
+    prev = P.workspace_bytes(P.config_default(64, 100.0), 10)
+    ex = P.workspace_bytes(P.config_default(64, 100.0, warm_start=P.SDPM_WS_EXTRAP), 10)
+    assert ex - prev == 2 * 64**3 * 4
+
+
 def test_power_spectrum_workspace(P):
     # mesh, half spectrum and FFT work area at least
     assert P.pk_workspace_bytes(64) >= 8 * 64**3 + 2 * 64 * 64 * 33 * 16
