@@ -396,6 +396,13 @@ typedef struct sdpm_kernel_stat {
   double bytes;   /* summed algorithmic bytes                        */
 } sdpm_kernel_stat;
 int sdpm_profile(sdpm_ctx* ctx, int32_t enable);
+/* Like sdpm_profile(ctx, 1) for the kernels named in `names` only (a
+ * comma-separated list of the names sdpm_profile_read reports, e.g.
+ * "smooth_color"); the other launches get no event pair.  Each event pair
+ * costs queue time between launches, so a run timed as a whole brackets only
+ * the kernels it needs.  An unknown or empty name: SDPM_EINVAL, profiling
+ * left as it was.                                                            */
+int sdpm_profile_kernels(sdpm_ctx* ctx, const char* names);
 /* Copies min(max, kinds) per-kernel totals to out; *n = number of kinds.
  * Totals cover launches completed by the last synchronising call.          */
 int sdpm_profile_read(sdpm_ctx* ctx, sdpm_kernel_stat* out, int32_t max, int32_t* n);

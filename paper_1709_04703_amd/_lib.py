@@ -37,7 +37,7 @@ EXPORTS = [
     "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
     "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
-    "sdpm_ade_sweep", "sdpm_pk_workspace_bytes", "sdpm_power_spectrum",
+    "sdpm_ade_sweep", "sdpm_pk_workspace_bytes", "sdpm_power_spectrum", "sdpm_profile_kernels",
 ]
 NET_PARAMS = 5 * (27 * 16 * 16 + 16)
 CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
@@ -151,6 +151,7 @@ def library() -> ctypes.CDLL:
         "sdpm_record_info": [vp, P(i64), P(dbl), P(dbl), P(dbl), i64],
         "sdpm_profile": [vp, i32],
         "sdpm_profile_read": [vp, P(KernelStat), i32, P(i32)],
+        "sdpm_profile_kernels": [vp, ctypes.c_char_p],
         "sdpm_destroy": [vp],
         "sdpm_set_lightcone": [vp, P(Lightcone)],
         "sdpm_lightcone_count": [vp, P(i64)],
@@ -494,8 +495,13 @@ class Simulation:
         return n, np.array(kap[:n]), np.array(rr[:n]), np.array(rp[:n])
 
     # -- tracing
-    def profile(self, enable: bool = True):
-        self._check(self.lib.sdpm_profile(self.ctx, 1 if enable else 0))
+    def profile(self, enable: bool = True, kernels=None):
+        """Per-kernel event timing on (all kernels, or only those named in
+        `kernels`, an iterable of profile names) or off; totals cleared."""
+        if enable and kernels is not None:
+            self._check(self.lib.sdpm_profile_kernels(self.ctx, ",".join(kernels).encode()))
+        else:
+            self._check(self.lib.sdpm_profile(self.ctx, 1 if enable else 0))
 
     def profile_read(self) -> dict:
         arr = (KernelStat * 64)()

@@ -137,7 +137,7 @@ void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool pe
                       bool forward, hipStream_t st) {
   const int nx = b.hi[0] - b.lo[0] + 1;
   const int per = periodic ? 1 : 0;
-  prof_begin(st);
+  prof_begin(st, K_ADE);
   if (nx <= 64)
     ade_diagonals<1>(phi, f, n, b, per, lam, forward, st);
   else if (nx <= 128)

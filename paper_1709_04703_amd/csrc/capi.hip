@@ -1422,6 +1422,32 @@ int sdpm_profile(sdpm_ctx* c, int32_t enable) {
   if (c->prof.on) c->prof.collect();
   c->prof.reset();
   c->prof.on = enable != 0;
+  c->prof.mask = ~0ull;
+  return SDPM_OK;
+}
+
+int sdpm_profile_kernels(sdpm_ctx* c, const char* names) {
+  if (!c) return SDPM_EINVAL;
+  if (!names) return fail(c, SDPM_EINVAL, "names must not be NULL");
+  uint64_t mask = 0;
+  const char* p = names;
+  while (*p) {
+    const char* q = std::strchr(p, ',');
+    const size_t len = q ? (size_t)(q - p) : std::strlen(p);
+    int id = -1;
+    for (int k = 0; k < K_NKERNELS; ++k)
+      if (std::strlen(kKernelNames[k]) == len && std::strncmp(kKernelNames[k], p, len) == 0) id = k;
+    if (id < 0) return fail(c, SDPM_EINVAL, "unknown kernel name '%.*s'", (int)len, p);
+    mask |= 1ull << id;
+    if (!q) break;
+    p = q + 1;
+  }
+  if (!mask) return fail(c, SDPM_EINVAL, "no kernel named");
+  HIP_TRY(c, hipStreamSynchronize(c->st));
+  if (c->prof.on) c->prof.collect();
+  c->prof.reset();
+  c->prof.on = true;
+  c->prof.mask = mask;
   return SDPM_OK;
 }
 

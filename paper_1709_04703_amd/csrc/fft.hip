@@ -100,16 +100,16 @@ int fft_solve(const FftPlan& p, const double* rhs, double* phi, double kappa_h2,
   const int n = p.n;
   const double cells = (double)n * n * n;
   auto* c = (hipfftDoubleComplex*)p.c;
-  prof_begin(st);
+  prof_begin(st, K_FFT);
   const hipfftResult r1 = hipfftExecD2Z((hipfftHandle)p.fwd, (hipfftDoubleReal*)rhs, c);
   prof_end(st, K_FFT, 16.0 * cells);   // read rhs, write the half spectrum
   if (r1 != HIPFFT_SUCCESS) return SDPM_EHIP;
   const int64_t half = (int64_t)n * n * (n / 2 + 1);
-  prof_begin(st);
+  prof_begin(st, K_FFT_DIVIDE);
   hipLaunchKernelGGL(k_fft_divide, dim3((unsigned)std::min<int64_t>((half + 255) / 256, 65536)),
                      dim3(256), 0, st, c, p.sym, n, kappa_h2, 1.0 / cells);
   prof_end(st, K_FFT_DIVIDE, 32.0 * (double)half);
-  prof_begin(st);
+  prof_begin(st, K_FFT);
   const hipfftResult r2 = hipfftExecZ2D((hipfftHandle)p.inv, c, (hipfftDoubleReal*)phi);
   prof_end(st, K_FFT, 16.0 * cells);
   return r2 == HIPFFT_SUCCESS ? SDPM_OK : SDPM_EHIP;

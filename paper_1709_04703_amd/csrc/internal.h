@@ -272,10 +272,13 @@ enum KernelId : int {
   K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK,
   K_NKERNELS
 };
+static_assert(K_NKERNELS <= 64, "the profiler's kernel mask holds 64 kernels");
 extern const char* const kKernelNames[K_NKERNELS];
 
 struct Profiler {
   bool on = false;
+  uint64_t mask = ~0ull;    // kernels bracketed while on (bit = KernelId)
+  bool wants(int id) const { return on && ((mask >> id) & 1ull); }
   std::vector<hipEvent_t> ev;
   size_t used = 0;
   std::vector<int> pend_id;
@@ -292,11 +295,11 @@ struct Profiler {
 
 // The profiler of the context making the current call (nullptr: none).
 extern thread_local Profiler* g_prof;
-inline void prof_begin(hipStream_t st) {
-  if (g_prof && g_prof->on) g_prof->begin(st);
+inline void prof_begin(hipStream_t st, int id) {
+  if (g_prof && g_prof->wants(id)) g_prof->begin(st);
 }
 inline void prof_end(hipStream_t st, int id, double bytes) {
-  if (g_prof && g_prof->on) g_prof->end(st, id, bytes);
+  if (g_prof && g_prof->wants(id)) g_prof->end(st, id, bytes);
 }
 
 }  // namespace sdpm

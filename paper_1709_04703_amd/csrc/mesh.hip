@@ -941,7 +941,7 @@ k_record_accum(const T* __restrict__ e, int n, Box b, float* __restrict__ dphi) 
 // ------------------------------------------------------------- launchers
 template <typename T>
 void launch_fill(T* a, int n, const Box& b, T v, hipStream_t st) {
-  prof_begin(st);
+  prof_begin(st, K_FILL);
   hipLaunchKernelGGL(k_fill<T>, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, a, n, b, v);
   prof_end(st, K_FILL, (double)box_cells(b) * sizeof(T));
 }
@@ -954,7 +954,7 @@ void launch_rhs(const uint64_t* counts, double* phi, double* rhs, int n, const B
                 bool apply, double* partial, int* nblocks, hipStream_t st) {
   const dim3 g = box_grid(b);
   *nblocks = (int)(g.x * g.y * g.z);
-  prof_begin(st);
+  prof_begin(st, K_RHS);
   if (chg)
     hipLaunchKernelGGL(k_rhs<true>, g, dim3(kBoxTx, kBoxTy), 0, st, counts, phi, rhs, n, b,
                        c_scale, c_off, kappa, chg, chg_scale, apply ? 1 : 0, partial);
@@ -990,7 +990,7 @@ template <typename T>
 void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
                      double kappa, double* partial, int* nblocks, hipStream_t st) {
   const int ib = b.lo[0] & ~3;
-  prof_begin(st);
+  prof_begin(st, K_RESIDUAL);
   if (b.hi[0] - ib + 1 >= 64) {
     // tile width as for the colour sweeps (the extent here in cells, 4 per thread)
     const int txv = tile_threads(b.hi[0] - ib + 1);
@@ -1023,7 +1023,7 @@ template void launch_residual<double>(const double*, const double*, double*, int
 
 template <typename T>
 void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st) {
-  prof_begin(st);
+  prof_begin(st, K_CORRECT);
   if (chg)
     hipLaunchKernelGGL((k_correct<T, true>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e, chg,
                        n, b);
@@ -1039,20 +1039,20 @@ void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int
                     hipStream_t st) {
   const dim3 g = box_grid(b);
   *nblocks = (int)(g.x * g.y * g.z);
-  prof_begin(st);
+  prof_begin(st, K_SUM_PHI);
   hipLaunchKernelGGL(k_sum_phi, g, dim3(kBoxTx, kBoxTy), 0, st, phi, n, b, partial);
   prof_end(st, K_SUM_PHI, 8.0 * box_cells(b));
 }
 
 void launch_add_const(double* phi, float* chg, int n, const Box& b, double v, hipStream_t st) {
-  prof_begin(st);
+  prof_begin(st, K_ADD_CONST);
   hipLaunchKernelGGL(k_add_const, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, chg, n, b, v);
   prof_end(st, K_ADD_CONST, (16.0 + (chg ? 8.0 : 0.0)) * box_cells(b));
 }
 
 void launch_reduce_final(const double* partial, int nblocks, int nslots, double* out,
                          hipStream_t st) {
-  prof_begin(st);
+  prof_begin(st, K_REDUCE);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, st, partial, nblocks, nslots, out);
   prof_end(st, K_REDUCE, 8.0 * nblocks * nslots);
 }
@@ -1064,7 +1064,7 @@ void launch_residual_guess(const double* phi, const float* d, double scale, cons
                            int* nblocks, hipStream_t st) {
   const dim3 g = box_grid(b);
   *nblocks = (int)g.x;
-  prof_begin(st);
+  prof_begin(st, K_NET_MISC);
   hipLaunchKernelGGL(k_residual_guess<T>, g, dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, rhs, r_out,
                      n, b, kappa, partial);
   prof_end(st, K_NET_MISC, (20.0 + sizeof(T)) * box_cells(b));
@@ -1078,7 +1078,7 @@ template void launch_residual_guess<double>(const double*, const float*, double,
 
 void launch_apply_guess(double* phi, const float* d, double scale, float* chg, int n,
                         const Box& b, hipStream_t st) {
-  prof_begin(st);
+  prof_begin(st, K_NET_MISC);
   hipLaunchKernelGGL(k_apply_guess, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, d, scale, chg,
                      n, b);
   prof_end(st, K_NET_MISC, (20.0 + (chg ? 8.0 : 0.0)) * box_cells(b));
@@ -1132,7 +1132,7 @@ static void smooth_color(T* e, const T* r, const Level& L, int level, int color,
                          T scale, T inv_diag, hipStream_t st) {
   const Box& b = L.box;
   const int txv = sizeof(T) == 4 ? v4_threads(b) : 0;   // FP64 levels: the scalar kernel is faster
-  prof_begin(st);
+  prof_begin(st, first ? K_SMOOTH_FIRST : level == 0 ? K_SMOOTH : K_SMOOTH_COARSE);
   const int64_t hc = (int64_t)L.n * L.n * (L.n >> 1);
   T* eo = e + color * hc;
   const T* ex = e + (color ^ 1) * hc;
@@ -1182,7 +1182,7 @@ static void resid_red(const T* e, const T* r, T* t, const Level& L, T inv_scale,
                       hipStream_t st) {
   const Box& b = L.box;
   const int txv = sizeof(T) == 4 ? v4_threads(b) : 0;
-  prof_begin(st);
+  prof_begin(st, K_RESID_LEVEL);
   if (txv == 64)
     hipLaunchKernelGGL((k_resid_red_v4<T, 64>), v4_grid(b, 64), dim3(64, 4), 0, st, e, r, t, L.n, b,
                        inv_scale, kappa);
@@ -1270,7 +1270,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     }
     resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
-    prof_begin(st);
+    prof_begin(st, K_RESTRICT);
     restrict_level<T>(L, C, st);
     prof_end(st, K_RESTRICT, es * (cells / 2 + (double)box_cells(C.box)));
   }
@@ -1298,7 +1298,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
       }
     }
     if (fits) {
-      prof_begin(st);
+      prof_begin(st, K_COARSE);
       hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), 0, st, (T*)L.e, (const T*)L.r, L.n,
                          L.box, scale, inv_diag, sweeps,
                          (periodic && kappa == 0.0) ? 1 : 0, periodic ? 1 : 0);
@@ -1317,7 +1317,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
     const double cells = (double)box_cells(L.box);
     const T scale = (T)std::ldexp(1.0, 2 * l);
     const T inv_diag = (T)(1.0 / (6.0 + std::ldexp(1.0, 2 * l) * kappa));
-    prof_begin(st);
+    prof_begin(st, K_PROLONG);
     prolong_level<T>(L, C, post == 0, st);
     prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
     for (int s = 0; s < post; ++s) {

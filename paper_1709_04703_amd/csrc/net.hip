@@ -357,7 +357,7 @@ void launch_conv(int n, const uint16_t* in, const float* w, const float* bias, i
                  const uint16_t* mask, void* out, hipStream_t st) {
   const dim3 g(conv_blocks(n));
   const double V = (double)n * n * n;
-  prof_begin(st);
+  prof_begin(st, K_CONV);
   switch (flags) {
     case 1: hipLaunchKernelGGL(k_conv<1>, g, dim3(256), 0, st, n, in, w, bias, mask, out); break;
     case 2: hipLaunchKernelGGL(k_conv<2>, g, dim3(256), 0, st, n, in, w, bias, mask, out); break;
@@ -374,7 +374,7 @@ size_t wgrad_scratch_bytes(int n) { return (size_t)wgrad_blocks(n) * kWG * sizeo
 void launch_conv_wgrad(int n, const uint16_t* in, const uint16_t* g, float* dw, float* db,
                        float* scratch, hipStream_t st) {
   const int nb = wgrad_blocks(n);
-  prof_begin(st);
+  prof_begin(st, K_CONV_WGRAD);
   hipLaunchKernelGGL(k_conv_wgrad, dim3(nb), dim3(256), 0, st, n, in, g, scratch);
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((kWG + 255) / 256), dim3(256), 0, st, scratch, nb, dw, db);
   prof_end(st, K_CONV_WGRAD, 2.0 * 27 * kNC * kNC * (double)n * n * n);

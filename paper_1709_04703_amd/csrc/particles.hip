@@ -529,7 +529,7 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
                           const MeshMap& mm, uint64_t* counts, uint32_t* flags,
                           hipStream_t st) {
   if (pa.n <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_DEPOSIT);
   const dim3 g(grid_for(pa.n, 256 * kDepPer));
   if (drift)
     hipLaunchKernelGGL((k_drift_deposit<PT, true>), g, dim3(256), 0, st, pa, drift_coef, mm,
@@ -549,7 +549,7 @@ void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double
                        hipStream_t st) {
   const int gx = (b.hi[0] - b.lo[0] + kBoxTx) / kBoxTx, gy = (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy;
   const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
-  prof_begin(st);
+  prof_begin(st, K_FORCE_MESH);
   hipLaunchKernelGGL(k_force_mesh, dim3((unsigned)gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st, phi, g3,
                      n, b, inv2h, gx, gy);
   prof_end(st, K_FORCE_MESH, 20.0 * box_cells(b));
@@ -561,7 +561,7 @@ void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const f
                               const double* x_obs, double r2, int count_removed,
                               uint32_t* removed_count, uint32_t* flags, hipStream_t st) {
   if (pa.n <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_INTERP_KICK_DRIFT);
   if (g3)
     hipLaunchKernelGGL((k_interp_kick_drift<PT, true>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st,
                        pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2],
@@ -587,7 +587,7 @@ void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMa
                          double inv2h, double* g0, double* g1, double* g2, uint32_t* flags,
                          hipStream_t st) {
   if (pa.n <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_INTERP_FORCE);
   hipLaunchKernelGGL(k_interp_force, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi, mm,
                      inv2h, g0, g1, g2, flags);
   prof_end(st, K_INTERP_FORCE, 48.0 * pa.n + 8.0 * box_cells(mm.active));
@@ -598,7 +598,7 @@ void launch_lightcone(const ParticleArgs& pa, int64_t first, int64_t count, cons
                       double r1, double light, double disp, double a1, double da, const LcArgs& out,
                       int64_t out_first, hipStream_t st) {
   if (count <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_LIGHTCONE);
   hipLaunchKernelGGL(k_lightcone<PT>, dim3(grid_for(count, 256)), dim3(256), 0, st, pa, first, count,
                      x_obs[0], x_obs[1], x_obs[2], r1, light, disp, a1, da, out, out_first);
   // particle read (x, p, id) and record written (id, a, x, p)
@@ -614,7 +614,7 @@ template void launch_lightcone<double>(const ParticleArgs&, int64_t, int64_t, co
 void launch_lc_mark(const ParticleArgs& pa, const double* x_obs, double r2, uint8_t* mark,
                     hipStream_t st) {
   if (pa.n <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_LIGHTCONE);
   hipLaunchKernelGGL(k_lc_mark, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
                      x_obs[2], r2, mark);
   prof_end(st, K_LIGHTCONE, 25.0 * pa.n);
@@ -626,7 +626,7 @@ void launch_lc_cross(const ParticleArgs& pa, const double* x_obs, double r2, dou
                      const LcArgs& out, int64_t base, int64_t capacity,
                      unsigned long long* counter, hipStream_t st) {
   if (pa.n <= 0) return;
-  prof_begin(st);
+  prof_begin(st, K_LIGHTCONE);
   hipLaunchKernelGGL(k_lc_cross<PT>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, x_obs[0],
                      x_obs[1], x_obs[2], r2, r, light, disp, a1, da, mark, out, base, capacity,
                      counter);
@@ -646,11 +646,11 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
                     hipStream_t st) {
   if (pa.n <= 0) return;
   const int64_t nb = (pa.n + kChunk - 1) / kChunk;
-  prof_begin(st);
+  prof_begin(st, K_COUNT_KEPT);
   hipLaunchKernelGGL(k_count_kept, dim3((unsigned)nb), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
                      x_obs[2], r2, block_counts);
   prof_end(st, K_COUNT_KEPT, 24.0 * pa.n);
-  prof_begin(st);
+  prof_begin(st, K_SCAN);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, block_offsets, nb,
                      kept_total);
   prof_end(st, K_SCAN, 8.0 * nb);
@@ -664,11 +664,11 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
   PT* sp2 = sp1 + n;
   uint32_t* sid = (uint32_t*)(sp2 + n);
   const double pbytes = (24.0 + 3.0 * sizeof(PT) + 4.0) * pa.n;
-  prof_begin(st);
+  prof_begin(st, K_SCATTER);
   hipLaunchKernelGGL(k_scatter<PT>, dim3((unsigned)nb), dim3(256), 0, st, pa, x_obs[0], x_obs[1],
                      x_obs[2], r2, block_offsets, kept_total, sx0, sx1, sx2, sp0, sp1, sp2, sid);
   prof_end(st, K_SCATTER, 2.0 * pbytes);
-  prof_begin(st);
+  prof_begin(st, K_COPY);
   for (int d = 0; d < 3; ++d) {
     (void)hipMemcpyAsync(pa.x[d], sx0 + d * n, n * sizeof(double), hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(pa.p[d], sp0 + d * n, n * sizeof(PT), hipMemcpyDeviceToDevice, st);

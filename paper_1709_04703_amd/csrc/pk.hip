@@ -261,7 +261,7 @@ int power_spectrum(const double* const x[3], int64_t npart, double box, int n, i
   // shell sums of the raw spectrum
   const double l3 = box * box * box;
   std::vector<double> raw((size_t)nb * kPkSums);
-  prof_begin(st);
+  prof_begin(st, K_PK);
   hipLaunchKernelGGL(k_pk_shells<true>, dim3(kPkBlocks), dim3(256),
                      (size_t)nb * kPkSums * sizeof(double), st, cbuf, n, l3, neff_dev, tab, sq,
                      partial);
@@ -291,7 +291,7 @@ int power_spectrum(const double* const x[3], int64_t npart, double box, int n, i
       if (hipMemcpyAsync(neff_dev, neff.data(), nb * sizeof(double), hipMemcpyHostToDevice, st) !=
           hipSuccess)
         return herr("copy of the slopes failed");
-      prof_begin(st);
+      prof_begin(st, K_PK);
       hipLaunchKernelGGL(k_pk_shells<false>, dim3(kPkBlocks), dim3(256), (size_t)nb * sizeof(double),
                          st, cbuf, n, l3, neff_dev, tab, sq, partial);
       prof_end(st, K_PK, 0.0);

@@ -219,7 +219,7 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
   while ((1 << lg) < ng) ++lg;
   const int bits = 3 * (lg - shift);
   const unsigned gp = (unsigned)((n + 255) / 256);
-  prof_begin(st);
+  prof_begin(st, K_SORT);
   hipLaunchKernelGGL(k_morton_keys, dim3(gp), dim3(256), 0, st, pa.x[0], pa.x[1], pa.x[2], n,
                      (double)ng / box, ng, shift, k0, v0);
   for (int bit = 0; bit < bits; bit += 8) {
@@ -241,11 +241,11 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
   PT* sp2 = sp1 + n;
   uint32_t* sid = (uint32_t*)(sp2 + n);
   const double pbytes = (24.0 + 3.0 * sizeof(PT) + 4.0) * n;
-  prof_begin(st);
+  prof_begin(st, K_GATHER);
   hipLaunchKernelGGL(k_gather<PT>, dim3(gp), dim3(256), 0, st, pa, v0, sx0, sx1, sx2, sp0, sp1, sp2,
                      sid);
   prof_end(st, K_GATHER, 2.0 * pbytes + 4.0 * n);
-  prof_begin(st);
+  prof_begin(st, K_COPY);
   for (int d = 0; d < 3; ++d) {
     (void)hipMemcpyAsync(pa.x[d], sx0 + d * n, n * sizeof(double), hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(pa.p[d], sp0 + d * n, n * sizeof(PT), hipMemcpyDeviceToDevice, st);
