@@ -200,7 +200,15 @@ k_residual(const double* __restrict__ phi, const double* __restrict__ rhs, T* __
 // k_residual with 4 consecutive cells per thread (vector loads of phi and
 // rhs, two 2-wide stores per colour of r).  Vectors start at multiples of 4
 // (the box's first x index rounded down); cells outside the box are masked.
-// A tile is 4 TXV cells x 256 / TXV rows x kBoxKz planes.
+// A tile is 4 TXV cells x 256 / TXV rows x kResKz planes.
+#ifndef SDPM_RES_KZ
+#define SDPM_RES_KZ 8
+#endif
+constexpr int kResKz = SDPM_RES_KZ;   // planes per thread of the FP64 residual's z-march
+// (its 256-thread tiles then span at least as many cells as the box
+// kernels', whose grid sizes the reduction partials)
+static_assert(kResKz >= 2, "more residual workgroups than reduction partials");
+
 template <typename T, int TXV>
 __global__ void __launch_bounds__(256)
 k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T* __restrict__ rout,
@@ -214,8 +222,8 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
   const int m = n - 1;
   double acc = 0.0;
   if (i0 <= b.hi[0] && j <= b.hi[1]) {
-    const int k0 = b.lo[2] + tl.bz * kBoxKz;
-    const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+    const int k0 = b.lo[2] + tl.bz * kResKz;
+    const int k1 = min(k0 + kResKz - 1, b.hi[2]);
     const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
     const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
     const int hn = n >> 1;
@@ -996,7 +1004,7 @@ void launch_residual(const double* phi, const double* rhs, T* r_out, int n, cons
     const int txv = tile_threads(b.hi[0] - ib + 1);
     const unsigned gx = (unsigned)((b.hi[0] - ib + 4 * txv) / (4 * txv));
     const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + 256 / txv) / (256 / txv));
-    const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz);
+    const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kResKz) / kResKz);
     *nblocks = (int)(gx * gy * gz);
     const dim3 g(gx * gy * gz), blk(txv, 256 / txv);
     if (txv == 64)
