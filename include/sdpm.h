@@ -105,7 +105,11 @@ typedef struct sdpm_config {
   int32_t box_align;     /* power of two A: the planes next to the active box
                             sit at multiples of A (A = 2^(mg_levels-1) nests
                             every multigrid level exactly)                     */
-  int32_t mg_levels;     /* multigrid levels incl. the finest (>= 2)           */
+  int32_t mg_levels;     /* multigrid levels incl. the finest (>= 2), at most:
+                            a V-cycle ends on the first coarser level whose
+                            own red-black sweeps cut its slowest mode by 1e-3
+                            in at most pre + post + 1 sweeps (kappa h^2 > 0
+                            makes the coarse diagonals dominant)             */
   int32_t pre, post;     /* RB Gauss-Seidel sweeps before / after coarse work  */
   int32_t coarse_sweeps; /* max RB Gauss-Seidel sweeps on the coarsest level   */
   int32_t max_outer;     /* FP64 defect-correction iterations per solve        */

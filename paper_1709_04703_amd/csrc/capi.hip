@@ -573,7 +573,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     double pred_next = rn_known * std::pow(c->rho_est, cyc - cyc_known + 1);
     double factor = c->rho_est;
     int ncyc = 1;
-    while (ncyc < g.cycles_per_outer && pred_next > kPairMargin * thresh &&
+    while (ncyc < g.cycles_per_outer && pred_next > kCycleMargin * thresh &&
            factor * c->rho_est > kFloorMargin * floor_rel) {
       ++ncyc;
       pred_next *= c->rho_est;

@@ -22,11 +22,11 @@ constexpr int kNormSlot = 16, kNormRing = 32, kHostNorm = 64, kHostScalars = 128
 constexpr int kMaxAhead = 16;
 constexpr double kAheadMargin = 10.0;
 // a further V-cycle in an outer iteration only while the cycles so far are
-// predicted to leave the norm above kPairMargin * threshold (a needless cycle
+// predicted to leave the norm above kCycleMargin * threshold (a needless cycle
 // costs about twice what a further outer iteration's FP64 passes do) and
 // their combined factor stays above kFloorMargin times the bound on the
 // rounding floor of the correction; at most kMaxCyclesPerOuter cycles
-constexpr double kPairMargin = 2.0;
+constexpr double kCycleMargin = 2.0;
 constexpr int kMaxCyclesPerOuter = 4;
 constexpr double kFloorMargin = 1.0;    // the floor is a worst-case bound already
 constexpr int kHostLcCount = 120;      // host slot of the fixed-domain lightcone counter

@@ -1257,11 +1257,38 @@ static void prolong_level(const Level& L, const Level& C, bool all_cells, hipStr
                      (T*)L.e, C.n, L.n, L.box, all_cells ? 1 : 0);
 }
 
+// Red-black sweeps that reduce the slowest mode of level l's operator by
+// 1e-3: Jacobi factor rho = 6 cos(theta) / (6 + 4^l kappa h^2), red-black GS
+// rho^2, theta = 2 pi / n (periodic) or pi / (extent + 1) (Dirichlet); a
+// large number when rho >= 1.
+static int sweeps_for_1e3(const Level& L, int l, double kappa, bool periodic) {
+  const int nx = L.box.hi[0] - L.box.lo[0] + 1, ny = L.box.hi[1] - L.box.lo[1] + 1,
+            nz = L.box.hi[2] - L.box.lo[2] + 1;
+  const int ext = std::max(nx, std::max(ny, nz));
+  const double th = periodic ? 2.0 * M_PI / L.n : M_PI / (ext + 1);
+  const double rho = 6.0 * std::cos(th) / (6.0 + std::ldexp(1.0, 2 * l) * kappa);
+  if (!(rho > 0.0 && rho < 1.0)) return rho <= 0.0 ? 1 : 1 << 20;
+  return std::max(1, (int)std::ceil(std::log(1e-3) / (2.0 * std::log(rho))));
+}
+
 template <typename T>
-const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
+const T* vcycle(const Level* lv, int nlev_all, double kappa, int pre, int post, int coarse_sweeps,
                 bool periodic, bool fine_start, hipStream_t st) {
   const dim3 blk(kBoxTx, kBoxTy);
   const double es = sizeof(T);
+  // The hierarchy ends at the first level below the finest whose own sweeps
+  // reach the coarsest solve's 1e-3 in at most pre + post + 1 sweeps: with
+  // kappa > 0 the level-l diagonal 6 + 4^l kappa h^2 makes the smoother a
+  // fast solver there (kappa h^2 = 0.113 on a 512^3 mesh: factor 0.45 per
+  // sweep on the 64^3 level, 5 sweeps), and the levels below it would cost
+  // more short launches than the sweeps they replace.  kappa = 0 keeps every
+  // level.
+  int nlev = nlev_all;
+  for (int l = 1; l < nlev_all - 1; ++l)
+    if (sweeps_for_1e3(lv[l], l, kappa, periodic) <= pre + post + 1) {
+      nlev = l + 1;
+      break;
+    }
   for (int l = 0; l < nlev - 1; ++l) {
     const Level& L = lv[l];
     const double cells = (double)box_cells(L.box);
@@ -1292,19 +1319,7 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
                                : ((int64_t)(nx + 2) * (ny + 2) * (nz + 2) <=
                                   (int64_t)kCoarseMax * kCoarseMax * kCoarseMax);
     const T scale = (T)sc, inv_diag = (T)(1.0 / (6.0 + sc * kappa));
-    // sweeps for a 1e-3 reduction of the slowest mode: Jacobi factor
-    // rho = 6 cos(theta) / (6 + 4^l kappa h^2), red-black GS factor rho^2,
-    // theta = 2 pi / n (periodic) or pi / (extent + 1) (Dirichlet)
-    int sweeps = coarse_sweeps;
-    {
-      const int ext = std::max(nx, std::max(ny, nz));
-      const double th = periodic ? 2.0 * M_PI / L.n : M_PI / (ext + 1);
-      const double rho = 6.0 * std::cos(th) / (6.0 + sc * kappa);
-      if (rho > 0.0 && rho < 1.0) {
-        const int need = (int)std::ceil(std::log(1e-3) / (2.0 * std::log(rho)));
-        sweeps = std::max(1, std::min(coarse_sweeps, need));
-      }
-    }
+    const int sweeps = std::max(1, std::min(coarse_sweeps, sweeps_for_1e3(L, l, kappa, periodic)));
     if (fits) {
       prof_begin(st, K_COARSE);
       hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), 0, st, (T*)L.e, (const T*)L.r, L.n,
@@ -1312,7 +1327,9 @@ const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int 
                          (periodic && kappa == 0.0) ? 1 : 0, periodic ? 1 : 0);
       prof_end(st, K_COARSE, 2 * es * (double)box_cells(L.box));
     } else {
-      // large degenerate Dirichlet box: sweeps through global memory
+      // a coarsest level beyond the LDS solve (a large degenerate Dirichlet
+      // box, or a level the hierarchy ends on early): sweeps through global
+      // memory
       for (int s = 0; s < sweeps; ++s) {
         smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 0, s == 0, scale, inv_diag, st);
         smooth_color<T>((T*)L.e, (const T*)L.r, L, l, 1, false, scale, inv_diag, st);
