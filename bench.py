@@ -13,8 +13,8 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
   extrap:  mixed, each solve started from the potential plus the change the
            same solve made in the previous step (linear extrapolation in time);
   learned: extrap, plus the conv-net warm start, gated: the library keeps the
-           net only while the outer iterations it saves outweigh its measured
-           cost (the headline value);
+           net only while the V-cycles it saves outweigh its measured cost
+           (the headline value);
   learned_always: extrap, plus the conv-net guess tried before every solve;
   ade:     the paper's own gravity integrator instead of the implicit solve
            (one alternating-direction explicit sweep per half sub-step, FP64

@@ -56,9 +56,10 @@ enum { SDPM_MIXED = 0, SDPM_PLAIN_FP64 = 1 };      /* sdpm_config.precision  */
 /* sdpm_config.warm_start.  PREV: the previous potential.  LEARNED: the
  * learned guess (below) before every solve.  LEARNED_GATED: the learned
  * guess only while it pays: per sub-step kind (first / second field
- * half-step) the context times the guess and one outer iteration with HIP
- * events and estimates the outer iterations an accepted guess saved (its
- * residual reduction in units of the solve's measured convergence factor);
+ * half-step) the context times the guess and one V-cycle (with its share of
+ * the defect-correction passes) with HIP events and estimates the V-cycles an
+ * accepted guess saved (its residual reduction in units of the solve's
+ * measured convergence factor per cycle);
  * when the saving is below the cost, the next B * max(1, cost / saving)
  * solves of that kind skip the net, B = 8, 16, 32, ... (doubling at each
  * failed try), at most 256.                                                */

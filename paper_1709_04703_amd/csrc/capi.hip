@@ -43,8 +43,9 @@ struct sdpm_ctx {
   bool net_ready = false;
   int warm_used = 0;
   // gate of the learned guess (SDPM_WS_LEARNED_GATED), per sub-step kind:
-  // moving averages of the guess time and of one outer iteration, and the
-  // number of solves to skip the net before the next try
+  // moving averages of the guess time and of one V-cycle (with its share of
+  // the outer iteration's passes), and the number of solves to skip the net
+  // before the next try
   double gate_net_ms = 0.0, gate_cycle_ms = 0.0;
   int gate_skip[2] = {0, 0};
   int gate_backoff[2] = {kGateProbe, kGateProbe};
