@@ -173,7 +173,7 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
                           const MeshMap& mm, uint64_t* counts, uint32_t* flags,
                           hipStream_t st);
 // g3 (FP32, 3 per cell in natural order) = -grad Phi by central differences
-// on the cells of box b.
+// on the cells of box b (mesh.hip).
 void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
                        hipStream_t st);
 // Lightcone records of particles [first, first + count) (see sdpm.h): light

@@ -1029,6 +1029,139 @@ template void launch_residual<float>(const double*, const double*, float*, int, 
 template void launch_residual<double>(const double*, const double*, double*, int, const Box&,
                                       double, double*, int*, hipStream_t);
 
+// g3 = -(Phi(i+1) - Phi(i-1)) / 2h per axis on the box, 3 FP32 values per
+// cell in natural order (the interpolation's one 12-byte load per CIC cell);
+// each thread walks kBoxKz planes carrying Phi at k-1 and k.
+__global__ void __launch_bounds__(256)
+k_force_mesh(const double* __restrict__ phi, float* __restrict__ g3, int n, Box b, double inv2h,
+             int gx, int gy) {
+  const int64_t bl = xcd_block();
+  const int bx = (int)(bl % gx), by = (int)((bl / gx) % gy), bz = (int)(bl / ((int64_t)gx * gy));
+  const int i = b.lo[0] + bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int m = n - 1;
+  const int k0 = b.lo[2] + bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
+  double below = phi[lin(i, j, (k0 - 1) & m, n)], ctr = phi[lin(i, j, k0, n)];
+  for (int k = k0; k <= k1; ++k) {
+    const double above = phi[lin(i, j, (k + 1) & m, n)];
+    float* q = g3 + 3 * lin(i, j, k, n);
+    q[0] = (float)(-(phi[lin(ip, j, k, n)] - phi[lin(im, j, k, n)]) * inv2h);
+    q[1] = (float)(-(phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]) * inv2h);
+    q[2] = (float)(-(above - below) * inv2h);
+    below = ctr;
+    ctr = above;
+  }
+}
+
+// k_force_mesh with 4 consecutive cells per thread (tiles as k_residual_v4):
+// vector loads of Phi; a lane's 4 cells are 12 contiguous values, so a row
+// segment of TXV lanes (always within one wave) is staged in LDS and stored
+// as 3 coalesced 16-byte streamed stores per lane (a lane storing its own 48
+// bytes leaves each store instruction strided: 0.78 against 0.62 ms at
+// 512^3); segments that leave the box store cell by cell.
+template <int TXV>
+__global__ void __launch_bounds__(256)
+k_force_mesh_v4(const double* __restrict__ phi, float* __restrict__ g3, int n, Box b,
+                double inv2h) {
+  constexpr int TY = 256 / TXV;
+  __shared__ __attribute__((aligned(16))) float stage[12 * 256];
+  const int ib = b.lo[0] & ~3;
+  const Tile tl = tile_of((b.hi[0] - ib + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int i0 = ib + (tl.bx * TXV + threadIdx.x) * 4;
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
+  if (i0 > b.hi[0] || j > b.hi[1]) return;
+  const int m = n - 1;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
+  const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
+  const int seg0 = ib + tl.bx * TXV * 4;          // first cell of this row segment
+  const bool row_full = seg0 >= b.lo[0] && seg0 + 4 * TXV - 1 <= b.hi[0];
+  Vec4<double> below = *(const Vec4<double>*)(phi + lin(i0, j, (k0 - 1) & m, n));
+  Vec4<double> ctr = *(const Vec4<double>*)(phi + lin(i0, j, k0, n));
+  for (int k = k0; k <= k1; ++k) {
+    const Vec4<double> above = *(const Vec4<double>*)(phi + lin(i0, j, (k + 1) & m, n));
+    const Vec4<double> ym = *(const Vec4<double>*)(phi + lin(i0, jm, k, n));
+    const Vec4<double> yp = *(const Vec4<double>*)(phi + lin(i0, jp, k, n));
+    const double xl = phi[lin(il, j, k, n)], xr = phi[lin(ir, j, k, n)];
+    float out[12];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double left = q == 0 ? xl : ctr.v[q - 1];
+      const double right = q == 3 ? xr : ctr.v[q + 1];
+      out[3 * q + 0] = (float)(-(right - left) * inv2h);
+      out[3 * q + 1] = (float)(-(yp.v[q] - ym.v[q]) * inv2h);
+      out[3 * q + 2] = (float)(-(above.v[q] - below.v[q]) * inv2h);
+    }
+    float* dst = g3 + 3 * lin(i0, j, k, n);
+    if (row_full) {
+      // the TXV lanes of a row segment hold 48 TXV contiguous bytes: stage
+      // them in LDS and store them back as 3 coalesced 16-byte stores per lane
+      float* seg = stage + threadIdx.y * (12 * TXV);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        Vec4<float> o;
+        o.v[0] = out[4 * v], o.v[1] = out[4 * v + 1], o.v[2] = out[4 * v + 2], o.v[3] = out[4 * v + 3];
+        *(Vec4<float>*)(seg + 12 * threadIdx.x + 4 * v) = o;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      float* gseg = g3 + 3 * lin(i0 - 4 * (int)threadIdx.x, j, k, n);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const Vec4<float> o = *(const Vec4<float>*)(seg + 4 * (TXV * v + threadIdx.x));
+        st_stream4(gseg + 4 * (TXV * v + threadIdx.x), o);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else if (full) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        Vec4<float> o;
+        o.v[0] = out[4 * v], o.v[1] = out[4 * v + 1], o.v[2] = out[4 * v + 2], o.v[3] = out[4 * v + 3];
+        st_stream4(dst + 4 * v, o);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (i0 + q >= b.lo[0] && i0 + q <= b.hi[0])
+          for (int d = 0; d < 3; ++d) dst[3 * q + d] = out[3 * q + d];
+    }
+    below = ctr;
+    ctr = above;
+  }
+}
+
+void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
+                       hipStream_t st) {
+  prof_begin(st, K_FORCE_MESH);
+  const int ib = b.lo[0] & ~3;
+  if (b.hi[0] - ib + 1 >= 64) {
+    const int txv = tile_threads(b.hi[0] - ib + 1);
+    const unsigned gx = (unsigned)((b.hi[0] - ib + 4 * txv) / (4 * txv));
+    const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + 256 / txv) / (256 / txv));
+    const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz);
+    const dim3 g(gx * gy * gz), blk(txv, 256 / txv);
+    if (txv == 64)
+      hipLaunchKernelGGL(k_force_mesh_v4<64>, g, blk, 0, st, phi, g3, n, b, inv2h);
+    else if (txv == 32)
+      hipLaunchKernelGGL(k_force_mesh_v4<32>, g, blk, 0, st, phi, g3, n, b, inv2h);
+    else
+      hipLaunchKernelGGL(k_force_mesh_v4<16>, g, blk, 0, st, phi, g3, n, b, inv2h);
+  } else {
+    const int gx = (b.hi[0] - b.lo[0] + kBoxTx) / kBoxTx, gy = (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy;
+    const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
+    hipLaunchKernelGGL(k_force_mesh, dim3((unsigned)gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st,
+                       phi, g3, n, b, inv2h, gx, gy);
+  }
+  prof_end(st, K_FORCE_MESH, 20.0 * box_cells(b));
+}
+
 template <typename T>
 void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st) {
   prof_begin(st, K_CORRECT);

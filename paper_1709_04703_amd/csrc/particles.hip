@@ -259,32 +259,6 @@ __device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm
   }
 }
 
-// g3 = -(Phi(i+1) - Phi(i-1)) / 2h per axis on the box; each thread walks
-// kBoxKz planes carrying Phi at k-1 and k.
-__global__ void __launch_bounds__(256)
-k_force_mesh(const double* __restrict__ phi, float* __restrict__ g3, int n, Box b, double inv2h,
-             int gx, int gy) {
-  const int64_t bl = xcd_block();
-  const int bx = (int)(bl % gx), by = (int)((bl / gx) % gy), bz = (int)(bl / ((int64_t)gx * gy));
-  const int i = b.lo[0] + bx * kBoxTx + threadIdx.x;
-  const int j = b.lo[1] + by * kBoxTy + threadIdx.y;
-  if (i > b.hi[0] || j > b.hi[1]) return;
-  const int m = n - 1;
-  const int k0 = b.lo[2] + bz * kBoxKz;
-  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
-  const int ip = (i + 1) & m, im = (i - 1) & m, jp = (j + 1) & m, jm = (j - 1) & m;
-  double below = phi[lin(i, j, (k0 - 1) & m, n)], ctr = phi[lin(i, j, k0, n)];
-  for (int k = k0; k <= k1; ++k) {
-    const double above = phi[lin(i, j, (k + 1) & m, n)];
-    float* q = g3 + 3 * lin(i, j, k, n);
-    q[0] = (float)(-(phi[lin(ip, j, k, n)] - phi[lin(im, j, k, n)]) * inv2h);
-    q[1] = (float)(-(phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]) * inv2h);
-    q[2] = (float)(-(above - below) * inv2h);
-    below = ctr;
-    ctr = above;
-  }
-}
-
 template <typename PT, bool G3>
 __global__ void __launch_bounds__(256)
 k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float* __restrict__ g3,
@@ -548,16 +522,6 @@ template void launch_drift_deposit<float>(const ParticleArgs&, double, int, cons
                                           uint64_t*, uint32_t*, hipStream_t);
 template void launch_drift_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
                                            uint64_t*, uint32_t*, hipStream_t);
-
-void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,
-                       hipStream_t st) {
-  const int gx = (b.hi[0] - b.lo[0] + kBoxTx) / kBoxTx, gy = (b.hi[1] - b.lo[1] + kBoxTy) / kBoxTy;
-  const int gz = (b.hi[2] - b.lo[2] + kBoxKz) / kBoxKz;
-  prof_begin(st, K_FORCE_MESH);
-  hipLaunchKernelGGL(k_force_mesh, dim3((unsigned)gx * gy * gz), dim3(kBoxTx, kBoxTy), 0, st, phi, g3,
-                     n, b, inv2h, gx, gy);
-  prof_end(st, K_FORCE_MESH, 20.0 * box_cells(b));
-}
 
 template <typename PT>
 void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,

@@ -223,3 +223,50 @@ def test_paired_cycles_same_state_fewer_outer_iterations(prec, cpo_max):
     assert rel_rms(out[m][2], out[1][2]) < 1e-5
     dx = periodic_delta(out[m][3], out[1][3], box)
     assert np.abs(dx).max() < 1e-5 * box / ng
+
+
+def test_one_step_on_a_wide_frozen_exterior_box():
+    """One mixed-precision step on a frozen-exterior box wide enough for the
+    vector stencil kernels (256^3 mesh, 128^3 particles, 2000 Mpc/h, a = 0.8:
+    r_lc = 706 Mpc/h, box cells 33 .. 223, whose rows start inside a 4-cell
+    vector), from the oracle's own starting state: positions and momenta of
+    the particles both sides keep, and the potential."""
+    import torch
+    ng, npart, box, a0, da = 256, 128, 2000.0, 0.8, 0.01
+    x, p, ids = zeldovich_ics(npart, box, a0, 2561)
+    cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=npart**3, tol=1e-10)
+    ocfg = oracle_config(cfg)
+    sim = make_sim(cfg, npart**3)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    s0 = sim.state()
+    log(f"box {s0['lo']} .. {s0['hi']} periodic={s0['periodic']} active={sim.n_active}")
+    assert s0["periodic"] == 0 and not ost.periodic
+    assert s0["lo"] == list(ost.lo) and s0["hi"] == list(ost.hi)
+    assert s0["hi"][0] - s0["lo"][0] + 1 >= 64 and s0["lo"][0] % 4 != 0
+    assert sim.n_active == ost.n_active
+    sim.phi.copy_(torch.as_tensor(ost.phi))
+    # the oracle takes the library's FP32 momenta, matched by id
+    k = ost.n_active
+    _, gp0, gid0 = sim.particles()
+    order = np.argsort(gid0)
+    at = np.searchsorted(gid0[order], ost.ids[:k])
+    assert np.array_equal(gid0[order][at], ost.ids[:k])
+    ost.p[:k] = gp0[order][at]
+    st = sim.step(a0, da)
+    ost = pm.step(ost, ocfg, da)
+    assert max(st["res"]) <= cfg.tol
+    gx, gp, gid = sim.particles()
+    common = np.intersect1d(gid, ost.ids[:ost.n_active])
+    assert len(common) >= min(len(gid), ost.n_active) - 2
+    gsel, osel = np.isin(gid, common), np.isin(ost.ids[:ost.n_active], common)
+    dx = _by_id(gx[gsel], gid[gsel]) - _by_id(ost.x[:ost.n_active][osel], ost.ids[:ost.n_active][osel])
+    perr = rel_rms(_by_id(gp[gsel], gid[gsel]), _by_id(ost.p[:ost.n_active][osel],
+                                                       ost.ids[:ost.n_active][osel]))
+    phierr = rel_rms(sim.phi_numpy(), ost.phi)
+    log(f"  max|dx|={np.abs(dx).max():.2e} p err={perr:.2e} phi err={phierr:.2e}")
+    assert np.abs(dx).max() <= 1e-9 * box
+    assert perr <= 2e-7
+    assert phierr <= 1e-7
+    sim.close()
