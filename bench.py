@@ -534,8 +534,8 @@ def main():
                          "known-size kernel that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the design notes for how the step would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the design notes describe how the step would shard)", file=sys.stderr)
         sys.exit(2)
 
     import torch
