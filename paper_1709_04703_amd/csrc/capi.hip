@@ -545,9 +545,9 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   // iterations (the residual keeps falling), never stop early.
   // An outer iteration runs further V-cycles on its defect equation (up to
   // cycles_per_outer) while fewer are predicted, with margin, to leave the
-  // norm above the threshold: each further cycle reduces the error as a
-  // further outer iteration would (the working precision's rounding floor
-  // lies far below the factor of four cycles) and saves that iteration's FP64
+  // norm above the threshold: a V-cycle is a linear stationary iteration, so
+  // each further cycle reduces the error as a further outer iteration would,
+  // down to the rounding floor below, and saves that iteration's FP64
   // correction and residual passes.
   // The cycles of one outer iteration cannot take the defect below the
   // rounding of the correction they store in T: |A de| <= (12 + kappa h^2)
