@@ -659,7 +659,8 @@ def main():
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
                          f"z={args.z_init:g}->0 in {args.schedule} steps (steps "
                          f"{args.warmup}..{args.warmup + args.steps - 1} timed), shrinking "
-                         "domain, c_eff = 0.019 h c, multigrid 6 levels V(2,2) to 1e-8"),
+                         "domain, c_eff = 0.019 h c, multigrid V(2,2) (up to 6 levels, up to 4 "
+                         "cycles per FP64 defect correction) to 1e-8"),
             "global_batch": int(ics[0].shape[0]),
             "parallelism": "single GPU",
         },
