@@ -55,6 +55,10 @@ struct sdpm_ctx {
   bool ex_have[2] = {false, false};
   double ex_dtau[2] = {0.0, 0.0};
   double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
+  // deposit: LDS tile size (see launch_drift_deposit) and the workgroups of
+  // the last deposit
+  bool dep_big_tile = false;
+  int64_t dep_workgroups = 0;
   // residual reduction per V-cycle of the last solve (geometric mean), used
   // to run ahead of the host without a sync per iteration and to pair cycles
   double rho_est = 0.1;
@@ -679,9 +683,12 @@ int deposit(sdpm_ctx* c, double drift_coef, int drift) {
   const ParticleArgs pa = particle_args(c);
   const MeshMap mm = mesh_map(c);
   if (c->cfg.precision == SDPM_MIXED)
-    launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
+    launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags,
+                                c->dep_big_tile, c->st);
   else
-    launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
+    launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags,
+                                 c->dep_big_tile, c->st);
+  c->dep_workgroups = deposit_workgroups(pa.n);
   return SDPM_OK;
 }
 
@@ -1107,6 +1114,9 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   c->lc_prev_r = sc.r_lc_end;
   rc = sync_scalars(c, 1);
   if (rc) return rc;
+  // the deposit tile for the next step: the larger one once more than a
+  // quarter of this step's deposit workgroups overflowed the smaller
+  c->dep_big_tile = 4 * (int64_t)((const uint32_t*)(c->hpin + 16))[2] > c->dep_workgroups;
   int lc_full = SDPM_OK;
   if (lc_fixed) {
     const int64_t crossed = (int64_t)((const unsigned long long*)(c->hpin + kHostLcCount))[0];

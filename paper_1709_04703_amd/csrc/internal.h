@@ -168,10 +168,15 @@ struct MeshMap {
   double scale;       // s = ng 2^B / L
   Box active;         // deposit / interpolation cells must lie inside
 };
+// Drift (when drift != 0) and fixed-point CIC deposit into counts.  flags[0]
+// collects error bits; flags[2] counts the workgroups whose particles span
+// more cells than the small LDS tile; big_tile takes the larger tile.
 template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
-                          const MeshMap& mm, uint64_t* counts, uint32_t* flags,
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, bool big_tile,
                           hipStream_t st);
+// Workgroups of a deposit of n particles.
+int64_t deposit_workgroups(int64_t n);
 // g3 (FP32, 3 per cell in natural order) = -grad Phi by central differences
 // on the cells of box b (mesh.hip).
 void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,

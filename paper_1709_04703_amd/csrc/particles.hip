@@ -75,13 +75,17 @@ __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0,
 }
 
 // Drift + deposit, 1024 particles per workgroup.  When the CIC cells of the
-// workgroup's particles fit a box of at most kDepLds cells (always for
-// spatially sorted particles, and for lattice order too) the weights are
-// summed with 64-bit LDS atomics and each touched cell is flushed with one
-// global atomic; otherwise every corner goes straight to global atomics.
-// Integer sums: the result is the same either way and in any order.
+// workgroup's particles fit a box of at most LDS cells the weights are summed
+// with 64-bit LDS atomics and each touched cell is flushed with one global
+// atomic; otherwise every corner goes straight to global atomics.  Integer
+// sums: the result is the same either way and in any order.  Two tile sizes:
+// kDepLds cells (32 KB) fit the particles of a workgroup while they stay near
+// their lattice order inside a sort block; once they have moved about a
+// whole 16^3-cell block apart its 17^3-cell box needs kDepLdsBig (48 KB,
+// fewer workgroups per CU).  Workgroups whose box exceeds kDepLds are counted
+// in flags[2] so that the caller can choose the tile for the next deposit.
 constexpr int kDepPer = 4;
-constexpr int kDepLds = 4096;
+constexpr int kDepLds = 4096, kDepLdsBig = 6144;
 
 __device__ inline int wave_min(int v) {
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_down(v, off, 64));
@@ -92,11 +96,11 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-template <typename PT, bool DRIFT>
+template <typename PT, bool DRIFT, int LDS>
 __global__ void __launch_bounds__(256)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
-  __shared__ unsigned long long acc[kDepLds];
+  __shared__ unsigned long long acc[LDS];
   __shared__ int blo[3], bhi[3];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * (256 * kDepPer);
@@ -150,7 +154,9 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
   const int lx = bhi[0] - blo[0] + 2, ly = bhi[1] - blo[1] + 2, lz = bhi[2] - blo[2] + 2;
   if (lx <= 1) return;                                   // no valid particle in the workgroup
   const int m = mm.ng - 1;
-  const bool use_lds = (int64_t)lx * ly * lz <= kDepLds;
+  const int64_t vol_box = (int64_t)lx * ly * lz;
+  if (tid == 0 && vol_box > kDepLds) atomicAdd(flags + 2, 1u);
+  const bool use_lds = vol_box <= LDS;
   if (use_lds) {
     const int vol = lx * ly * lz;
     for (int q = tid; q < vol; q += 256) acc[q] = 0ull;
@@ -504,24 +510,29 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
-                          const MeshMap& mm, uint64_t* counts, uint32_t* flags,
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, bool big_tile,
                           hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st, K_DEPOSIT);
   const dim3 g(grid_for(pa.n, 256 * kDepPer));
-  if (drift)
-    hipLaunchKernelGGL((k_drift_deposit<PT, true>), g, dim3(256), 0, st, pa, drift_coef, mm,
-                       (unsigned long long*)counts, flags);
-  else
-    hipLaunchKernelGGL((k_drift_deposit<PT, false>), g, dim3(256), 0, st, pa, drift_coef, mm,
-                       (unsigned long long*)counts, flags);
+  unsigned long long* cu = (unsigned long long*)counts;
+#define SDPM_DEP(D, L)                                                                          \
+  hipLaunchKernelGGL((k_drift_deposit<PT, D, L>), g, dim3(256), 0, st, pa, drift_coef, mm, cu, flags)
+  if (drift) {
+    if (big_tile) SDPM_DEP(true, kDepLdsBig); else SDPM_DEP(true, kDepLds);
+  } else {
+    if (big_tile) SDPM_DEP(false, kDepLdsBig); else SDPM_DEP(false, kDepLds);
+  }
+#undef SDPM_DEP
   const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
   prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
 }
+
+int64_t deposit_workgroups(int64_t n) { return (n + 256 * kDepPer - 1) / (256 * kDepPer); }
 template void launch_drift_deposit<float>(const ParticleArgs&, double, int, const MeshMap&,
-                                          uint64_t*, uint32_t*, hipStream_t);
+                                          uint64_t*, uint32_t*, bool, hipStream_t);
 template void launch_drift_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
-                                           uint64_t*, uint32_t*, hipStream_t);
+                                           uint64_t*, uint32_t*, bool, hipStream_t);
 
 template <typename PT>
 void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,
