@@ -171,3 +171,46 @@ def test_fullsize_removal(big):
                                           cfg.box_align)
     assert dirichlet and st["periodic"] == 0
     assert list(st["lo"]) == list(lo) and list(st["hi"]) == list(hi)
+
+
+def test_fullsize_extrapolated_start_step():
+    """The headline solve configuration at full size: mixed precision with the
+    extrapolated start, two steps; the second applies the start (each solve
+    begins from the potential plus the previous step's scaled change, the
+    finer cycles per correction and the short hierarchy as in the bench), and
+    both of its potentials are the exact solves of the oracle's own source of
+    the library's (exact) counts within cond(A) tol."""
+    import paper_1709_04703_amd as P
+    a0 = 1.0 / (1.0 + Z_INIT)
+    x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
+    n = x.shape[0]
+    cfg = lib_config(NG, BOX, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED, n_initial=n,
+                     sort_every=10, warm_start=P.SDPM_WS_EXTRAP)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    del x, p, ids
+    sim.init_potential(a0)
+    edges = np.linspace(a0, 1.0, SCHEDULE + 1)
+    h = BOX / NG
+    sim.step(edges[0], edges[1] - edges[0])
+    phi0 = sim.phi_numpy().copy()
+    a, da = edges[1], edges[2] - edges[1]
+    log("full size: second step with the extrapolated start")
+    st = sim.step(a, da)
+    assert max(st["res"]) <= cfg.tol
+    log(f"  V-cycles {st['vcycles']}, outer iterations {st['outer_iters']}, "
+        f"start residual {st['res0']}")
+    sc = ocosmo.step_scalars(a, da, cfg.omega_m, cfg.omega_l, BOX, NG, cfg.c_grav, cfg.c_light)
+    k1, k2 = st["kappa_h2"]
+    f = pm.source(sim.counts_numpy().reshape(NG, NG, NG), n, B, sc["s_half"], h, True)
+    phi_half = pm.solve_periodic(f - k1 * phi0, k1)
+    del phi0
+    phi_half_gpu = (f - sim.rhs.cpu().numpy()) / k2
+    err1 = rel_rms(phi_half_gpu, phi_half)
+    del phi_half_gpu
+    phi1 = pm.solve_periodic(f - k2 * phi_half, k2)
+    err2 = rel_rms(sim.phi_numpy(), phi1)
+    log(f"  potential errors: half step {err1:.2e}, full step {err2:.2e}")
+    assert err1 <= cond_periodic(NG, k1) * cfg.tol
+    assert err2 <= 2.0 * cond_periodic(NG, k2) * cfg.tol
+    sim.close()
