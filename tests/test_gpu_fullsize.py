@@ -214,3 +214,55 @@ def test_fullsize_extrapolated_start_step():
     assert err1 <= cond_periodic(NG, k1) * cfg.tol
     assert err2 <= 2.0 * cond_periodic(NG, k2) * cfg.tol
     sim.close()
+
+
+def test_fullsize_frozen_exterior_step():
+    """The shrinking phase at full size, as the bench times it: the 512^3 run
+    to step 160 of the 200-step schedule (z = 0.24: a 383^3-cell
+    frozen-exterior box, 17 % of the particles active), then one step whose
+    two potentials, on the box, are the oracle's exact Dirichlet solves (DST)
+    of the source of the library's exact counts with the frozen exterior,
+    within cond(A) tol; the exterior is left as it was."""
+    import paper_1709_04703_amd as P
+    a0 = 1.0 / (1.0 + Z_INIT)
+    x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
+    n = x.shape[0]
+    cfg = lib_config(NG, BOX, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED, n_initial=n,
+                     sort_every=10)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    del x, p, ids
+    sim.init_potential(a0)
+    edges = np.linspace(a0, 1.0, SCHEDULE + 1)
+    log("full size: 160 steps into the shrinking phase")
+    for s in range(160):
+        sim.step(edges[s], edges[s + 1] - edges[s])
+    st0 = sim.state()
+    lo, hi = np.array(st0["lo"]), np.array(st0["hi"])
+    log(f"  box {st0['lo']} .. {st0['hi']}, active {sim.n_active} of {n}")
+    assert st0["periodic"] == 0
+    phi0 = sim.phi_numpy().copy()
+    a, da = edges[160], edges[161] - edges[160]
+    h = BOX / NG
+    st = sim.step(a, da)
+    assert max(st["res"]) <= cfg.tol
+    sc = ocosmo.step_scalars(a, da, cfg.omega_m, cfg.omega_l, BOX, NG, cfg.c_grav, cfg.c_light)
+    k1, k2 = st["kappa_h2"]
+    sl = (slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
+    f = pm.source(sim.counts_numpy().reshape(NG, NG, NG), n, B, sc["s_half"], h, False)
+    phi_half = pm.solve_box(phi0, f - k1 * phi0, lo, hi, k1)
+    rhs2 = sim.rhs.cpu().numpy()
+    err1 = rel_rms(((f - rhs2) / k2)[sl], phi_half[sl])
+    del rhs2
+    phi1 = pm.solve_box(phi_half, f - k2 * phi_half, lo, hi, k2)
+    phi = sim.phi_numpy()
+    err2 = rel_rms(phi[sl], phi1[sl])
+    log(f"  potential errors on the box: half step {err1:.2e}, full step {err2:.2e}")
+    nmax = int(max(hi - lo + 1))
+    cond = lambda kap: (12.0 + kap) / (3 * (2 - 2 * np.cos(np.pi / (nmax + 1))) + kap)
+    assert err1 <= cond(k1) * cfg.tol
+    assert err2 <= 2.0 * cond(k2) * cfg.tol
+    outside = np.ones(phi.shape, dtype=bool)
+    outside[sl] = False
+    assert np.array_equal(phi[outside], phi0[outside])
+    sim.close()
