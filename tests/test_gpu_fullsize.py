@@ -222,7 +222,8 @@ def test_fullsize_frozen_exterior_step():
     frozen-exterior box, 17 % of the particles active), then one step whose
     two potentials, on the box, are the oracle's exact Dirichlet solves (DST)
     of the source of the library's exact counts with the frozen exterior,
-    within cond(A) tol; the exterior is left as it was."""
+    within cond(A) tol; the exterior is left as it was; and its lightcone
+    records are the removed particles, in removal order, on the sphere."""
     import paper_1709_04703_amd as P
     a0 = 1.0 / (1.0 + Z_INIT)
     x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
@@ -244,8 +245,26 @@ def test_fullsize_frozen_exterior_step():
     phi0 = sim.phi_numpy().copy()
     a, da = edges[160], edges[161] - edges[160]
     h = BOX / NG
+    sim.set_lightcone(4_000_000)
+    n_before = sim.n_active
     st = sim.step(a, da)
     assert max(st["res"]) <= cfg.tol
+    # lightcone output: one record per removed particle, in removal order,
+    # each (crossing strictly inside the step) on the sphere r_lc + u c dtau
+    rid, ra, rx, _ = sim.lightcone_records()
+    _, _, ids_all = sim.particles(all_particles=True)
+    k = sim.n_active
+    assert st["n_removed"] == n_before - k > 0
+    assert np.array_equal(rid.astype(np.uint32), ids_all[k:n_before])
+    u = (a + da - ra) / da
+    inner = (u > 0.0) & (u < 1.0)
+    dist = np.linalg.norm(rx[inner] - np.asarray(cfg.x_obs), axis=1)
+    r_u = st["r_lc"] + u[inner] * cfg.c_light * st["dtau"]
+    log(f"  {len(rid)} lightcone records, {int(inner.sum())} inside the step, "
+        f"max |distance - r| = {np.abs(dist - r_u).max():.2e} Mpc/h")
+    assert inner.sum() > 0.9 * len(rid)
+    assert np.abs(dist - r_u).max() <= 1e-9 * r_u.max()
+    del rid, ra, rx, ids_all
     sc = ocosmo.step_scalars(a, da, cfg.omega_m, cfg.omega_l, BOX, NG, cfg.c_grav, cfg.c_light)
     k1, k2 = st["kappa_h2"]
     sl = (slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
