@@ -726,7 +726,7 @@ k_prolong_black_v4(const float* __restrict__ ec, float* __restrict__ ef, int nc,
     }
     const float w = 0.125f * (float)((3 - ny) * (3 - nz));
     const int64_t frow = hcf + ((int64_t)k * nf + j) * hnf + h0;
-    const Vec4<float> e = *(const Vec4<float>*)(ef + frow);
+    const Vec4<float> e = ld_stream4(ef + frow);     // read and written once: streamed
     float out[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[q] = e.v[q] + w * (L[q] + (p ? L[q + 1] : L[q]));
@@ -734,7 +734,7 @@ k_prolong_black_v4(const float* __restrict__ ec, float* __restrict__ ef, int nc,
       Vec4<float> o;
 #pragma unroll
       for (int q = 0; q < 4; ++q) o.v[q] = out[q];
-      *(Vec4<float>*)(ef + frow) = o;
+      st_stream4(ef + frow, o);
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
