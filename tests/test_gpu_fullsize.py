@@ -222,8 +222,9 @@ def test_fullsize_frozen_exterior_step():
     frozen-exterior box, 17 % of the particles active), then one step whose
     two potentials, on the box, are the oracle's exact Dirichlet solves (DST)
     of the source of the library's exact counts with the frozen exterior,
-    within cond(A) tol; the exterior is left as it was; and its lightcone
-    records are the removed particles, in removal order, on the sphere."""
+    within cond(A) tol; the exterior is left as it was; its deposit is exact
+    (total mass and whole planes); and its lightcone records are the removed
+    particles, in removal order, on the sphere."""
     import paper_1709_04703_amd as P
     a0 = 1.0 / (1.0 + Z_INIT)
     x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
@@ -245,10 +246,25 @@ def test_fullsize_frozen_exterior_step():
     phi0 = sim.phi_numpy().copy()
     a, da = edges[160], edges[161] - edges[160]
     h = BOX / NG
+    x0, p0, _ = sim.particles()
     sim.set_lightcone(4_000_000)
     n_before = sim.n_active
     st = sim.step(a, da)
     assert max(st["res"]) <= cfg.tol
+    # the deposit of the drifted positions (no wrap on the box): the total
+    # mass and whole z-planes exact (late in the run the deposit takes its
+    # larger LDS tile)
+    xh = x0 + p0 * (0.5 * st["dtau"] / a)
+    del x0, p0
+    counts = sim.counts_numpy().reshape(NG, NG, NG)
+    tot = int((counts & np.uint64(0xFFFFFFFF)).sum(dtype=np.uint64)) + \
+        (int((counts >> np.uint64(32)).sum(dtype=np.uint64)) << 32)
+    assert tot == n_before << (3 * B)
+    kz = pm.fixed_point_coords(xh[:, 2:3], NG, BOX, B, False)[:, 0] >> B
+    for kp in (int(lo[2]), 200, 256, int(hi[2])):
+        sel = (kz == kp) | (kz == kp - 1)
+        assert np.array_equal(counts[kp], pm.deposit(xh[sel], NG, BOX, B, False)[kp]), kp
+    del counts, kz, xh
     # lightcone output: one record per removed particle, in removal order,
     # each (crossing strictly inside the step) on the sphere r_lc + u c dtau
     rid, ra, rx, _ = sim.lightcone_records()
