@@ -71,6 +71,7 @@ class Config:
     frac_bits: int = 14
     n_initial: int = 0
     solver: str = "implicit"     # "implicit": backward Euler; "ade": the paper's ADE sweeps
+    assignment: str = "cic"      # "cic" or "tsc" (Sec. 2.4 names both schemes)
 
     def observer(self) -> np.ndarray:
         if self.x_obs is None:
@@ -139,13 +140,59 @@ def _corners(u: np.ndarray, ng: int, frac_bits: int, periodic: bool):
                 yield (kk * ng + jj) * ng + ii, wt
 
 
+def tsc_weights(u: np.ndarray, frac_bits: int):
+    """TSC in fixed point (Sec. 2.4 names TSC beside CIC; the integer form is
+    a reading): the nearest node i = (U + 2^(B-1)) >> B of the coordinate U,
+    the offset D = U - i 2^B in [-2^(B-1), 2^(B-1)), and the three weights of
+    nodes i - 1, i, i + 1 in units of 2^-B: the continuous TSC weights
+    (1/2 - d)^2 / 2 and (1/2 + d)^2 / 2 (d = D / 2^B) rounded to the nearest
+    unit, and the middle one 2^B minus both, so that they sum to 2^B exactly.
+    Returns (node, [w_minus, w_mid, w_plus]) as int64 arrays."""
+    one = np.int64(1) << frac_bits
+    half = one >> 1
+    node = (u + half) >> frac_bits
+    d = u - (node << frac_bits)
+    wm = ((half - d) ** 2 + one) >> (frac_bits + 1)
+    wp = ((half + d) ** 2 + one) >> (frac_bits + 1)
+    return node, [wm, one - wm - wp, wp]
+
+
+def _tsc_corners(u: np.ndarray, ng: int, frac_bits: int, periodic: bool):
+    """Yield (flat cell index, uint64 weight product) for the 27 TSC nodes."""
+    node, w = tsc_weights(u, frac_bits)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                ii = node[:, 0] + dx
+                jj = node[:, 1] + dy
+                kk = node[:, 2] + dz
+                if periodic:
+                    ii %= ng
+                    jj %= ng
+                    kk %= ng
+                if ii.size and (ii.max() >= ng or jj.max() >= ng or kk.max() >= ng
+                                or ii.min() < 0 or jj.min() < 0 or kk.min() < 0):
+                    raise ValueError("TSC node outside the mesh")
+                wt = (w[dx + 1][:, 0].astype(np.uint64) * w[dy + 1][:, 1].astype(np.uint64)
+                      * w[dz + 1][:, 2].astype(np.uint64))
+                yield (kk * ng + jj) * ng + ii, wt
+
+
+def _assignment_corners(assignment: str):
+    if assignment == "cic":
+        return _corners
+    if assignment == "tsc":
+        return _tsc_corners
+    raise ValueError(f"unknown assignment {assignment!r}")
+
+
 def deposit(x: np.ndarray, ng: int, box: float, frac_bits: int,
-            periodic: bool) -> np.ndarray:
-    """Exact CIC mass counts C (uint64, shape (N,N,N)); each particle adds
-    weight products summing to 2^(3B)."""
+            periodic: bool, assignment: str = "cic") -> np.ndarray:
+    """Exact mass counts C (uint64, shape (N,N,N)) of the CIC (default) or
+    TSC assignment; each particle adds weight products summing to 2^(3B)."""
     u = fixed_point_coords(x, ng, box, frac_bits, periodic)
     c = np.zeros(ng**3, dtype=np.uint64)
-    for flat, wt in _corners(u, ng, frac_bits, periodic):
+    for flat, wt in _assignment_corners(assignment)(u, ng, frac_bits, periodic):
         np.add.at(c, flat, wt)
     return c.reshape(ng, ng, ng)
 
@@ -254,14 +301,14 @@ def force_mesh(phi: np.ndarray, h: float) -> np.ndarray:
 
 
 def interpolate(x: np.ndarray, g: np.ndarray, ng: int, box: float, frac_bits: int,
-                periodic: bool) -> np.ndarray:
-    """CIC interpolation with the deposit's own fixed-point weights (same
+                periodic: bool, assignment: str = "cic") -> np.ndarray:
+    """Interpolation with the deposit's own fixed-point weights (same
     scheme both ways, the footnote of Sec. 2.4); returns (n, 3)."""
     u = fixed_point_coords(x, ng, box, frac_bits, periodic)
     out = np.zeros((x.shape[0], 3))
     norm = 2.0 ** (-3 * frac_bits)
     gf = g.reshape(3, -1)
-    for flat, wt in _corners(u, ng, frac_bits, periodic):
+    for flat, wt in _assignment_corners(assignment)(u, ng, frac_bits, periodic):
         wf = wt.astype(np.float64) * norm
         for comp in range(3):
             out[:, comp] += wf * gf[comp][flat]
@@ -384,9 +431,14 @@ def _check_domain(x: np.ndarray, state: State, cfg: Config) -> None:
     if state.periodic or x.shape[0] == 0:
         return
     u = fixed_point_coords(x, cfg.ng, cfg.box, cfg.frac_bits, False)
-    cell = u >> cfg.frac_bits
-    if np.any(cell < state.lo) or np.any(cell + 1 > state.hi):
-        raise ValueError("particle CIC support leaves the active box")
+    if cfg.assignment == "tsc":
+        node, _ = tsc_weights(u, cfg.frac_bits)
+        first, last = node - 1, node + 1
+    else:
+        first = u >> cfg.frac_bits
+        last = first + 1
+    if np.any(first < state.lo) or np.any(last > state.hi):
+        raise ValueError("particle assignment support leaves the active box")
 
 
 def solve(phi: np.ndarray, rhs: np.ndarray, state: State, kappa_h2: float) -> np.ndarray:
@@ -418,7 +470,7 @@ def init_state(x, p, ids, cfg: Config, a: float) -> State:
     shrink(st, cfg, a)
     n = st.n_active
     h = cfg.box / ng
-    counts = deposit(st.x[:n], ng, cfg.box, cfg.frac_bits, st.periodic)
+    counts = deposit(st.x[:n], ng, cfg.box, cfg.frac_bits, st.periodic, cfg.assignment)
     f = source(counts, cfg.n_initial, cfg.frac_bits, 1.5 * cfg.omega_m / a, h, st.periodic)
     st.phi = solve(st.phi, f, st, 0.0)
     return st
@@ -443,7 +495,7 @@ def step(state: State, cfg: Config, da: float, diag: dict | None = None) -> Stat
         x = _wrap(x, cfg.box)
     _check_domain(x, st, cfg)
     # density at t + dt/2
-    counts = deposit(x, cfg.ng, cfg.box, cfg.frac_bits, st.periodic)
+    counts = deposit(x, cfg.ng, cfg.box, cfg.frac_bits, st.periodic, cfg.assignment)
     f = source(counts, cfg.n_initial, cfg.frac_bits, sc["s_half"], h, st.periodic)
     # Phi from t to t + dt/2
     k1 = sc["kappa1_h2"]
@@ -455,7 +507,7 @@ def step(state: State, cfg: Config, da: float, diag: dict | None = None) -> Stat
         phi_half = solve(st.phi, f - k1 * st.phi, st, k1)
     # grad Phi, interpolation, kick with a(t + dt/2)  (Eq. 8)
     g = force_mesh(phi_half, h)
-    gp = interpolate(x, g, cfg.ng, cfg.box, cfg.frac_bits, st.periodic)
+    gp = interpolate(x, g, cfg.ng, cfg.box, cfg.frac_bits, st.periodic, cfg.assignment)
     p = p + gp * (sc["a_half"] * sc["dtau"])
     # drift 1/2 with a(t + dt)  (Eq. 9)
     x = x + p * (half / (a + da))
