@@ -89,6 +89,15 @@ enum { SDPM_WS_EXTRAP = 4 };
  * with their work area in the workspace; needs warm_start == SDPM_WS_PREV;
  * reports 0 iterations and residual 0 for FFT solves.                      */
 enum { SDPM_SOLVER_IMPLICIT = 0, SDPM_SOLVER_ADE = 1, SDPM_SOLVER_FFT = 2 };
+/* sdpm_config.assignment.  CIC: the 2^3 cells around a particle, axis
+ * weights (2^B - q, q) of the fixed-point coordinate U = floor(x s),
+ * q = U mod 2^B.  TSC: the 3^3 nodes around the nearest node
+ * i = (U + 2^(B-1)) >> B; with D = U - i 2^B the outer axis weights are
+ * (2^(B-1) -+ D)^2 / 2^(B+1) rounded to the nearest integer and the middle
+ * one 2^B minus both.  Either way the products sum to 2^(3B) exactly, the
+ * deposit is exact integer arithmetic, and the active box must hold the
+ * whole support (one node more on each side for TSC).                      */
+enum { SDPM_ASSIGN_CIC = 0, SDPM_ASSIGN_TSC = 1 };
 
 typedef struct sdpm_ctx sdpm_ctx;                  /* opaque */
 
@@ -133,6 +142,9 @@ typedef struct sdpm_config {
                             stays well above the rounding floor of the
                             stored correction; the result meets tol either
                             way                                              */
+  int32_t assignment;    /* SDPM_ASSIGN_CIC (default) or SDPM_ASSIGN_TSC: the
+                            mass assignment and force interpolation scheme
+                            (Sec. 2.4 names both; the same weights both ways) */
 } sdpm_config;
 
 /* Caller-owned device arrays.  x: FP64 positions in [0, box); p: momenta,

@@ -20,6 +20,7 @@ SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW, SDPM_ESTATE, SDPM_EFULL = -4, -5, -6
 SDPM_MIXED, SDPM_PLAIN_FP64 = 0, 1
 SDPM_WS_PREV, SDPM_WS_LEARNED, SDPM_WS_LEARNED_GATED, SDPM_WS_EXTRAP = 0, 1, 2, 4
 SDPM_SOLVER_IMPLICIT, SDPM_SOLVER_ADE, SDPM_SOLVER_FFT = 0, 1, 2
+SDPM_ASSIGN_CIC, SDPM_ASSIGN_TSC = 0, 1
 SDPM_PK_SHOT, SDPM_PK_JING = 1, 2
 
 ERROR_NAMES = {
@@ -56,6 +57,7 @@ class Config(ctypes.Structure):
         ("warm_start", ctypes.c_int32), ("n_initial", ctypes.c_int64),
         ("sort_every", ctypes.c_int32), ("sort_shift", ctypes.c_int32),
         ("solver", ctypes.c_int32), ("cycles_per_outer", ctypes.c_int32),
+        ("assignment", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -168,6 +168,8 @@ int validate(const sdpm_config* c, char* msg, size_t len) {
   if (c->solver != SDPM_SOLVER_IMPLICIT && c->solver != SDPM_SOLVER_ADE &&
       c->solver != SDPM_SOLVER_FFT)
     return snprintf(msg, len, "unknown solver %d", c->solver), SDPM_EINVAL;
+  if (c->assignment != SDPM_ASSIGN_CIC && c->assignment != SDPM_ASSIGN_TSC)
+    return snprintf(msg, len, "unknown assignment %d", c->assignment), SDPM_EINVAL;
   if (c->cycles_per_outer < 1 || c->cycles_per_outer > kMaxCyclesPerOuter)
     return snprintf(msg, len, "cycles_per_outer must be in 1..%d", kMaxCyclesPerOuter), SDPM_EINVAL;
   if (c->solver == SDPM_SOLVER_FFT && c->warm_start != SDPM_WS_PREV)
@@ -379,6 +381,7 @@ MeshMap mesh_map(sdpm_ctx* c) {
   mm.box = c->cfg.box;
   mm.scale = (double)((int64_t)c->cfg.ng << c->cfg.frac_bits) / c->cfg.box;
   mm.active = c->periodic ? full_box(c->cfg.ng) : c->box;
+  mm.tsc = c->cfg.assignment == SDPM_ASSIGN_TSC ? 1 : 0;
   return mm;
 }
 
@@ -832,6 +835,7 @@ int sdpm_config_default(sdpm_config* cfg, int32_t ng, double box) {
   cfg->sort_shift = ng >= 64 ? 4 : 0;   // Morton order of 16^3-cell blocks
   cfg->solver = SDPM_SOLVER_IMPLICIT;
   cfg->cycles_per_outer = 4;
+  cfg->assignment = SDPM_ASSIGN_CIC;
   return SDPM_OK;
 }
 

@@ -167,6 +167,7 @@ struct MeshMap {
   double box;         // L
   double scale;       // s = ng 2^B / L
   Box active;         // deposit / interpolation cells must lie inside
+  int tsc;            // 0: CIC, 1: TSC assignment
 };
 // Drift (when drift != 0) and fixed-point CIC deposit into counts.  flags[0]
 // collects error bits; flags[2] counts the workgroups whose particles span

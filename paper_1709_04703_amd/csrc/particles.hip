@@ -7,6 +7,11 @@
 // the fraction q = U mod 2^B; the axis weights are (2^B - q, q) and the
 // 8 products (<= 2^(3B)) are added to 64-bit integer counts, so the deposit
 // is exact and independent of the order in which atomics land.
+// TSC (Sec. 2.4 names it beside CIC; sdpm_config.assignment): the nearest
+// node i = (U + 2^(B-1)) >> B, the offset D = U - i 2^B, and the weights of
+// nodes i - 1, i, i + 1: (2^(B-1) -+ D)^2 / 2^(B+1) rounded to the nearest
+// integer for the outer two and 2^B minus both for the middle, so that the
+// 27 products again sum to 2^(3B) exactly.
 // Leapfrog (Sec. 2.2 Eqs. 7-9): x += p (dtau/2)/a ; p += a_half g dtau ;
 // x += p (dtau/2)/a_next, with g = -grad Phi by central differences.
 #include "internal.h"
@@ -14,39 +19,51 @@
 namespace sdpm {
 namespace {
 
-struct Cic {
+// The S x S x S mesh nodes a particle is assigned to (S = 2: CIC, S = 3:
+// TSC): the first node per axis (unwrapped: it may be -1 or reach ng on a
+// periodic mesh, where the users wrap it with & (ng - 1)) and the weights.
+template <int S>
+struct Stencil {
   int cell[3];
-  uint64_t w[3][2];
+  uint64_t w[3][S];
 };
 
-// Fixed-point coordinates of one particle.  Returns 0 or a kFlag* bit.
-__device__ inline uint32_t cic_setup(const double x[3], const MeshMap& mm, Cic& c) {
+// Fixed-point coordinates and weights of one particle.  Returns 0 or a
+// kFlag* bit (then the stencil is a harmless one-node placeholder).
+template <int S>
+__device__ inline uint32_t assign_setup(const double x[3], const MeshMap& mm, Stencil<S>& c) {
   const int64_t span = (int64_t)mm.ng << mm.frac_bits;
   const uint64_t one = 1ull << mm.frac_bits;
   uint32_t bad = 0;
   for (int d = 0; d < 3; ++d) {
     const double u = x[d] * mm.scale;
-    if (u != u || __builtin_isinf(u)) {
-      bad |= kFlagOverflow;
+    const bool nan_or_inf = u != u || __builtin_isinf(u);
+    if (nan_or_inf || !(u >= 0.0 && u <= (double)span)) {
+      bad |= nan_or_inf ? kFlagOverflow : kFlagDomain;
       c.cell[d] = 0;
       c.w[d][0] = one;
-      c.w[d][1] = 0;
-      continue;
-    }
-    if (!(u >= 0.0 && u <= (double)span)) {
-      bad |= kFlagDomain;
-      c.cell[d] = 0;
-      c.w[d][0] = one;
-      c.w[d][1] = 0;
+      for (int t = 1; t < S; ++t) c.w[d][t] = 0;
       continue;
     }
     int64_t U = (int64_t)floor(u);
     if (mm.periodic) U &= span - 1;
-    c.cell[d] = (int)(U >> mm.frac_bits);
-    const uint64_t q = (uint64_t)U & (one - 1);
-    c.w[d][0] = one - q;
-    c.w[d][1] = q;
-    if (!mm.periodic && (c.cell[d] < mm.active.lo[d] || c.cell[d] + 1 > mm.active.hi[d]))
+    if constexpr (S == 2) {
+      c.cell[d] = (int)(U >> mm.frac_bits);
+      const uint64_t q = (uint64_t)U & (one - 1);
+      c.w[d][0] = one - q;
+      c.w[d][1] = q;
+    } else {
+      const int64_t half = (int64_t)one >> 1;
+      const int64_t node = (U + half) >> mm.frac_bits;
+      const int64_t D = U - (node << mm.frac_bits);
+      const uint64_t wm = (uint64_t)((half - D) * (half - D) + (int64_t)one) >> (mm.frac_bits + 1);
+      const uint64_t wp = (uint64_t)((half + D) * (half + D) + (int64_t)one) >> (mm.frac_bits + 1);
+      c.cell[d] = (int)node - 1;
+      c.w[d][0] = wm;
+      c.w[d][1] = one - wm - wp;
+      c.w[d][2] = wp;
+    }
+    if (!mm.periodic && (c.cell[d] < mm.active.lo[d] || c.cell[d] + S - 1 > mm.active.hi[d]))
       bad |= kFlagDomain;
   }
   return bad;
@@ -96,7 +113,7 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-template <typename PT, bool DRIFT, int LDS>
+template <typename PT, bool DRIFT, int LDS, int S>
 __global__ void __launch_bounds__(256)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
@@ -108,7 +125,7 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     blo[tid] = 0x7fffffff;
     bhi[tid] = -0x7fffffff;
   }
-  Cic c[kDepPer];
+  Stencil<S> c[kDepPer];
   bool ok[kDepPer];
   int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
   uint32_t bad_all = 0;
@@ -130,7 +147,7 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
       }
       x[d] = v;
     }
-    const uint32_t bad = cic_setup(x, mm, c[u]);
+    const uint32_t bad = assign_setup<S>(x, mm, c[u]);
     if (bad) {
       bad_all |= bad;
       continue;
@@ -151,8 +168,8 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     }
   }
   __syncthreads();
-  const int lx = bhi[0] - blo[0] + 2, ly = bhi[1] - blo[1] + 2, lz = bhi[2] - blo[2] + 2;
-  if (lx <= 1) return;                                   // no valid particle in the workgroup
+  const int lx = bhi[0] - blo[0] + S, ly = bhi[1] - blo[1] + S, lz = bhi[2] - blo[2] + S;
+  if (lx < S) return;                                    // no valid particle in the workgroup
   const int m = mm.ng - 1;
   const int64_t vol_box = (int64_t)lx * ly * lz;
   if (tid == 0 && vol_box > kDepLds) atomicAdd(flags + 2, 1u);
@@ -165,11 +182,11 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     for (int u = 0; u < kDepPer; ++u) {
       if (!ok[u]) continue;
       const int ax = c[u].cell[0] - blo[0], ay = c[u].cell[1] - blo[1], az = c[u].cell[2] - blo[2];
-      for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy) {
+      for (int dz = 0; dz < S; ++dz)
+        for (int dy = 0; dy < S; ++dy) {
           const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
           if (wyz == 0) continue;
-          for (int dx = 0; dx < 2; ++dx) {
+          for (int dx = 0; dx < S; ++dx) {
             const uint64_t wgt = c[u].w[0][dx] * wyz;
             if (wgt) atomicAdd(&acc[((az + dz) * ly + ay + dy) * lx + ax + dx], (unsigned long long)wgt);
           }
@@ -191,13 +208,13 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
 #pragma unroll
     for (int u = 0; u < kDepPer; ++u) {
       if (!ok[u]) continue;
-      for (int dz = 0; dz < 2; ++dz) {
+      for (int dz = 0; dz < S; ++dz) {
         const int kk = mm.periodic ? ((c[u].cell[2] + dz) & m) : c[u].cell[2] + dz;
-        for (int dy = 0; dy < 2; ++dy) {
+        for (int dy = 0; dy < S; ++dy) {
           const int jj = mm.periodic ? ((c[u].cell[1] + dy) & m) : c[u].cell[1] + dy;
           const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
           if (wyz == 0) continue;
-          for (int dx = 0; dx < 2; ++dx) {
+          for (int dx = 0; dx < S; ++dx) {
             const uint64_t wgt = c[u].w[0][dx] * wyz;
             if (wgt == 0) continue;
             const int ii = mm.periodic ? ((c[u].cell[0] + dx) & m) : c[u].cell[0] + dx;
@@ -209,20 +226,21 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
   }
 }
 
-// g = sum over the 8 CIC cells of w * (-grad Phi) (central differences).
-__device__ inline void interp_g(const double* __restrict__ phi, const MeshMap& mm, const Cic& c,
-                                double inv2h, double g[3]) {
+// g = sum over the S^3 assignment nodes of w * (-grad Phi) (central differences).
+template <int S>
+__device__ inline void interp_g(const double* __restrict__ phi, const MeshMap& mm,
+                                const Stencil<S>& c, double inv2h, double g[3]) {
   const int n = mm.ng, m = n - 1;
   const double norm = ldexp(1.0, -3 * mm.frac_bits);
   g[0] = g[1] = g[2] = 0.0;
-  for (int dz = 0; dz < 2; ++dz) {
+  for (int dz = 0; dz < S; ++dz) {
     const int k = (c.cell[2] + dz) & m;
     const int kp = (k + 1) & m, km = (k - 1) & m;
-    for (int dy = 0; dy < 2; ++dy) {
+    for (int dy = 0; dy < S; ++dy) {
       const int j = (c.cell[1] + dy) & m;
       const int jp = (j + 1) & m, jm = (j - 1) & m;
       const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
-      for (int dx = 0; dx < 2; ++dx) {
+      for (int dx = 0; dx < S; ++dx) {
         const uint64_t wgt = c.w[0][dx] * wyz;
         const int i = (c.cell[0] + dx) & m;
         const double wd = (double)wgt * norm;
@@ -238,22 +256,23 @@ __device__ inline void interp_g(const double* __restrict__ phi, const MeshMap& m
 }
 
 // The same from the FP32 force mesh g3 (3 values per cell): one 12-byte
-// load per CIC cell instead of six FP64 potential values.
-// Both read all 8 cells, zero weights included (a particle that passed
-// cic_setup has them on the written mesh, so a zero weight adds an exact 0):
-// without a branch per cell the loads of all cells are in flight at once,
-// which measured 2.95 -> 2.28 ms for the 512^3 interpolation pass.
-__device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm, const Cic& c,
-                                 double g[3]) {
+// load per node instead of six FP64 potential values.
+// Both read all S^3 nodes, zero weights included (a particle that passed
+// assign_setup has them on the written mesh, so a zero weight adds an exact
+// 0): without a branch per node the loads of all nodes are in flight at
+// once, which measured 2.95 -> 2.28 ms for the 512^3 CIC interpolation pass.
+template <int S>
+__device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm,
+                                 const Stencil<S>& c, double g[3]) {
   const int n = mm.ng, m = n - 1;
   const double norm = ldexp(1.0, -3 * mm.frac_bits);
   g[0] = g[1] = g[2] = 0.0;
-  for (int dz = 0; dz < 2; ++dz) {
+  for (int dz = 0; dz < S; ++dz) {
     const int k = (c.cell[2] + dz) & m;
-    for (int dy = 0; dy < 2; ++dy) {
+    for (int dy = 0; dy < S; ++dy) {
       const int j = (c.cell[1] + dy) & m;
       const uint64_t wyz = c.w[1][dy] * c.w[2][dz];
-      for (int dx = 0; dx < 2; ++dx) {
+      for (int dx = 0; dx < S; ++dx) {
         const uint64_t wgt = c.w[0][dx] * wyz;
         const float* q = g3 + 3 * lin((c.cell[0] + dx) & m, j, k, n);
         const double wd = (double)wgt * norm;
@@ -265,7 +284,7 @@ __device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm
   }
 }
 
-template <typename PT, bool G3>
+template <typename PT, bool G3, int S>
 __global__ void __launch_bounds__(256)
 k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float* __restrict__ g3,
                     MeshMap mm, double inv2h,
@@ -281,16 +300,16 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
     const PT p_old[3] = {__builtin_nontemporal_load((const PT*)pa.p[0] + i),
                          __builtin_nontemporal_load((const PT*)pa.p[1] + i),
                          __builtin_nontemporal_load((const PT*)pa.p[2] + i)};
-    Cic c;
-    const uint32_t bad = cic_setup(x, mm, c);
+    Stencil<S> c;
+    const uint32_t bad = assign_setup<S>(x, mm, c);
     if (bad) {
       atomicOr(flags, bad);
     } else {
       double g[3];
       if (G3)
-        interp_g3(g3, mm, c, g);
+        interp_g3<S>(g3, mm, c, g);
       else
-        interp_g(phi, mm, c, inv2h, g);
+        interp_g<S>(phi, mm, c, inv2h, g);
       for (int d = 0; d < 3; ++d) {
         PT* p = (PT*)pa.p[d];
         const PT pn = (PT)((double)p_old[d] + g[d] * kick_coef);
@@ -381,6 +400,7 @@ k_lc_cross(ParticleArgs pa, double o0, double o1, double o2, double r2, double r
   lc_record<PT>(pa, i, o, r, light, disp, a1, da, out, j);
 }
 
+template <int S>
 __global__ void __launch_bounds__(256)
 k_interp_force(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, double inv2h,
                double* __restrict__ g0, double* __restrict__ g1, double* __restrict__ g2,
@@ -388,14 +408,14 @@ k_interp_force(ParticleArgs pa, const double* __restrict__ phi, MeshMap mm, doub
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pa.n) return;
   const double x[3] = {pa.x[0][i], pa.x[1][i], pa.x[2][i]};
-  Cic c;
-  const uint32_t bad = cic_setup(x, mm, c);
+  Stencil<S> c;
+  const uint32_t bad = assign_setup<S>(x, mm, c);
   if (bad) {
     atomicOr(flags, bad);
     return;
   }
   double g[3];
-  interp_g(phi, mm, c, inv2h, g);
+  interp_g<S>(phi, mm, c, inv2h, g);
   g0[i] = g[0];
   g1[i] = g[1];
   g2[i] = g[2];
@@ -516,12 +536,19 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
   prof_begin(st, K_DEPOSIT);
   const dim3 g(grid_for(pa.n, 256 * kDepPer));
   unsigned long long* cu = (unsigned long long*)counts;
-#define SDPM_DEP(D, L)                                                                          \
-  hipLaunchKernelGGL((k_drift_deposit<PT, D, L>), g, dim3(256), 0, st, pa, drift_coef, mm, cu, flags)
-  if (drift) {
-    if (big_tile) SDPM_DEP(true, kDepLdsBig); else SDPM_DEP(true, kDepLds);
+#define SDPM_DEP(D, L, S)                                                                       \
+  hipLaunchKernelGGL((k_drift_deposit<PT, D, L, S>), g, dim3(256), 0, st, pa, drift_coef, mm, cu, \
+                     flags)
+  if (mm.tsc) {
+    if (drift) {
+      if (big_tile) SDPM_DEP(true, kDepLdsBig, 3); else SDPM_DEP(true, kDepLds, 3);
+    } else {
+      if (big_tile) SDPM_DEP(false, kDepLdsBig, 3); else SDPM_DEP(false, kDepLds, 3);
+    }
+  } else if (drift) {
+    if (big_tile) SDPM_DEP(true, kDepLdsBig, 2); else SDPM_DEP(true, kDepLds, 2);
   } else {
-    if (big_tile) SDPM_DEP(false, kDepLdsBig); else SDPM_DEP(false, kDepLds);
+    if (big_tile) SDPM_DEP(false, kDepLdsBig, 2); else SDPM_DEP(false, kDepLds, 2);
   }
 #undef SDPM_DEP
   const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
@@ -541,14 +568,16 @@ void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const f
                               uint32_t* removed_count, uint32_t* flags, hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st, K_INTERP_KICK_DRIFT);
-  if (g3)
-    hipLaunchKernelGGL((k_interp_kick_drift<PT, true>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st,
-                       pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2],
-                       r2, count_removed, removed_count, flags);
-  else
-    hipLaunchKernelGGL((k_interp_kick_drift<PT, false>), dim3(grid_for(pa.n, 256)), dim3(256), 0,
-                       st, pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1],
-                       x_obs[2], r2, count_removed, removed_count, flags);
+#define SDPM_IKD(G, S)                                                                          \
+  hipLaunchKernelGGL((k_interp_kick_drift<PT, G, S>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st, \
+                     pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2],  \
+                     r2, count_removed, removed_count, flags)
+  if (mm.tsc) {
+    if (g3) SDPM_IKD(true, 3); else SDPM_IKD(false, 3);
+  } else {
+    if (g3) SDPM_IKD(true, 2); else SDPM_IKD(false, 2);
+  }
+#undef SDPM_IKD
   // particles 36 B read and written; the mesh read once (FP32 force or FP64 potential)
   prof_end(st, K_INTERP_KICK_DRIFT,
            (48.0 + 6.0 * sizeof(PT)) * pa.n + (g3 ? 12.0 : 8.0) * box_cells(mm.active));
@@ -567,8 +596,12 @@ void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMa
                          hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st, K_INTERP_FORCE);
-  hipLaunchKernelGGL(k_interp_force, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi, mm,
-                     inv2h, g0, g1, g2, flags);
+  if (mm.tsc)
+    hipLaunchKernelGGL(k_interp_force<3>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi, mm,
+                       inv2h, g0, g1, g2, flags);
+  else
+    hipLaunchKernelGGL(k_interp_force<2>, dim3(grid_for(pa.n, 256)), dim3(256), 0, st, pa, phi, mm,
+                       inv2h, g0, g1, g2, flags);
   prof_end(st, K_INTERP_FORCE, 48.0 * pa.n + 8.0 * box_cells(mm.active));
 }
 

@@ -241,3 +241,53 @@ def test_deposit_exact_when_particles_fill_their_sort_blocks():
         a += da
     log("  three steps of exact counts across both deposit tiles")
     sim.close()
+
+
+@pytest.mark.parametrize("kind,ng,n,prec", [
+    ("uniform", 32, 10000, 0), ("clustered", 32, 20000, 1), ("edge", 16, 8, 0),
+    ("lattice", 32, 32**3, 0), ("clustered", 128, 70001, 0),
+])
+def test_tsc_deposit_bit_exact(kind, ng, n, prec):
+    import paper_1709_04703_amd as P
+    box = 100.0
+    x, p, ids = _particles(kind, ng, box, n)
+    log(f"TSC deposit {kind} ng={ng} n={x.shape[0]} precision={prec}")
+    cfg = lib_config(ng, box, precision=prec, n_initial=x.shape[0], assignment=P.SDPM_ASSIGN_TSC)
+    sim = make_sim(cfg, x.shape[0])
+    sim.bind(x, p, ids)
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(x, ng, box, B, True, "tsc"))
+    sim.close()
+
+
+def test_tsc_deposit_and_interpolation_in_a_dirichlet_box():
+    # the 3^3 support must lie in the active box: the deposit and the force
+    # interpolation on the frozen-exterior box are exact / agree with the
+    # oracle, and a particle one node from the box edge is a domain error
+    import paper_1709_04703_amd as P
+    ng, box, n = 64, 640.0, 4000
+    cfg = lib_config(ng, box, shrink=1, n_initial=n, assignment=P.SDPM_ASSIGN_TSC, precision=1)
+    ocfg = oracle_config(cfg)
+    ocfg.assignment = "tsc"
+    x, p, ids = clustered_particles(n, box, 9, ng=ng, width_cells=1.0, lo=260.0, hi=380.0)
+    rng = np.random.Generator(np.random.PCG64(21))
+    phi = rng.normal(size=(ng, ng, ng))
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids, phi=phi)
+    sim.shrink_radius(150.0)
+    ost = pm.State(x.copy(), p.copy(), ids.copy(), n, np.zeros((ng,) * 3), 0.5)
+    pm.shrink_radius(ost, ocfg, 150.0)
+    k = ost.n_active
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(ost.x[:k], ng, box, B, False, "tsc"))
+    g = sim.interp_force().cpu().numpy().T
+    gx, _, gid = sim.particles()
+    order = np.argsort(gid)
+    oorder = np.argsort(ost.ids[:k])
+    g_ref = pm.interpolate(ost.x[:k], pm.force_mesh(phi, box / ng), ng, box, B, False, "tsc")
+    assert np.abs(g[order] - g_ref[oorder]).max() <= 1e-13 * np.abs(g_ref).max()
+    lo = sim.state()["lo"][0]
+    sim.x[0, 0] = (lo + 0.25) * box / ng          # nearest node lo: node lo - 1 is outside
+    with pytest.raises(P.SdpmError, match="EDOMAIN"):
+        sim.deposit()
+    sim.close()

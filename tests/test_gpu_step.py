@@ -270,3 +270,36 @@ def test_one_step_on_a_wide_frozen_exterior_box():
     assert perr <= 2e-7
     assert phierr <= 1e-7
     sim.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_one_tsc_step_from_identical_state(prec):
+    """One step with TSC assignment (deposit and interpolation) against the
+    oracle's TSC step from the same state."""
+    import paper_1709_04703_amd as P
+    import torch
+    ng, box, a0, da = 32, 100.0, 0.02, 0.049
+    x, p, ids = zeldovich_ics(ng, box, a0, 1709, "powerlaw-2")
+    cfg = lib_config(ng, box, precision=prec, c_grav=-1.0, tol=1e-10, n_initial=ng**3,
+                     assignment=P.SDPM_ASSIGN_TSC)
+    ocfg = oracle_config(cfg)
+    ocfg.assignment = "tsc"
+    sim = make_sim(cfg, ng**3)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    assert rel_rms(sim.phi_numpy(), ost.phi) <= 1e-7
+    sim.phi.copy_(torch.as_tensor(ost.phi))
+    ost.p = (p.astype(np.float32).astype(np.float64) if prec == 0 else p).copy()
+    st = sim.step(a0, da)
+    diag = {}
+    ost = pm.step(ost, ocfg, da, diag)
+    assert np.array_equal(sim.counts_numpy(), diag["counts"])
+    gx, gp, gid = sim.particles()
+    dx = periodic_delta(_by_id(gx, gid), _by_id(ost.x, ost.ids), box)
+    perr = rel_rms(_by_id(gp, gid), _by_id(ost.p, ost.ids))
+    log(f"  TSC step precision={prec}: max|dx|={np.abs(dx).max():.2e} p err={perr:.2e}")
+    assert np.abs(dx).max() <= 1e-9 * box
+    assert perr <= (1e-7 if prec == 0 else 1e-8)
+    assert rel_rms(sim.phi_numpy(), ost.phi) <= 1e-7
+    sim.close()

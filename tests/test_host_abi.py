@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol(P):
 
 
 def test_struct_sizes_match_header_layout(P):
-    assert ctypes.sizeof(P.Config) == 144   # ..., sort_every, sort_shift, solver, cycles_per_outer
+    assert ctypes.sizeof(P.Config) == 152   # ..., solver, cycles_per_outer, assignment (+4 padding)
     assert ctypes.sizeof(P.StepStats) == 8 * 2 + 4 * 4 + 8 * 4 + 8 * 5 + 4 * 7 + 4 * 8 + 4 + 16
 
 
@@ -90,11 +90,13 @@ def test_solver_config_validation(P):
                 dict(c_grav=-1.0, solver=P.SDPM_SOLVER_ADE, warm_start=P.SDPM_WS_EXTRAP),
                 dict(c_grav=-1.0, solver=3),
                 dict(solver=P.SDPM_SOLVER_FFT, warm_start=P.SDPM_WS_EXTRAP),
-                dict(cycles_per_outer=0), dict(cycles_per_outer=5)):
+                dict(cycles_per_outer=0), dict(cycles_per_outer=5), dict(assignment=2)):
         with pytest.raises(P.SdpmError, match="EINVAL"):
             P.workspace_bytes(P.config_default(64, 100.0, **bad), 10)
     assert P.config_default(64, 100.0).solver == P.SDPM_SOLVER_IMPLICIT
     assert P.config_default(64, 100.0).cycles_per_outer == 4
+    assert P.config_default(64, 100.0).assignment == P.SDPM_ASSIGN_CIC
+    assert P.workspace_bytes(P.config_default(64, 100.0, assignment=P.SDPM_ASSIGN_TSC), 10) > 0
     for cpo in (1, 4):
         assert P.workspace_bytes(P.config_default(64, 100.0, cycles_per_outer=cpo), 10) > 0
     # the FFT solver's half spectrum and work area come from the workspace
