@@ -23,7 +23,9 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
            steps are compared with those of the implicit modes (ade_vs_implicit);
   fft:     the implicit step solved exactly by FP64 FFT while the mesh is
            periodic (the standard particle-mesh solver), FP32 momenta; compared
-           with the implicit modes like ade (fft_vs_implicit).
+           with the implicit modes like ade (fft_vs_implicit);
+  tsc:     extrap with TSC instead of CIC assignment (27 nodes per particle
+           both ways).
 The net is trained once before the timed regions, on the GPU, on solves
 recorded (with the extrapolated start) from 128^3 runs of the same schedule
 with other seeds.
@@ -157,7 +159,7 @@ def train_net(P, torch, args):
 
 
 def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, extrap=False,
-             solver=0, keep=False):
+             solver=0, keep=False, assignment=0):
     x, p, ids = ics
     ng, box = args.ng, args.box
     n = x.shape[0]
@@ -166,7 +168,7 @@ def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, 
                            warm_start=(P.SDPM_WS_PREV if weights is None else
                                        P.SDPM_WS_LEARNED_GATED if gated else P.SDPM_WS_LEARNED)
                            | (P.SDPM_WS_EXTRAP if extrap else 0), solver=solver,
-                           cycles_per_outer=args.cycles_per_outer)
+                           cycles_per_outer=args.cycles_per_outer, assignment=assignment)
     sim = P.Simulation(cfg, n)
     if weights is not None:
         sim.set_warmstart_weights(weights)
@@ -505,7 +507,7 @@ def main():
     ap.add_argument("--z-init", type=float, default=49.0)
     ap.add_argument("--schedule", type=int, default=200)
     ap.add_argument("--seed", type=int, default=512)
-    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade,fft")
+    ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade,fft,tsc")
     ap.add_argument("--train-ng", type=int, default=128)
     ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
     ap.add_argument("--train-pairs", type=int, default=400)
@@ -570,12 +572,13 @@ def main():
                      extrap=mode not in ("plain", "mixed", "ade", "fft"),
                      solver={"ade": P.SDPM_SOLVER_ADE, "fft": P.SDPM_SOLVER_FFT}.get(
                          mode, P.SDPM_SOLVER_IMPLICIT),
-                     keep=mode in ("ade", "fft", "extrap", "mixed"))
+                     keep=mode in ("ade", "fft", "extrap", "mixed"),
+                     assignment=P.SDPM_ASSIGN_TSC if mode == "tsc" else P.SDPM_ASSIGN_CIC)
         log(f"{mode}: {r['steps'] if 'steps' in r else args.steps} steps in {r['seconds']:.3f} s, "
             f"iters {r['iters']}")
         results[mode] = r
     head_mode = next(m for m in ("learned", "mixed", "extrap", "plain", "learned_always", "ade",
-                                 "fft") if m in results)
+                                 "fft", "tsc") if m in results)
     cmp = {}
     ref_mode = next((m for m in ("extrap", "mixed") if m in results), None)
     for other in ("ade", "fft"):
@@ -653,7 +656,8 @@ def main():
                   "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
                   "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
                   "extrap": "f32 V-cycles in f64 defect correction",
-                  "ade": "f64 ADE sweeps", "fft": "f64 FFT solves"}[head_mode],
+                  "ade": "f64 ADE sweeps", "fft": "f64 FFT solves",
+                  "tsc": "f32 V-cycles in f64 defect correction"}[head_mode],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
