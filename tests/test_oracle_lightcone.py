@@ -55,3 +55,44 @@ def test_no_light_travel_records_the_removal_instant():
     x1 = XO + np.array([[90.0, 0.0, 0.0]])
     u, a, xc, _ = pm.lightcone_crossing(x1, np.ones((1, 3)), XO, 75.0, 0.0, 0.0, 0.6, 0.0)
     assert u[0] == 0.0 and a[0] == 0.6 and np.array_equal(xc, x1)
+
+
+def test_fixed_domain_crossing_step_of_radial_motion():
+    # Fixed domain (nothing removed): a particle moving radially at constant
+    # comoving speed v, d(tau) = d0 + v (tau - tau0), meets the shrinking
+    # lightcone r(tau) = c (tau(1) - tau) at tau* = (c tau(1) - d0 + v tau0) / (c + v).
+    # In Einstein-de Sitter (H0 = 1) tau = 2 sqrt(a), so r(a) = 2 c (1 - sqrt(a)).
+    # lightcone_crossed must flag each particle in exactly the step that
+    # contains tau*, and in no other.
+    c = 2997.92458
+    a_edges = np.linspace(0.5, 1.0, 41)
+    tau = 2.0 * np.sqrt(a_edges)
+    tau0, tau1 = tau[0], 2.0
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 400
+    direc = rng.normal(size=(n, 3))
+    direc /= np.linalg.norm(direc, axis=1)[:, None]
+    v = rng.uniform(-0.3, 0.3, size=n) * c          # inward and outward
+    r0 = c * (tau1 - tau0)
+    # inward movers must not reach the observer before a = 1
+    lower = np.maximum(0.02 * r0, -v * (tau1 - tau0) + 1.0)
+    d0 = lower + rng.uniform(0.0, 1.0, size=n) * (0.98 * r0 - lower)
+    t_star = (c * tau1 - d0 + v * tau0) / (c + v)
+    expect = np.searchsorted(tau, t_star, side="left") - 1   # tau_j < tau* <= tau_{j+1}
+    assert np.all((expect >= 0) & (expect < len(tau) - 1))
+    # keep clear of step edges by far more than rounding
+    gap = np.min(np.abs(t_star[:, None] - tau[None, :]), axis=1)
+    keep = gap > 1e-9
+    hits = np.zeros(n, dtype=np.int64)
+    first = np.full(n, -1)
+    for j in range(len(tau) - 1):
+        xs = XO + direc * (d0 + v * (tau[j] - tau0))[:, None]
+        xe = XO + direc * (d0 + v * (tau[j + 1] - tau0))[:, None]
+        rs = 2.0 * c * (1.0 - np.sqrt(a_edges[j]))
+        re = 2.0 * c * (1.0 - np.sqrt(a_edges[j + 1]))
+        got = pm.lightcone_crossed(xs, xe, XO, rs, re)
+        hits += got
+        first = np.where(got & (first < 0), j, first)
+    assert np.count_nonzero(keep) > 0.99 * n
+    assert np.all(hits[keep] == 1)
+    assert np.array_equal(first[keep], expect[keep])
