@@ -27,8 +27,11 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
   tsc:     extrap with TSC instead of CIC assignment (27 nodes per particle
            both ways).
 The net is trained once before the timed regions, on the GPU, on solves
-recorded (with the extrapolated start) from 128^3 runs of the same schedule
-with other seeds.
+recorded (with the extrapolated start) from the periodic phase of 128^3 runs
+(2000 Mpc/h, z = 49 -> 0 in 100 steps, seeds 10001-10010: every solve, up to
+2000), and applied both at 512^3 (the learned modes above) and at 256^3
+(learned_transfer: seeds 20001-20003, steps 5-24 of the 100-step schedule,
+the extrapolated start with and without the learned guess).
 The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
@@ -82,6 +85,11 @@ MEASURED_TRAFFIC = {"smooth_color": 813715135}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
+# forward flops per voxel of the warm-start net: the method's channels
+# (2 x 27 x (3 x 16 + 3 x 16 x 16 + 16 x 1)) and what the kernels compute with
+# every layer padded to 16 x 16 channels (5 x 2 x 27 x 16 x 16)
+NET_METHOD_FLOPS_PER_VOXEL = 2 * 27 * (3 * 16 + 3 * 16 * 16 + 16)
+NET_KERNEL_FLOPS_PER_VOXEL = 5 * 2 * 27 * 16 * 16
 
 
 def kernel_roofline(name, d):
@@ -126,8 +134,10 @@ def roofline_of(prof, prof_full=None, full_steps=0):
 
 
 def train_net(P, torch, args):
-    """Record solves from args.train_ng^3 runs (periodic phase) and train the
-    warm-start net on them; returns (weights, info)."""
+    """Record solves from args.train_ng^3 runs (periodic phase of the
+    args.train_schedule-step schedule, every solve of it, up to
+    args.train_pairs) and train the warm-start net on them; returns
+    (weights, info)."""
     from paper_1709_04703_amd.train import Trainer, init_params, record_pairs
     from synth import zeldovich_ics
 
@@ -135,10 +145,8 @@ def train_net(P, torch, args):
     a0 = 1.0 / (1.0 + args.z_init)
     seeds = [int(s) for s in args.train_seeds.split(",")]
     ics = [zeldovich_ics(args.train_ng, args.box, a0, s) for s in seeds]
-    per_run = max(1, args.train_pairs // (2 * len(seeds)))
-    buf, kap, rms_r, rms_phi = record_pairs(ics, args.train_ng, args.box, a0, args.schedule,
-                                            args.train_pairs, steps_per_run=per_run,
-                                            warm_start=P.SDPM_WS_EXTRAP)
+    buf, kap, rms_r, rms_phi = record_pairs(ics, args.train_ng, args.box, a0, args.train_schedule,
+                                            args.train_pairs, warm_start=P.SDPM_WS_EXTRAP)
     del ics
     t1 = time.perf_counter()
     tr = Trainer(args.train_ng, init_params(0), lr=args.train_lr)
@@ -150,12 +158,75 @@ def train_net(P, torch, args):
     w = tr.weights()
     del buf, tr
     torch.cuda.empty_cache()
-    info = {"train_mesh": args.train_ng, "seeds": seeds, "pairs": int(len(kap)),
-            "iterations": args.train_iters, "record_s": round(t1 - t0, 2),
-            "train_s": round(t2 - t1, 2), "loss": [(i, round(v, 5)) for i, v in hist],
-            "rel_err_dphi": round(err, 4)}
+    info = {"train_mesh": args.train_ng, "seeds": seeds, "schedule": args.train_schedule,
+            "pairs": int(len(kap)), "iterations": args.train_iters,
+            "record_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+            "loss": [(i, round(v, 5)) for i, v in hist], "rel_err_dphi": round(err, 4)}
     log(f"net: {info}")
     return w, info
+
+
+def learned_transfer(P, torch, args, weights):
+    """The trained net applied at args.apply_ng^3 (seeds args.apply_seeds, the
+    same box and schedule as the training runs): per seed, args.apply_warmup
+    untimed then args.apply_steps timed steps with the extrapolated start
+    alone, with the gated learned guess added, and with the learned guess
+    before every solve; mixed precision, every solve to 1e-8."""
+    from synth import zeldovich_ics
+
+    ng = args.apply_ng
+    a0 = 1.0 / (1.0 + args.z_init)
+    edges = np.linspace(a0, 1.0, args.train_schedule + 1)
+    rows = {m: [] for m in ("extrap", "learned", "learned_always")}
+    for seed in (int(v) for v in args.apply_seeds.split(",")):
+        x, p, ids = zeldovich_ics(ng, args.box, a0, seed)
+        n = x.shape[0]
+        for mode in rows:
+            ws = P.SDPM_WS_EXTRAP | {"extrap": P.SDPM_WS_PREV, "learned": P.SDPM_WS_LEARNED_GATED,
+                                     "learned_always": P.SDPM_WS_LEARNED}[mode]
+            cfg = P.config_default(ng, args.box, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED,
+                                   n_initial=n, sort_every=args.sort_every,
+                                   sort_shift=args.sort_shift, warm_start=ws,
+                                   cycles_per_outer=args.cycles_per_outer)
+            sim = P.Simulation(cfg, n)
+            if mode != "extrap":
+                sim.set_warmstart_weights(weights)
+            sim.bind(x, p, ids)
+            sim.init_potential(a0)
+            for s_ in range(args.apply_warmup):
+                sim.step(edges[s_], edges[s_ + 1] - edges[s_])
+            sim.profile(True, kernels=["conv3d_mfma"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vc, used = 0, 0
+            for s_ in range(args.apply_warmup, args.apply_warmup + args.apply_steps):
+                st = sim.step(edges[s_], edges[s_ + 1] - edges[s_])
+                vc += st["vcycles"]
+                used += st["warm_used"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            prof = sim.profile_read().get("conv3d_mfma", {"launches": 0, "ms": 0.0})
+            rows[mode].append({"seed": seed, "ms_per_step": 1e3 * dt / args.apply_steps,
+                               "vcycles_per_solve": vc / (2.0 * args.apply_steps),
+                               "net_calls": prof["launches"] // 5, "guesses_accepted": used,
+                               "net_ms_per_call": (prof["ms"] / max(1, prof["launches"] // 5))})
+            sim.close()
+            del sim
+        del x, p, ids
+    torch.cuda.empty_cache()
+    mean = {m: {k: float(np.mean([r[k] for r in v])) for k in v[0] if k != "seed"}
+            for m, v in rows.items()}
+    out = {"mesh": ng, "seeds": args.apply_seeds, "steps": (f"{args.apply_warmup}.."
+                                                             f"{args.apply_warmup + args.apply_steps - 1}"
+                                                             f" of {args.train_schedule}"),
+           "per_seed": rows, "mean": mean,
+           "learned_speedup_vs_extrap": mean["extrap"]["ms_per_step"] / mean["learned"]["ms_per_step"],
+           "learned_always_speedup_vs_extrap": (mean["extrap"]["ms_per_step"]
+                                                / mean["learned_always"]["ms_per_step"]),
+           "vcycles_saved_per_solve_always": (mean["extrap"]["vcycles_per_solve"]
+                                              - mean["learned_always"]["vcycles_per_solve"])}
+    log(f"learned transfer {ng}^3: {json.dumps(out['mean'])}")
+    return out
 
 
 def run_mode(P, torch, ics, args, precision, profile, weights=None, gated=True, extrap=False,
@@ -509,10 +580,17 @@ def main():
     ap.add_argument("--seed", type=int, default=512)
     ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade,fft,tsc")
     ap.add_argument("--train-ng", type=int, default=128)
-    ap.add_argument("--train-seeds", default="10001,10002,10003,10004")
-    ap.add_argument("--train-pairs", type=int, default=400)
-    ap.add_argument("--train-iters", type=int, default=2000)
+    ap.add_argument("--train-seeds", default=",".join(str(10001 + i) for i in range(10)))
+    ap.add_argument("--train-schedule", type=int, default=100,
+                    help="steps of the training runs' schedule (z_init -> 0)")
+    ap.add_argument("--train-pairs", type=int, default=2000)
+    ap.add_argument("--train-iters", type=int, default=6000)
     ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--apply-ng", type=int, default=256)
+    ap.add_argument("--apply-seeds", default="20001,20002,20003")
+    ap.add_argument("--apply-warmup", type=int, default=5)
+    ap.add_argument("--apply-steps", type=int, default=20)
+    ap.add_argument("--no-learned-transfer", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps after the timed ones with every kernel profiled")
     ap.add_argument("--cycles-per-outer", type=int, default=4, choices=(1, 2, 3, 4),
@@ -629,7 +707,17 @@ def main():
         lp = results[lmode]["prof"]
         if lp.get("conv3d_mfma", {}).get("launches"):
             learned_roofline = kernel_roofline("conv3d_mfma", lp["conv3d_mfma"])
+            # the library charges each layer its padded 16 x 16 channel work; the
+            # method's own work is 3 -> 16, 16 -> 16 (three layers), 16 -> 1
+            scale = NET_METHOD_FLOPS_PER_VOXEL / NET_KERNEL_FLOPS_PER_VOXEL
+            learned_roofline["achieved"] *= scale
+            learned_roofline["frac"] *= scale
+            learned_roofline["flops_per_voxel"] = NET_METHOD_FLOPS_PER_VOXEL
+            learned_roofline["kernel_flops_per_voxel"] = NET_KERNEL_FLOPS_PER_VOXEL
             learned_roofline["mode"] = lmode
+    transfer = None
+    if net_info is not None and not args.no_learned_transfer:
+        transfer = learned_transfer(P, torch, args, net_weights)
     copy_gbs = copy_bandwidth(torch)
     shrink = None
     if not args.no_shrink_phase and args.shrink_from + args.shrink_steps <= args.schedule:
@@ -641,6 +729,29 @@ def main():
         t = time.perf_counter()
         cpu = cpu_baseline(ics, args)
         log(f"cpu baseline in {time.perf_counter() - t:.1f} s")
+    head_net_calls = modes[head_mode]["net_calls"]
+    dtype = {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
+             "learned": "f32 V-cycles in f64 defect correction",
+             "learned_always": "f32 V-cycles in f64 defect correction",
+             "extrap": "f32 V-cycles in f64 defect correction",
+             "ade": "f64 ADE sweeps", "fft": "f64 FFT solves",
+             "tsc": "f32 V-cycles in f64 defect correction"}[head_mode]
+    if head_mode.startswith("learned") and head_net_calls > 0:
+        dtype += ", bf16 MFMA net"
+    warm = {"plain": "previous potential", "mixed": "previous potential",
+            "extrap": "previous potential + extrapolated change",
+            "tsc": "previous potential + extrapolated change",
+            "learned": ("previous potential + extrapolated change + learned guess, gated "
+                        f"({head_net_calls} net calls in the timed steps)"),
+            "learned_always": ("previous potential + extrapolated change + learned guess "
+                               f"before every solve ({head_net_calls} net calls)"),
+            "ade": "none (explicit sweeps)", "fft": "none (exact solve)"}[head_mode]
+    learned_gain = {}
+    if "extrap" in modes:
+        for m in ("learned", "learned_always"):
+            if m in modes:
+                learned_gain[m] = (modes[m]["particle_updates_per_s"]
+                                   / modes["extrap"]["particle_updates_per_s"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -652,12 +763,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"plain": "f64", "mixed": "f32 V-cycles in f64 defect correction",
-                  "learned": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
-                  "learned_always": "f32 V-cycles in f64 defect correction, bf16 MFMA net",
-                  "extrap": "f32 V-cycles in f64 defect correction",
-                  "ade": "f64 ADE sweeps", "fft": "f64 FFT solves",
-                  "tsc": "f32 V-cycles in f64 defect correction"}[head_mode],
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
             "workload": (f"{args.ng}^3 particles, {args.ng}^3 mesh, {args.box:g} Mpc/h, "
@@ -667,8 +773,14 @@ def main():
                          "cycles per FP64 defect correction) to 1e-8"),
             "global_batch": int(ics[0].shape[0]),
             "parallelism": "single GPU",
+            "mode": head_mode,
+            "warm_start": warm,
+            "net_calls_in_timed_steps": head_net_calls,
         },
         "headline_mode": head_mode,
+        # the learned guess's own share: gated / ungated learned over the same
+        # mixed-precision solve with the extrapolated start and no net
+        "learned_gain_vs_extrap": learned_gain,
         "vcycles_per_s": modes[head_mode]["vcycles_per_s"],
         "modes": modes,
         "roofline": roofline,
@@ -680,6 +792,7 @@ def main():
         "table4": t4,
         "roofline_learned": learned_roofline,
         "net": net_info,
+        "learned_transfer": transfer,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -22,7 +22,11 @@
  * Conventions for every call:
  *  - Return value: SDPM_OK (0) or a negative SDPM_E* code.  No call throws or
  *    aborts across the ABI.  sdpm_last_error() describes the last failure on
- *    a context.  An error leaves the context usable and its state consistent.
+ *    a context.  An error other than SDPM_EHIP leaves the context usable and
+ *    its state consistent (what a failing call has completed is stated with
+ *    the call).  SDPM_EHIP reports a failed HIP runtime call: the device
+ *    state is then undefined (a step may have been applied in part) and the
+ *    context should be destroyed.
  *  - Device buffers (particles, fields, workspace) are caller-owned device
  *    memory that the context borrows; they must outlive the context.
  *  - All device work is enqueued on the stream given to sdpm_create.  Calls
@@ -111,7 +115,9 @@ typedef struct sdpm_config {
                             Eq. 12, h in Mpc/h); > 0: this speed              */
   double x_obs[3];       /* observer position [Mpc/h]                          */
   int32_t shrink;        /* 0: fixed periodic domain; 1: shrinking domain      */
-  int32_t margin;        /* cells added around the lightcone sphere (>= 2)     */
+  int32_t margin;        /* cells added around the lightcone sphere (>= 2;
+                            TSC assignment adds one more, see
+                            sdpm_domain_box)                                   */
   int32_t box_align;     /* power of two A: the planes next to the active box
                             sit at multiples of A (A = 2^(mg_levels-1) nests
                             every multigrid level exactly)                     */
@@ -131,8 +137,9 @@ typedef struct sdpm_config {
   int64_t n_initial;     /* particles at the start: mean density n0 / ng^3     */
   int32_t sort_every;    /* Morton re-sort before every k-th step (0: never)   */
   int32_t sort_shift;    /* sort key: Morton order of cell blocks of 2^shift
-                            cells per axis (stable: particles keep their
-                            order inside a block); default 4 for ng >= 64    */
+                            cells per axis, then the cell row (z, then y)
+                            inside the block (stable: particles keep their
+                            order inside a row); default 4 for ng >= 64      */
   int32_t solver;        /* SDPM_SOLVER_IMPLICIT (default), _ADE or _FFT        */
   int32_t cycles_per_outer; /* V-cycles per defect-correction iteration, at most
                             (1..4, default 4): further cycles on the same
@@ -158,9 +165,15 @@ typedef struct sdpm_particles {
   int64_t capacity;
 } sdpm_particles;
 
-/* Caller-owned device mesh arrays, ng^3 each.  phi: potential (in/out);
- * rhs: right-hand side of the last solve (out); counts: fixed-point CIC mass
- * of the last deposit, sum over a particle's cells = 2^(3B) (out).          */
+/* Caller-owned device mesh arrays, ng^3 each.  phi: potential (in/out): a
+ * step reads it as Phi_old (the previous potential of Eq. 4's implicit
+ * step and the solve's initial guess) and overwrites it in place with
+ * Phi(t + dt/2), then Phi(t + dt); rhs: right-hand side of the last solve
+ * (out); counts: fixed-point CIC mass of the last deposit, sum over a
+ * particle's cells = 2^(3B) (out).  The force -grad Phi has no caller
+ * array: in mixed precision the step writes it to an FP32 mesh in the
+ * workspace (3 values per cell), in plain FP64 the interpolation
+ * differences phi at each node.                                             */
 typedef struct sdpm_fields {
   double* phi;
   double* rhs;
@@ -194,8 +207,9 @@ int sdpm_step_scalars(const sdpm_config* cfg, double a, double da, double out[7]
 int sdpm_lightcone_radius(const sdpm_config* cfg, double a, double* r);
 
 /* Active index box for lightcone radius r (host only), Sec. 2.4: cells
- * within r + margin cells of the observer per axis,
- *   lo0 = floor((x_o - r)/h) - margin,  hi0 = floor((x_o + r)/h) + margin,
+ * within r + m cells of the observer per axis, m = margin (CIC) or
+ * margin + 1 (TSC, whose support reaches one node further),
+ *   lo0 = floor((x_o - r)/h) - m,  hi0 = floor((x_o + r)/h) + m,
  * rounded outward so that lo - 1 and hi + 1 are multiples of box_align.  periodic
  * = 1 (and the box is the whole mesh) while that box does not fit in
  * [1, ng - 2]; lo/hi are inclusive, axis order x, y, z.                     */
@@ -230,8 +244,14 @@ int sdpm_init_potential(sdpm_ctx* ctx, double a, sdpm_step_stats* out);
  * CIC deposit, solve to a_half, FD force, CIC interpolation, kick with
  * a_half (Eq. 8), drift dtau/2 with a + da (Eq. 9), second field half
  * sub-step (skipped for static gravity), lightcone and elimination at
- * a + da.  out may be NULL.  Returns SDPM_EDOMAIN / SDPM_ENOCONV on those
- * failures (the step's data is then complete but flagged).                 */
+ * a + da.  out may be NULL.  Errors: SDPM_EINVAL / SDPM_ESTATE before any
+ * device work (nothing changed); SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW
+ * and SDPM_EFULL after the whole step has been applied (positions, momenta,
+ * potential and time advanced; ENOCONV keeps the best iterate of the solve
+ * that missed tol; with EDOMAIN / EOVERFLOW the offending particles took
+ * the first drift only, without deposit, kick or second drift, and the
+ * lightcone is not applied in that step: no particle removed, the domain
+ * not shrunk); SDPM_EHIP as above.                                         */
 int sdpm_step(sdpm_ctx* ctx, double a, double da, sdpm_step_stats* out);
 
 /* "Shrink domain": lightcone at a; stable-partitions the active particles
@@ -282,11 +302,30 @@ int sdpm_lightcone_count(sdpm_ctx* ctx, int64_t* count);
 int sdpm_get_state(sdpm_ctx* ctx, sdpm_step_stats* out);
 
 /* Sub-steps for kernel-level checks --------------------------------------- */
-/* CIC deposit of the active particles at their current positions into
- * fields->counts (zeroed first over the active box).                        */
+/* Mass assignment of Sec. 2.4 (CIC, or TSC when sdpm_config.assignment
+ * selects it; the same weights as the interpolation): the active particles
+ * at their current positions (no drift) into fields->counts, which is
+ * zeroed first over the active box (the whole mesh while periodic).  Fixed
+ * point: U = floor(x ng 2^B / box) per axis, CIC axis weights (2^B - q, q)
+ * of the cells U >> B and (U >> B) + 1, q = U mod 2^B; the weight products
+ * (<= 2^(3B)) are summed exactly in uint64, so every particle adds 2^(3B).
+ * Errors: SDPM_ESTATE before sdpm_bind; SDPM_EDOMAIN when a particle's
+ * support leaves the active box, SDPM_EOVERFLOW for a non-finite
+ * coordinate (those particles are skipped, the others deposited).          */
 int sdpm_deposit(sdpm_ctx* ctx);
-/* rhs = h^2 S (counts / (n0/ng^3 2^3B) - 1) [- mean, periodic] - kappa h^2 phi,
- * then solve (Lap_h - kappa h^2) phi = rhs on the active box, phi as guess. */
+/* Source and mesh solve of one implicit half sub-step of Eq. 4 (Sec. 2.1;
+ * kappa = 0 is Poisson's equation, Eq. 3), from the last deposit:
+ *   rhs = h^2 S (counts / (n0/ng^3 2^3B) - 1) [- its mean while periodic]
+ *         - kappa h^2 phi,
+ * then (Lap_h - kappa h^2) phi = rhs on the active box (7-point Laplacian
+ * in grid units, frozen exterior values once the box is smaller than the
+ * mesh, zero mean for periodic kappa = 0) by the configured solver, phi
+ * (fields->phi, in/out) as the initial guess, to the relative residual
+ * sdpm_config.tol.  kappa_h2 = kappa h^2 >= 0; s_h2_factor = S (the factor
+ * 3 Omega_m / (2 a) of Eq. 3; h^2 is applied inside).  fields->rhs receives
+ * the right-hand side.  Errors: SDPM_EINVAL for kappa_h2 < 0 or a non-finite
+ * argument; SDPM_ENOCONV when max_outer corrections do not reach tol (phi
+ * holds the last iterate, out->res its residual).                           */
 int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_stats* out);
 /* One ADE sweep (Sec. 2.3) of fields->phi in place over the active box with
  * fields->rhs as the source f = S h^2 delta (the caller's values; sdpm_step
@@ -299,12 +338,19 @@ int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_sta
  * launch per diagonal of rows (ny + nz - 1 launches).  SDPM_EINVAL for lam
  * not finite and positive.                                                  */
 int sdpm_ade_sweep(sdpm_ctx* ctx, double lam, int forward);
-/* Morton re-sort of the active particles (all SoA arrays permuted together
- * by the Morton code of their cell, stable LSD radix sort).  Results of the
- * step do not depend on particle order; the sort improves locality.       */
+/* Re-sort of the active particles (all SoA arrays permuted together by the
+ * key of sort_shift: the Morton code of the cell's block, then its row
+ * inside the block; stable LSD radix sort).  Results of the step do not
+ * depend on particle order (only the order of removed particles and of
+ * lightcone records follows it); the sort improves locality.              */
 int sdpm_sort(sdpm_ctx* ctx);
-/* g = -grad Phi (central differences) interpolated to the active particles
- * with the deposit's CIC weights; g_dev[3]: device FP64 arrays (n_active). */
+/* Force interpolation of Sec. 2.4 with the deposit's own weights (the same
+ * scheme both ways, which conserves momentum): g = -grad Phi by central
+ * differences of fields->phi, (Phi_{i+1} - Phi_{i-1}) / (2h) per axis, at
+ * each assignment node, weighted and summed per active particle (FP64).
+ * g_dev[3]: caller-owned device FP64 arrays of n_active entries (x, y, z
+ * components), written in the particles' current order.  Errors: as
+ * sdpm_deposit (an offending particle's entries are left unwritten).       */
 int sdpm_interp_force(sdpm_ctx* ctx, double* g_dev[3]);
 
 /* Power spectrum ------------------------------------------------------------

@@ -409,7 +409,9 @@ def shrink_radius(state: State, cfg: Config, r: float) -> np.ndarray:
             removed = state.ids[keep.size:n].copy()
             state.n_active = keep.size
         h = cfg.box / cfg.ng
-        dirichlet, lo, hi = box_for_radius(r, x_obs, h, cfg.ng, cfg.margin, cfg.align)
+        # TSC reaches one node further than CIC: one more cell of margin
+        margin = cfg.margin + (1 if cfg.assignment == "tsc" else 0)
+        dirichlet, lo, hi = box_for_radius(r, x_obs, h, cfg.ng, margin, cfg.align)
         if dirichlet:
             if not state.periodic:
                 lo = np.maximum(lo, state.lo)

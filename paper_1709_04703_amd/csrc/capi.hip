@@ -55,10 +55,6 @@ struct sdpm_ctx {
   bool ex_have[2] = {false, false};
   double ex_dtau[2] = {0.0, 0.0};
   double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
-  // deposit: LDS tile size (see launch_drift_deposit) and the workgroups of
-  // the last deposit
-  bool dep_big_tile = false;
-  int64_t dep_workgroups = 0;
   // residual reduction per V-cycle of the last solve (geometric mean), used
   // to run ahead of the host without a sync per iteration and to pair cycles
   double rho_est = 0.1;
@@ -279,15 +275,18 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   return off;
 }
 
-// Active box for radius r (host; Sec. 2.4 index box, outward rounding).
+// Active box for radius r (host; Sec. 2.4 index box, outward rounding).  TSC
+// reaches one node further than CIC on each side, so its box takes one more
+// cell of margin and keeps the same drift slack between shrinks.
 void domain_box(const sdpm_config& c, double r, Box* b, int* periodic) {
   const double h = c.box / c.ng;
   const int64_t A = c.box_align;
+  const int m = c.margin + (c.assignment == SDPM_ASSIGN_TSC ? 1 : 0);
   bool fits = true;
   Box out;
   for (int d = 0; d < 3; ++d) {
-    int64_t lo = (int64_t)std::floor((c.x_obs[d] - r) / h) - c.margin;
-    int64_t hi = (int64_t)std::floor((c.x_obs[d] + r) / h) + c.margin;
+    int64_t lo = (int64_t)std::floor((c.x_obs[d] - r) / h) - m;
+    int64_t hi = (int64_t)std::floor((c.x_obs[d] + r) / h) + m;
     // planes lo-1 and hi+1 on multiples of A (floor / ceil division)
     const int64_t lm = lo - 1, hp = hi + 1;
     const int64_t lf = (lm >= 0 ? lm / A : -((-lm + A - 1) / A)) * A;
@@ -382,6 +381,7 @@ MeshMap mesh_map(sdpm_ctx* c) {
   mm.scale = (double)((int64_t)c->cfg.ng << c->cfg.frac_bits) / c->cfg.box;
   mm.active = c->periodic ? full_box(c->cfg.ng) : c->box;
   mm.tsc = c->cfg.assignment == SDPM_ASSIGN_TSC ? 1 : 0;
+  mm.block_shift = c->cfg.sort_shift;
   return mm;
 }
 
@@ -424,7 +424,8 @@ int flags_error(sdpm_ctx* c) {
   if (f & kFlagOverflow)
     return fail(c, SDPM_EOVERFLOW, "a particle coordinate is not finite");
   if (f & kFlagDomain)
-    return fail(c, SDPM_EDOMAIN, "a particle's CIC cells leave the active box or the mesh");
+    return fail(c, SDPM_EDOMAIN, "a particle's assignment support (the %s nodes) leaves the active box or the mesh",
+                c->cfg.assignment == SDPM_ASSIGN_TSC ? "3^3 TSC" : "2^3 CIC");
   return SDPM_OK;
 }
 
@@ -443,7 +444,18 @@ bool extrap_active(const sdpm_ctx* c, int slot) {
 // solve of kind `slot` (-1: none) extrapolates, the same pass applies the
 // extrapolated start after reading phi_old for the rhs and starts the running
 // change ex_d[slot] that the solve's later updates of phi add to.
-void assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot) {
+//
+// With multigrid (mg) and a box wide enough for its vector tiles, the same
+// pass also forms the solve's first FP64 residual into level 0's r and its
+// norm into dscal[1] (res_ready), and an extrapolated start is left pending
+// (pending_scale != 0): phi and the running change are updated by the
+// solve's first correction or by launch_apply_start instead, since the
+// fused pass reads the neighbours of the cells it would write.
+struct RhsOut {
+  bool res_ready = false;
+  double pending_scale = 0.0;
+};
+RhsOut assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot, bool mg = false) {
   const sdpm_config& g = c->cfg;
   const double h = g.box / g.ng;
   const double nbar = (double)g.n_initial / ((double)g.ng * g.ng * g.ng);
@@ -452,11 +464,32 @@ void assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot) {
   const double c_off = s_source * h * h * ratio;
   const bool extrap = extrap_active(c, slot);
   const bool apply = extrap && c->ex_have[slot] && c->ex_dtau[slot] > 0.0;
+  const double chg_scale = apply ? c->cur_dtau / c->ex_dtau[slot] : 0.0;
+  float* chg = extrap ? c->ex_d[slot] : nullptr;
   int nb = 0;
+  RhsOut out;
+  if (mg) {
+    const bool fused =
+        g.precision == SDPM_MIXED
+            ? launch_rhs_residual<float>(c->fields.counts, c->fields.phi, c->fields.rhs,
+                                         (float*)c->lv[0].r, chg, apply, chg_scale, g.ng,
+                                         c->lv[0].box, c_scale, c_off, kappa, c->partial, &nb,
+                                         c->st)
+            : launch_rhs_residual<double>(c->fields.counts, c->fields.phi, c->fields.rhs,
+                                          (double*)c->lv[0].r, chg, apply, chg_scale, g.ng,
+                                          c->lv[0].box, c_scale, c_off, kappa, c->partial, &nb,
+                                          c->st);
+    if (fused) {
+      launch_reduce_final(c->partial, nb, 2, c->dscal, c->st);
+      out.res_ready = true;
+      out.pending_scale = apply ? chg_scale : 0.0;
+      return out;
+    }
+  }
   launch_rhs(c->fields.counts, c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c_scale, c_off,
-             kappa, extrap ? c->ex_d[slot] : nullptr, apply ? c->cur_dtau / c->ex_dtau[slot] : 0.0,
-             apply, c->partial, &nb, c->st);
+             kappa, chg, chg_scale, apply, c->partial, &nb, c->st);
   launch_reduce_final(c->partial, nb, 1, c->dscal, c->st);
+  return out;
 }
 
 struct SolveOut {
@@ -465,19 +498,28 @@ struct SolveOut {
 };
 
 // FP64 defect correction around V-cycles in T; rhs and ||rhs||^2 (dscal[0])
-// must be in place.  phi is the initial guess and the result.
+// must be in place, and with rh.res_ready the first residual and its norm
+// (dscal[1]) too.  phi is the initial guess and the result.
 template <typename T>
-int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
+int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
   const sdpm_config& g = c->cfg;
   const Box& b = c->lv[0].box;
   int nb = 0;
-  // extrapolated start: applied by assemble_rhs; every later update of phi
-  // in this solve is added to the running change chg as well
+  // extrapolated start: applied by assemble_rhs, or pending until the first
+  // correction (rh.pending_scale); every later update of phi in this solve
+  // is added to the running change chg as well
   const bool extrap = extrap_active(c, slot);
   float* chg = extrap ? c->ex_d[slot] : nullptr;
-  launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial, &nb,
-                     c->st);
-  launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+  double pending = chg ? rh.pending_scale : 0.0;
+  auto flush_pending = [&]() {
+    if (pending != 0.0) launch_apply_start(c->fields.phi, chg, pending, g.ng, b, c->st);
+    pending = 0.0;
+  };
+  if (!rh.res_ready) {
+    launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
+                       &nb, c->st);
+    launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
+  }
   int rc = sync_scalars(c, 2);
   if (rc) return rc;
   const double bn = std::sqrt(c->hpin[0]);
@@ -497,6 +539,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     try_net = false;
   }
   if (try_net || recording) {
+    flush_pending();
     launch_sum_sq(c->fields.phi, g.ng, full_box(g.ng), c->partial, &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 3, c->st);
     rc = sync_scalars(c, 4);
@@ -592,7 +635,8 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     for (int q = 0; q < ncyc; ++q)
       e0 = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
                      q > 0, c->st);
-    launch_correct<T>(c->fields.phi, e0, chg, g.ng, b, c->st);
+    launch_correct<T>(c->fields.phi, e0, chg, pending, g.ng, b, c->st);
+    pending = 0.0;
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
     launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
                        &nb, c->st);
@@ -618,6 +662,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
     it_known = it;
     cyc_known = cyc;
   }
+  flush_pending();      // a start already within tol: no correction took it
   if (cyc > 0 && rn > 0.0 && rn_start > 0.0 && std::isfinite(rn)) {
     const double rho = std::pow(rn / rn_start, 1.0 / cyc);
     if (rho > 0.0 && rho < 1.0) c->rho_est = std::min(std::max(rho, 1e-3), 0.9);
@@ -669,15 +714,21 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
   return SDPM_OK;
 }
 
-int solve(sdpm_ctx* c, double kappa, int slot, SolveOut* so) {
+// Whether the next solve is multigrid (not the FFT of the periodic phase,
+// not the ADE sweeps).
+bool mg_solve(const sdpm_ctx* c) {
+  return c->cfg.solver == SDPM_SOLVER_IMPLICIT || (c->cfg.solver == SDPM_SOLVER_FFT && !c->periodic);
+}
+
+int solve(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh = RhsOut{}) {
   if (c->cfg.solver == SDPM_SOLVER_FFT && c->periodic) {
     // exact: no iterations, residual at rounding level (reported as 0)
     *so = SolveOut{};
     const int rc = fft_solve(c->fft, c->fields.rhs, c->fields.phi, kappa, c->st);
     return rc ? fail(c, rc, "hipFFT execution failed") : SDPM_OK;
   }
-  return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, slot, so)
-                                        : solve_impl<double>(c, kappa, slot, so);
+  return c->cfg.precision == SDPM_MIXED ? solve_impl<float>(c, kappa, slot, so, rh)
+                                        : solve_impl<double>(c, kappa, slot, so, rh);
 }
 
 int deposit(sdpm_ctx* c, double drift_coef, int drift) {
@@ -686,12 +737,9 @@ int deposit(sdpm_ctx* c, double drift_coef, int drift) {
   const ParticleArgs pa = particle_args(c);
   const MeshMap mm = mesh_map(c);
   if (c->cfg.precision == SDPM_MIXED)
-    launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags,
-                                c->dep_big_tile, c->st);
+    launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
   else
-    launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags,
-                                 c->dep_big_tile, c->st);
-  c->dep_workgroups = deposit_workgroups(pa.n);
+    launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
   return SDPM_OK;
 }
 
@@ -998,9 +1046,9 @@ int sdpm_init_potential(sdpm_ctx* c, double a, sdpm_step_stats* out) {
   HIP_TRY(c, hipMemsetAsync(c->dflags, 0, 16 * sizeof(uint32_t), c->st));
   launch_fill<uint64_t>(c->fields.counts, c->cfg.ng, full_box(c->cfg.ng), 0ull, c->st);
   deposit(c, 0.0, 0);
-  assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0, 0);
+  const RhsOut rh = assemble_rhs(c, 1.5 * c->cfg.omega_m / a, 0.0, 0, mg_solve(c));
   SolveOut so;
-  const int src = solve(c, 0.0, 0, &so);
+  const int src = solve(c, 0.0, 0, &so, rh);
   rc = flags_error(c);
   st.n_removed = removed;
   st.outer_iters[0] = so.iters;
@@ -1047,7 +1095,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   // Phi from t to t + dt/2                              (row 3)
   const bool ade = g.solver == SDPM_SOLVER_ADE;
   const StepDtau step_dtau(c, sc.dtau);
-  assemble_rhs(c, sc.s_half, ade ? 0.0 : sc.kappa1_h2, 0);
+  const RhsOut rh1 = assemble_rhs(c, sc.s_half, ade ? 0.0 : sc.kappa1_h2, 0, !ade && mg_solve(c));
   HIP_TRY(c, hipEventRecord(c->ev[2], c->st));
   SolveOut s1;
   int src1 = SDPM_OK;
@@ -1056,7 +1104,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
                      1.0 / sc.kappa1_h2, true, c->st);
   } else {
-    src1 = solve(c, sc.kappa1_h2, 0, &s1);
+    src1 = solve(c, sc.kappa1_h2, 0, &s1, rh1);
     if (src1 && src1 != SDPM_ENOCONV) return src1;
   }
   HIP_TRY(c, hipEventRecord(c->ev[3], c->st));
@@ -1088,8 +1136,8 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
                      1.0 / sc.kappa2_h2, false, c->st);
   } else if (sc.kappa2_h2 > 0.0) {
-    assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1);
-    src2 = solve(c, sc.kappa2_h2, 1, &s2);
+    const RhsOut rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, mg_solve(c));
+    src2 = solve(c, sc.kappa2_h2, 1, &s2, rh2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], c->st));
@@ -1118,9 +1166,6 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   c->lc_prev_r = sc.r_lc_end;
   rc = sync_scalars(c, 1);
   if (rc) return rc;
-  // the deposit tile for the next step: the larger one once more than a
-  // quarter of this step's deposit workgroups overflowed the smaller
-  c->dep_big_tile = 4 * (int64_t)((const uint32_t*)(c->hpin + 16))[2] > c->dep_workgroups;
   int lc_full = SDPM_OK;
   if (lc_fixed) {
     const int64_t crossed = (int64_t)((const unsigned long long*)(c->hpin + kHostLcCount))[0];
@@ -1249,9 +1294,9 @@ int sdpm_solve(sdpm_ctx* c, double kappa_h2, double s_source, sdpm_step_stats* o
   if (rc) return rc;
   if (!(kappa_h2 >= 0.0) || !std::isfinite(s_source))
     return fail(c, SDPM_EINVAL, "kappa_h2 must be >= 0 and s finite");
-  assemble_rhs(c, s_source, kappa_h2, 0);
+  const RhsOut rh = assemble_rhs(c, s_source, kappa_h2, 0, mg_solve(c));
   SolveOut so;
-  rc = solve(c, kappa_h2, 0, &so);
+  rc = solve(c, kappa_h2, 0, &so, rh);
   if (out) {
     std::memset(out, 0, sizeof(*out));
     out->outer_iters[0] = so.iters;

@@ -113,8 +113,25 @@ template <typename T>
 void launch_residual(const double* phi, const double* rhs, T* r_out, int n, const Box& b,
                      double kappa, double* partial, int* nblocks, hipStream_t st);
 // phi += e (colour-split e); chg += e as well when chg is given.
+// pending_scale != 0: a pending start d = (float)(pending_scale chg) is
+// added first, phi = (phi + d) + e, chg = d + e.
 template <typename T>
-void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st);
+void launch_correct(double* phi, const T* e, float* chg, double pending_scale, int n,
+                    const Box& b, hipStream_t st);
+// A pending start over the box: d = (float)(chg_scale chg), phi += d, chg = d.
+void launch_apply_start(double* phi, float* chg, double chg_scale, int n, const Box& b,
+                        hipStream_t st);
+// The rhs pass fused with the first FP64 residual of a multigrid solve:
+// rhs and r (colour-split T) with phi0 = phi + (float)(chg_scale chg) when
+// apply (the start is then pending: phi and chg unchanged), else phi0 = phi
+// and chg (when given) cleared; partial[0 .. nb) = rhs^2, partial[nb ..
+// 2 nb) = r^2 sums.  Returns false without launching when the box is
+// narrower than the vector tiles.
+template <typename T>
+bool launch_rhs_residual(const uint64_t* counts, const double* phi, double* rhs, T* r_out,
+                         float* chg, bool apply, double chg_scale, int n, const Box& b,
+                         double c_scale, double c_off, double kappa, double* partial,
+                         int* nblocks, hipStream_t st);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st);
@@ -168,16 +185,13 @@ struct MeshMap {
   double scale;       // s = ng 2^B / L
   Box active;         // deposit / interpolation cells must lie inside
   int tsc;            // 0: CIC, 1: TSC assignment
+  int block_shift;    // the re-sort's blocks: 2^block_shift cells per axis
 };
-// Drift (when drift != 0) and fixed-point CIC deposit into counts.  flags[0]
-// collects error bits; flags[2] counts the workgroups whose particles span
-// more cells than the small LDS tile; big_tile takes the larger tile.
+// Drift (when drift != 0) and fixed-point CIC / TSC deposit into counts.
+// flags[0] collects error bits.
 template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
-                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, bool big_tile,
-                          hipStream_t st);
-// Workgroups of a deposit of n particles.
-int64_t deposit_workgroups(int64_t n);
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, hipStream_t st);
 // g3 (FP32, 3 per cell in natural order) = -grad Phi by central differences
 // on the cells of box b (mesh.hip).
 void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double inv2h,

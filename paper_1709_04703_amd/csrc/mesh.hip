@@ -282,10 +282,165 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
 }
 
-// phi += e; with CHG the same increment is added to the running change.
-template <typename T, bool CHG>
+// Source assembly fused with the first FP64 residual of a multigrid solve,
+// on the tiles of k_residual_v4:
+//   rhs = c_scale C - c_off - kappa phi_old                (the rhs pass)
+//   r   = rhs - (Lap_h phi0 - kappa phi0),  phi0 = phi_old + d,
+// d = (float)(chg_scale chg) the extrapolated start from the previous
+// solve's change in chg (MODE 2; MODE 1: d = 0 and the running change chg
+// cleared; MODE 0: no running change), evaluated on the fly for each cell
+// and its six neighbours.  With a start, neither phi nor chg is written here
+// (a neighbour's thread may still read them): the solve's first correction,
+// or k_apply_start, adds d to phi and makes it the start of the running
+// change.  partial[block] = sum of rhs^2,
+// partial[nblocks + block] = sum of r^2.  One pass instead of the rhs pass
+// and the residual pass: phi and rhs are not read a second time (and with
+// the start, phi is not written here).
+template <typename T, int TXV, int MODE>
 __global__ void __launch_bounds__(256)
-k_correct(double* __restrict__ phi, const T* __restrict__ e, float* __restrict__ chg, int n, Box b) {
+k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
+                  double* __restrict__ rhs, T* __restrict__ rout, float* __restrict__ chg, int n,
+                  Box b, double c_scale, double c_off, double kappa, double chg_scale,
+                  int nblocks, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  constexpr int TY = 256 / TXV;
+  const int ib = b.lo[0] & ~3;
+  const Tile tl = tile_of((b.hi[0] - ib + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int i0 = ib + (tl.bx * TXV + threadIdx.x) * 4;
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
+  const int m = n - 1;
+  double acc_r = 0.0, acc_b = 0.0;
+  // phi0 at four cells from phi_old there (and d, when MODE 2)
+  auto start4 = [&](int64_t c, Vec4<double>& raw, Vec4<float>& d) {
+    raw = *(const Vec4<double>*)(phi + c);
+    if (MODE == 2) {
+      const Vec4<float> prev = *(const Vec4<float>*)(chg + c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d.v[q] = (float)(chg_scale * (double)prev.v[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d.v[q] = 0.f;
+    }
+  };
+  auto start1 = [&](int64_t c) -> double {
+    const double v = phi[c];
+    return MODE == 2 ? v + (double)(float)(chg_scale * (double)chg[c]) : v;
+  };
+  if (i0 <= b.hi[0] && j <= b.hi[1]) {
+    const int k0 = b.lo[2] + tl.bz * kResKz;
+    const int k1 = min(k0 + kResKz - 1, b.hi[2]);
+    const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
+    const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
+    const int hn = n >> 1;
+    const int64_t hc = half_cells(n);
+    Vec4<double> raw, below, ctr, ctr_raw;
+    Vec4<float> d, ctr_d;
+    start4(lin(i0, j, (k0 - 1) & m, n), raw, d);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) below.v[q] = raw.v[q] + (double)d.v[q];
+    start4(lin(i0, j, k0, n), ctr_raw, ctr_d);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ctr.v[q] = ctr_raw.v[q] + (double)ctr_d.v[q];
+    for (int k = k0; k <= k1; ++k) {
+      Vec4<double> above_raw, ym, yp, above;
+      Vec4<float> above_d;
+      start4(lin(i0, j, (k + 1) & m, n), above_raw, above_d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) above.v[q] = above_raw.v[q] + (double)above_d.v[q];
+      start4(lin(i0, jm, k, n), raw, d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ym.v[q] = raw.v[q] + (double)d.v[q];
+      start4(lin(i0, jp, k, n), raw, d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yp.v[q] = raw.v[q] + (double)d.v[q];
+      const double xl = start1(lin(il, j, k, n)), xr = start1(lin(ir, j, k, n));
+      const int64_t c = lin(i0, j, k, n);
+      Vec4<uint64_t> cnt;
+      {
+        const Vec2<uint64_t> lo2 = *(const Vec2<uint64_t>*)(counts + c);
+        const Vec2<uint64_t> hi2 = *(const Vec2<uint64_t>*)(counts + c + 2);
+        cnt.v[0] = lo2.v[0], cnt.v[1] = lo2.v[1], cnt.v[2] = hi2.v[0], cnt.v[3] = hi2.v[1];
+      }
+      double rv[4], res[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        rv[q] = (double)cnt.v[q] * c_scale - c_off - kappa * ctr_raw.v[q];
+        const double left = q == 0 ? xl : ctr.v[q - 1];
+        const double right = q == 3 ? xr : ctr.v[q + 1];
+        const double nb = left + right + ym.v[q] + yp.v[q] + above.v[q] + below.v[q];
+        res[q] = rv[q] - (nb - 6.0 * ctr.v[q] - kappa * ctr.v[q]);
+      }
+      const int c0 = (i0 + j + k) & 1;
+      const int64_t row = ((int64_t)k * n + j) * hn + (i0 >> 1);
+      if (full) {
+        Vec4<double> rr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rr.v[q] = rv[q];
+        st_stream4(rhs + c, rr);
+        if (MODE == 1) st_stream4(chg + c, ctr_d);
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 ta, tb;
+        ta.x = (T)res[0], ta.y = (T)res[2], tb.x = (T)res[1], tb.y = (T)res[3];
+        __builtin_nontemporal_store(ta, (v2*)(rout + (int64_t)c0 * hc + row));
+        __builtin_nontemporal_store(tb, (v2*)(rout + (int64_t)(c0 ^ 1) * hc + row));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc_r += res[q] * res[q];
+          acc_b += rv[q] * rv[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + q;
+          if (i < b.lo[0] || i > b.hi[0]) continue;
+          rhs[c + q] = rv[q];
+          if (MODE == 1) chg[c + q] = 0.f;
+          rout[(int64_t)((c0 + q) & 1) * hc + row + (q >> 1)] = (T)res[q];
+          acc_r += res[q] * res[q];
+          acc_b += rv[q] * rv[q];
+        }
+      }
+      below = ctr;
+      ctr = above;
+      ctr_raw = above_raw;
+      ctr_d = above_d;
+    }
+  }
+  const double sb = block_sum<256>(acc_b, sh);
+  const double sr = block_sum<256>(acc_r, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    partial[block_linear()] = sb;
+    partial[nblocks + block_linear()] = sr;
+  }
+}
+
+// A pending extrapolated start: d = (float)(chg_scale chg), phi += d, and d
+// becomes the running change.
+__global__ void __launch_bounds__(256)
+k_apply_start(double* __restrict__ phi, float* __restrict__ chg, int n, Box b, double chg_scale) {
+  const Tile tl = tile_box(b);
+  const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
+  const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
+  if (i > b.hi[0] || j > b.hi[1]) return;
+  const int k0 = b.lo[2] + tl.bz * kBoxKz;
+  const int k1 = min(k0 + kBoxKz - 1, b.hi[2]);
+  for (int k = k0; k <= k1; ++k) {
+    const int64_t c = lin(i, j, k, n);
+    const float d = (float)(chg_scale * (double)ld_stream(chg + c));
+    phi[c] += (double)d;
+    st_stream(chg + c, d);
+  }
+}
+
+// phi += e; with CHG the same increment is added to the running change.
+// PENDING: the extrapolated start d = (float)(chg_scale chg) of the fused
+// rhs pass (k_rhs_residual_v4) is not yet in phi nor in chg (which still
+// holds the previous solve's change): phi = (phi + d) + e, chg = d + e, the
+// roundings of adding d in a separate pass and then e.
+template <typename T, bool CHG, bool PENDING>
+__global__ void __launch_bounds__(256)
+k_correct(double* __restrict__ phi, const T* __restrict__ e, float* __restrict__ chg, int n, Box b,
+          double chg_scale) {
   const Tile tl = tile_box(b);
   const int i = b.lo[0] + tl.bx * kBoxTx + threadIdx.x;
   const int j = b.lo[1] + tl.by * kBoxTy + threadIdx.y;
@@ -295,8 +450,18 @@ k_correct(double* __restrict__ phi, const T* __restrict__ e, float* __restrict__
   for (int k = k0; k <= k1; ++k) {
     const int64_t c = lin(i, j, k, n);
     const T ev = ld_stream(e + sidx(i, j, k, n));
-    phi[c] += (double)ev;
-    if (CHG) st_stream(chg + c, ld_stream(chg + c) + (float)ev);
+    if (CHG) {
+      float cv = ld_stream(chg + c);
+      if (PENDING) {
+        cv = (float)(chg_scale * (double)cv);
+        phi[c] = (phi[c] + (double)cv) + (double)ev;
+      } else {
+        phi[c] += (double)ev;
+      }
+      st_stream(chg + c, cv + (float)ev);
+    } else {
+      phi[c] += (double)ev;
+    }
   }
 }
 
@@ -1163,18 +1328,78 @@ void launch_force_mesh(const double* phi, float* g3, int n, const Box& b, double
 }
 
 template <typename T>
-void launch_correct(double* phi, const T* e, float* chg, int n, const Box& b, hipStream_t st) {
+void launch_correct(double* phi, const T* e, float* chg, double pending_scale, int n,
+                    const Box& b, hipStream_t st) {
   prof_begin(st, K_CORRECT);
-  if (chg)
-    hipLaunchKernelGGL((k_correct<T, true>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e, chg,
-                       n, b);
+  if (chg && pending_scale != 0.0)
+    hipLaunchKernelGGL((k_correct<T, true, true>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e,
+                       chg, n, b, pending_scale);
+  else if (chg)
+    hipLaunchKernelGGL((k_correct<T, true, false>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi,
+                       e, chg, n, b, 0.0);
   else
-    hipLaunchKernelGGL((k_correct<T, false>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, e,
-                       nullptr, n, b);
+    hipLaunchKernelGGL((k_correct<T, false, false>), box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi,
+                       e, nullptr, n, b, 0.0);
   prof_end(st, K_CORRECT, (16.0 + sizeof(T) + (chg ? 8.0 : 0.0)) * box_cells(b));
 }
-template void launch_correct<float>(double*, const float*, float*, int, const Box&, hipStream_t);
-template void launch_correct<double>(double*, const double*, float*, int, const Box&, hipStream_t);
+template void launch_correct<float>(double*, const float*, float*, double, int, const Box&,
+                                    hipStream_t);
+template void launch_correct<double>(double*, const double*, float*, double, int, const Box&,
+                                     hipStream_t);
+
+void launch_apply_start(double* phi, float* chg, double chg_scale, int n, const Box& b,
+                        hipStream_t st) {
+  prof_begin(st, K_CORRECT);
+  hipLaunchKernelGGL(k_apply_start, box_grid(b), dim3(kBoxTx, kBoxTy), 0, st, phi, chg, n, b,
+                     chg_scale);
+  prof_end(st, K_CORRECT, 24.0 * box_cells(b));
+}
+
+// The rhs pass and the first residual of a multigrid solve in one pass (see
+// k_rhs_residual_v4) when the box is wide enough for its 4-cell vectors;
+// returns false (nothing launched) otherwise.  chg == nullptr: no running
+// change; apply: the start d = chg_scale chg is pending afterwards.
+template <typename T>
+bool launch_rhs_residual(const uint64_t* counts, const double* phi, double* rhs, T* r_out,
+                         float* chg, bool apply, double chg_scale, int n, const Box& b,
+                         double c_scale, double c_off, double kappa, double* partial,
+                         int* nblocks, hipStream_t st) {
+  const int ib = b.lo[0] & ~3;
+  if (b.hi[0] - ib + 1 < 64) return false;
+  const int txv = tile_threads(b.hi[0] - ib + 1);
+  const unsigned gx = (unsigned)((b.hi[0] - ib + 4 * txv) / (4 * txv));
+  const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + 256 / txv) / (256 / txv));
+  const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kResKz) / kResKz);
+  const int nb = (int)(gx * gy * gz);
+  *nblocks = nb;
+  const dim3 g(gx * gy * gz), blk(txv, 256 / txv);
+  const int mode = chg ? (apply ? 2 : 1) : 0;
+  prof_begin(st, K_RHS);
+#define SDPM_RR(TX, M)                                                                           \
+  hipLaunchKernelGGL((k_rhs_residual_v4<T, TX, M>), g, blk, 0, st, counts, phi, rhs, r_out, chg, \
+                     n, b, c_scale, c_off, kappa, chg_scale, nb, partial)
+#define SDPM_RR_TX(M)                                                                            \
+  if (txv == 64) SDPM_RR(64, M); else if (txv == 32) SDPM_RR(32, M); else SDPM_RR(16, M)
+  if (mode == 2) {
+    SDPM_RR_TX(2);
+  } else if (mode == 1) {
+    SDPM_RR_TX(1);
+  } else {
+    SDPM_RR_TX(0);
+  }
+#undef SDPM_RR_TX
+#undef SDPM_RR
+  // counts, phi and rhs 8 B each, r sizeof(T); the running change 4 B
+  // (read with a start to apply, cleared without)
+  prof_end(st, K_RHS, (24.0 + sizeof(T) + (mode ? 4.0 : 0.0)) * box_cells(b));
+  return true;
+}
+template bool launch_rhs_residual<float>(const uint64_t*, const double*, double*, float*, float*,
+                                         bool, double, int, const Box&, double, double, double,
+                                         double*, int*, hipStream_t);
+template bool launch_rhs_residual<double>(const uint64_t*, const double*, double*, double*, float*,
+                                          bool, double, int, const Box&, double, double, double,
+                                          double*, int*, hipStream_t);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st) {
@@ -1390,16 +1615,24 @@ static void prolong_level(const Level& L, const Level& C, bool all_cells, hipStr
                      (T*)L.e, C.n, L.n, L.box, all_cells ? 1 : 0);
 }
 
-// Red-black sweeps that reduce the slowest mode of level l's operator by
-// 1e-3: Jacobi factor rho = 6 cos(theta) / (6 + 4^l kappa h^2), red-black GS
-// rho^2, theta = 2 pi / n (periodic) or pi / (extent + 1) (Dirichlet); a
-// large number when rho >= 1.
+// Red-black sweeps that reduce the slowest mode of level l's operator
+// A = Lap_h - 4^l kappa h^2 by 1e-3, red-black Gauss-Seidel taken as the
+// square of the Jacobi factor rho = (sum over axes of 2 cos theta_d) /
+// (6 + 4^l kappa h^2) of that mode: on a Dirichlet box the lowest sine mode,
+// theta_d = pi / (extent_d + 1); on the periodic mesh with kappa > 0 the
+// constant mode (theta = 0, rho = 6 / (6 + 4^l kappa h^2)); periodic with
+// kappa = 0, where the constant mode is projected out, the lowest nonzero
+// mode along one axis, rho = (4 + 2 cos(2 pi / n)) / 6.  A large number
+// when rho >= 1.
 static int sweeps_for_1e3(const Level& L, int l, double kappa, bool periodic) {
-  const int nx = L.box.hi[0] - L.box.lo[0] + 1, ny = L.box.hi[1] - L.box.lo[1] + 1,
-            nz = L.box.hi[2] - L.box.lo[2] + 1;
-  const int ext = std::max(nx, std::max(ny, nz));
-  const double th = periodic ? 2.0 * M_PI / L.n : M_PI / (ext + 1);
-  const double rho = 6.0 * std::cos(th) / (6.0 + std::ldexp(1.0, 2 * l) * kappa);
+  double num;
+  if (periodic) {
+    num = kappa > 0.0 ? 6.0 : 4.0 + 2.0 * std::cos(2.0 * M_PI / L.n);
+  } else {
+    num = 0.0;
+    for (int d = 0; d < 3; ++d) num += 2.0 * std::cos(M_PI / (L.box.hi[d] - L.box.lo[d] + 2));
+  }
+  const double rho = num / (6.0 + std::ldexp(1.0, 2 * l) * kappa);
   if (!(rho > 0.0 && rho < 1.0)) return rho <= 0.0 ? 1 : 1 << 20;
   return std::max(1, (int)std::ceil(std::log(1e-3) / (2.0 * std::log(rho))));
 }

@@ -21,19 +21,44 @@ namespace {
 
 // The S x S x S mesh nodes a particle is assigned to (S = 2: CIC, S = 3:
 // TSC): the first node per axis (unwrapped: it may be -1 or reach ng on a
-// periodic mesh, where the users wrap it with & (ng - 1)) and the weights.
+// periodic mesh, where the users wrap it with & (ng - 1)) and, per axis, the
+// fixed-point offset the weights follow from: q = U mod 2^B for CIC, D = U -
+// i 2^B (i the nearest node) for TSC.
+struct Frac {
+  int cell[3];
+  int f[3];
+};
 template <int S>
 struct Stencil {
   int cell[3];
   uint64_t w[3][S];
 };
 
-// Fixed-point coordinates and weights of one particle.  Returns 0 or a
-// kFlag* bit (then the stencil is a harmless one-node placeholder).
+// Axis weights in units of 2^-B from the offset f: CIC (2^B - q, q); TSC the
+// nodes i - 1, i, i + 1: (2^(B-1) -+ D)^2 / 2^(B+1) rounded to the nearest
+// integer for the outer two, 2^B minus both for the middle (sum exactly 2^B).
 template <int S>
-__device__ inline uint32_t assign_setup(const double x[3], const MeshMap& mm, Stencil<S>& c) {
+__device__ inline void axis_weights(int f, int frac_bits, uint64_t w[S]) {
+  const uint64_t one = 1ull << frac_bits;
+  if constexpr (S == 2) {
+    w[0] = one - (uint64_t)f;
+    w[1] = (uint64_t)f;
+  } else {
+    const int64_t half = (int64_t)one >> 1, D = f;
+    const uint64_t wm = (uint64_t)((half - D) * (half - D) + (int64_t)one) >> (frac_bits + 1);
+    const uint64_t wp = (uint64_t)((half + D) * (half + D) + (int64_t)one) >> (frac_bits + 1);
+    w[0] = wm;
+    w[1] = one - wm - wp;
+    w[2] = wp;
+  }
+}
+
+// Fixed-point coordinates of one particle.  Returns 0 or a kFlag* bit (then
+// cell and offset are placeholders that no caller uses).
+template <int S>
+__device__ inline uint32_t assign_frac(const double x[3], const MeshMap& mm, Frac& c) {
   const int64_t span = (int64_t)mm.ng << mm.frac_bits;
-  const uint64_t one = 1ull << mm.frac_bits;
+  const int64_t one = 1ll << mm.frac_bits;
   uint32_t bad = 0;
   for (int d = 0; d < 3; ++d) {
     const double u = x[d] * mm.scale;
@@ -41,30 +66,39 @@ __device__ inline uint32_t assign_setup(const double x[3], const MeshMap& mm, St
     if (nan_or_inf || !(u >= 0.0 && u <= (double)span)) {
       bad |= nan_or_inf ? kFlagOverflow : kFlagDomain;
       c.cell[d] = 0;
-      c.w[d][0] = one;
-      for (int t = 1; t < S; ++t) c.w[d][t] = 0;
+      c.f[d] = 0;
       continue;
     }
     int64_t U = (int64_t)floor(u);
     if (mm.periodic) U &= span - 1;
     if constexpr (S == 2) {
       c.cell[d] = (int)(U >> mm.frac_bits);
-      const uint64_t q = (uint64_t)U & (one - 1);
-      c.w[d][0] = one - q;
-      c.w[d][1] = q;
+      c.f[d] = (int)(U & (one - 1));
     } else {
-      const int64_t half = (int64_t)one >> 1;
-      const int64_t node = (U + half) >> mm.frac_bits;
-      const int64_t D = U - (node << mm.frac_bits);
-      const uint64_t wm = (uint64_t)((half - D) * (half - D) + (int64_t)one) >> (mm.frac_bits + 1);
-      const uint64_t wp = (uint64_t)((half + D) * (half + D) + (int64_t)one) >> (mm.frac_bits + 1);
+      const int64_t node = (U + (one >> 1)) >> mm.frac_bits;
       c.cell[d] = (int)node - 1;
-      c.w[d][0] = wm;
-      c.w[d][1] = one - wm - wp;
-      c.w[d][2] = wp;
+      c.f[d] = (int)(U - (node << mm.frac_bits));
     }
     if (!mm.periodic && (c.cell[d] < mm.active.lo[d] || c.cell[d] + S - 1 > mm.active.hi[d]))
       bad |= kFlagDomain;
+  }
+  return bad;
+}
+
+// The cell a particle lies in along axis d, floor(x_d / h).
+template <int S>
+__device__ inline int home_cell(const Frac& c, int d) {
+  return S == 2 ? c.cell[d] : c.cell[d] + (c.f[d] < 0 ? 0 : 1);
+}
+
+// The same with the weights expanded.
+template <int S>
+__device__ inline uint32_t assign_setup(const double x[3], const MeshMap& mm, Stencil<S>& c) {
+  Frac fr;
+  const uint32_t bad = assign_frac<S>(x, mm, fr);
+  for (int d = 0; d < 3; ++d) {
+    c.cell[d] = fr.cell[d];
+    axis_weights<S>(fr.f[d], mm.frac_bits, c.w[d]);
   }
   return bad;
 }
@@ -91,47 +125,115 @@ __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0,
   return (a + b) + c;
 }
 
-// Drift + deposit, 1024 particles per workgroup.  When the CIC cells of the
-// workgroup's particles fit a box of at most LDS cells the weights are summed
-// with 64-bit LDS atomics and each touched cell is flushed with one global
-// atomic; otherwise every corner goes straight to global atomics.  Integer
-// sums: the result is the same either way and in any order.  Two tile sizes:
-// kDepLds cells (32 KB) fit the particles of a workgroup while they stay near
-// their lattice order inside a sort block; once they have moved about a
-// whole 16^3-cell block apart its 17^3-cell box needs kDepLdsBig (48 KB,
-// fewer workgroups per CU).  Workgroups whose box exceeds kDepLds are counted
-// in flags[2] so that the caller can choose the tile for the next deposit.
-constexpr int kDepPer = 4;
-constexpr int kDepLds = 4096, kDepLdsBig = 6144;
+// Drift + deposit, kDepThreads x kDepPer particles per workgroup, with the
+// weights summed in LDS windows (at most kDepTile cells together) and each
+// nonzero window cell added to the mesh with one global 64-bit atomic.
+// Every particle is routed on its own: one whose S^3 support lies inside its
+// window goes to LDS, any other (an outlier) straight to global atomics, so
+// a few stray particles never push a whole workgroup onto global atomics.
+// Cells are taken relative to a reference cell (thread 0's first valid
+// particle; on a periodic mesh offsets wrap into [-ng/2, ng/2)).  One window
+// is the workgroup's bounding box when that fits the tile.  Otherwise the
+// particles split in two groups, those in the reference particle's re-sort
+// block and the rest (a workgroup of sorted particles straddles at most two
+// blocks, which need not be neighbours in every axis), each with its own
+// window: its bounding box if both fit, else boxes of a share of the tile
+// centred on the group's mean offset, the axes with the smallest extent
+// kept whole first.  Integer sums: the result is exact and the same in any
+// order and for any routing.
+constexpr int kDepThreads = 512, kDepPer = 2;
+constexpr int kDepTile = 4096;       // 32 KB
 
 __device__ inline int wave_min(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_down(v, off, 64));
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
   return v;
 }
 __device__ inline int wave_max(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_down(v, off, 64));
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline int wave_sum(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-template <typename PT, bool DRIFT, int LDS, int S>
-__global__ void __launch_bounds__(256)
+// Window of at most cap cells for the cnt particles with offsets in [mn, mx]
+// (sums sm and sums of squares sq per axis), support S: the bounding box
+// when it fits; else per axis the extent of a uniform spread of the same
+// variance (sqrt(12 var) + S, which a few far particles hardly change),
+// reduced to fit cap (the axes with the smallest extent kept whole first),
+// centred on the mean.  Returns its volume.
+template <int S>
+__device__ inline int dep_window(const int mn[3], const int mx[3], const int sm[3],
+                                 const unsigned long long sq[3], int cnt, int cap, int lo[3],
+                                 int w[3]) {
+  int ext[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = mx[d] - mn[d] + S;
+    lo[d] = mn[d];
+    w[d] = ext[d];
+  }
+  if ((int64_t)ext[0] * ext[1] * ext[2] <= cap) return ext[0] * ext[1] * ext[2];
+  double mean[3];
+  for (int d = 0; d < 3; ++d) {
+    mean[d] = (double)sm[d] / cnt;
+    const double var = fmax(0.0, (double)sq[d] / cnt - mean[d] * mean[d]);
+    ext[d] = min(ext[d], (int)ceil(sqrt(12.0 * var)) + S);
+  }
+  int k = 1;
+  while ((k + 1) * (k + 1) * (k + 1) <= cap) ++k;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) w[d] = min(ext[d], k);
+  // rank of each axis by extent (ties in axis order); the loops below use
+  // constant indices only, so that w and ext stay in registers
+  int rank[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rank[d] = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      if (e != d && (ext[e] < ext[d] || (ext[e] == ext[d] && e < d))) ++rank[d];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (rank[d] == r) {
+        const int other = w[(d + 1) % 3] * w[(d + 2) % 3];
+        w[d] = max(w[d], min(ext[d], cap / other));
+      }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int start = (int)floor(mean[d] - 0.5 * (w[d] - S));
+    lo[d] = min(max(start, mn[d]), mx[d] + S - w[d]);
+  }
+  return w[0] * w[1] * w[2];
+}
+
+template <typename PT, bool DRIFT, int S>
+__global__ void __launch_bounds__(kDepThreads)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
-  __shared__ unsigned long long acc[LDS];
-  __shared__ int blo[3], bhi[3];
+  __shared__ unsigned long long acc[kDepTile];
+  __shared__ int s_ref[6];                       // reference cell, its re-sort block
+  __shared__ int s_mn[2][3], s_mx[2][3], s_sum[2][3], s_cnt[2];
+  __shared__ unsigned long long s_sq[2][3];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * (256 * kDepPer);
-  if (tid < 3) {
-    blo[tid] = 0x7fffffff;
-    bhi[tid] = -0x7fffffff;
+  const int64_t base = xcd_block() * (kDepThreads * kDepPer);
+  for (int q = tid; q < kDepTile; q += kDepThreads) acc[q] = 0ull;
+  if (tid < 6) {
+    s_mn[tid / 3][tid % 3] = 0x7fffffff;
+    s_mx[tid / 3][tid % 3] = -0x7fffffff;
+    s_sum[tid / 3][tid % 3] = 0;
+    s_sq[tid / 3][tid % 3] = 0ull;
   }
-  Stencil<S> c[kDepPer];
+  if (tid < 2) s_cnt[tid] = 0;
+  Frac c[kDepPer];
   bool ok[kDepPer];
-  int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
   uint32_t bad_all = 0;
 #pragma unroll
   for (int u = 0; u < kDepPer; ++u) {
-    const int64_t i = base + u * 256 + tid;
+    const int64_t i = base + u * kDepThreads + tid;
     ok[u] = false;
     if (i >= pa.n) continue;
     double x[3];
@@ -147,82 +249,191 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
       }
       x[d] = v;
     }
-    const uint32_t bad = assign_setup<S>(x, mm, c[u]);
+    const uint32_t bad = assign_frac<S>(x, mm, c[u]);
     if (bad) {
       bad_all |= bad;
       continue;
     }
     ok[u] = true;
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = min(mn[d], c[u].cell[d]);
-      mx[d] = max(mx[d], c[u].cell[d]);
-    }
   }
   if (bad_all) atomicOr(flags, bad_all);
-  __syncthreads();
-  for (int d = 0; d < 3; ++d) {
-    const int a = wave_min(mn[d]), b = wave_max(mx[d]);
-    if ((tid & 63) == 0) {
-      atomicMin(&blo[d], a);
-      atomicMax(&bhi[d], b);
+  // a particle's block is that of the cell it lies in, floor(x / h), as in
+  // the re-sort's key (CIC: the first node; TSC: the nearest node, less one
+  // below its centre), which lies in [0, ng) on every axis
+  if (tid == 0) {
+    // the first valid particle, by constant indices (a runtime index into
+    // c[] would put it in scratch memory)
+    int rc[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
+#pragma unroll
+    for (int u = kDepPer - 1; u >= 0; --u)
+      if (ok[u])
+        for (int d = 0; d < 3; ++d) {
+          rc[d] = c[u].cell[d];
+          rb[d] = home_cell<S>(c[u], d) >> mm.block_shift;
+        }
+    for (int d = 0; d < 3; ++d) {
+      s_ref[d] = rc[d];
+      s_ref[3 + d] = rb[d];
     }
   }
   __syncthreads();
-  const int lx = bhi[0] - blo[0] + S, ly = bhi[1] - blo[1] + S, lz = bhi[2] - blo[2] + S;
-  if (lx < S) return;                                    // no valid particle in the workgroup
-  const int m = mm.ng - 1;
-  const int64_t vol_box = (int64_t)lx * ly * lz;
-  if (tid == 0 && vol_box > kDepLds) atomicAdd(flags + 2, 1u);
-  const bool use_lds = vol_box <= LDS;
-  if (use_lds) {
-    const int vol = lx * ly * lz;
-    for (int q = tid; q < vol; q += 256) acc[q] = 0ull;
-    __syncthreads();
+  const int ref[3] = {s_ref[0], s_ref[1], s_ref[2]};
+  const int m = mm.ng - 1, half = mm.ng >> 1;
+  // from here on c[u].cell holds the offset from ref; grp[u]: 0 in the
+  // reference block, 1 elsewhere
+  int mn[2][3], mx[2][3], sm[2][3], sq[2][3], cnt[2] = {0, 0};
+  for (int g = 0; g < 2; ++g)
+    for (int d = 0; d < 3; ++d) {
+      mn[g][d] = 0x7fffffff;
+      mx[g][d] = -0x7fffffff;
+      sm[g][d] = 0;
+      sq[g][d] = 0;
+    }
+  int grp[kDepPer];
 #pragma unroll
-    for (int u = 0; u < kDepPer; ++u) {
-      if (!ok[u]) continue;
-      const int ax = c[u].cell[0] - blo[0], ay = c[u].cell[1] - blo[1], az = c[u].cell[2] - blo[2];
+  for (int u = 0; u < kDepPer; ++u) {
+    grp[u] = 1;
+    if (!ok[u]) continue;
+    bool same = true;
+    for (int d = 0; d < 3; ++d) same = same && (home_cell<S>(c[u], d) >> mm.block_shift) == s_ref[3 + d];
+    grp[u] = same ? 0 : 1;
+    ++cnt[grp[u]];
+    for (int d = 0; d < 3; ++d) {
+      int o = c[u].cell[d] - ref[d];
+      if (mm.periodic) o = ((o + half) & m) - half;
+      c[u].cell[d] = o;
+      // |o| <= ng / 2 <= 1024: a thread's kDepPer squares fit an int
+      if (same) {
+        mn[0][d] = min(mn[0][d], o);
+        mx[0][d] = max(mx[0][d], o);
+        sm[0][d] += o;
+        sq[0][d] += o * o;
+      } else {
+        mn[1][d] = min(mn[1][d], o);
+        mx[1][d] = max(mx[1][d], o);
+        sm[1][d] += o;
+        sq[1][d] += o * o;
+      }
+    }
+  }
+  for (int g = 0; g < 2; ++g) {
+    for (int d = 0; d < 3; ++d) {
+      const int a = wave_min(mn[g][d]), b = wave_max(mx[g][d]), t = wave_sum(sm[g][d]);
+      // 64 lanes x kDepPer squares of at most 2^20: below 2^31
+      const int q2 = wave_sum(sq[g][d]);
+      if ((tid & 63) == 0) {
+        atomicMin(&s_mn[g][d], a);
+        atomicMax(&s_mx[g][d], b);
+        atomicAdd(&s_sum[g][d], t);
+        atomicAdd(&s_sq[g][d], (unsigned long long)(unsigned)q2);
+      }
+    }
+    const int t = wave_sum(cnt[g]);
+    if ((tid & 63) == 0 && t) atomicAdd(&s_cnt[g], t);
+  }
+  __syncthreads();
+  const int n0 = s_cnt[0], n1 = s_cnt[1];
+  if (n0 + n1 == 0) return;                    // no valid particle in the workgroup
+  // the two windows (the second empty when one window takes every particle);
+  // kept in separately named registers: a window chosen per particle by a
+  // runtime index would put them in scratch memory
+  int lo0[3], w0[3], lo1[3] = {0, 0, 0}, w1[3] = {S, S, S};
+  int vol0 = 0, vol1 = 0;
+  {
+    int umn[3], umx[3], usm[3];
+    unsigned long long usq[3];
+    for (int d = 0; d < 3; ++d) {
+      umn[d] = min(s_mn[0][d], s_mn[1][d]);
+      umx[d] = max(s_mx[0][d], s_mx[1][d]);
+      usm[d] = s_sum[0][d] + s_sum[1][d];
+      usq[d] = s_sq[0][d] + s_sq[1][d];
+    }
+    const int64_t uvol = (int64_t)(umx[0] - umn[0] + S) * (umx[1] - umn[1] + S) * (umx[2] - umn[2] + S);
+    if (uvol <= kDepTile || n0 == 0 || n1 == 0) {
+      // one window for every particle
+      vol0 = dep_window<S>(umn, umx, usm, usq, n0 + n1, kDepTile, lo0, w0);
+#pragma unroll
+      for (int u = 0; u < kDepPer; ++u) grp[u] = 0;
+    } else {
+      int64_t need[2];
+      for (int g = 0; g < 2; ++g)
+        need[g] = (int64_t)(s_mx[g][0] - s_mn[g][0] + S) * (s_mx[g][1] - s_mn[g][1] + S) *
+                  (s_mx[g][2] - s_mn[g][2] + S);
+      int cap0 = kDepTile / 2, cap1 = kDepTile / 2;
+      if (need[0] + need[1] <= kDepTile) {
+        cap0 = (int)need[0];
+        cap1 = (int)need[1];
+      } else if (need[1] <= kDepTile / 2) {
+        cap1 = (int)need[1];
+        cap0 = kDepTile - cap1;
+      } else if (need[0] <= kDepTile / 2) {
+        cap0 = (int)need[0];
+        cap1 = kDepTile - cap0;
+      }
+      vol0 = dep_window<S>(s_mn[0], s_mx[0], s_sum[0], s_sq[0], n0, cap0, lo0, w0);
+      vol1 = dep_window<S>(s_mn[1], s_mx[1], s_sum[1], s_sq[1], n1, cap1, lo1, w1);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kDepPer; ++u) {
+    if (!ok[u]) continue;
+    uint64_t wt[3][S];
+    for (int d = 0; d < 3; ++d) axis_weights<S>(c[u].f[d], mm.frac_bits, wt[d]);
+    const bool second = grp[u] != 0;
+    const int wx = second ? w1[0] : w0[0], wy = second ? w1[1] : w0[1], wz = second ? w1[2] : w0[2];
+    const int r0 = c[u].cell[0] - (second ? lo1[0] : lo0[0]);
+    const int r1 = c[u].cell[1] - (second ? lo1[1] : lo0[1]);
+    const int r2 = c[u].cell[2] - (second ? lo1[2] : lo0[2]);
+    const bool in = (unsigned)r0 <= (unsigned)(wx - S) && (unsigned)r1 <= (unsigned)(wy - S) &&
+                    (unsigned)r2 <= (unsigned)(wz - S);
+    if (in) {
+      unsigned long long* tile = acc + (second ? vol0 : 0);
       for (int dz = 0; dz < S; ++dz)
         for (int dy = 0; dy < S; ++dy) {
-          const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
+          const uint64_t wyz = wt[1][dy] * wt[2][dz];
           if (wyz == 0) continue;
+          const int row = ((r2 + dz) * wy + r1 + dy) * wx + r0;
           for (int dx = 0; dx < S; ++dx) {
-            const uint64_t wgt = c[u].w[0][dx] * wyz;
-            if (wgt) atomicAdd(&acc[((az + dz) * ly + ay + dy) * lx + ax + dx], (unsigned long long)wgt);
+            const uint64_t wgt = wt[0][dx] * wyz;
+            if (wgt) atomicAdd(&tile[row + dx], (unsigned long long)wgt);
           }
         }
-    }
-    __syncthreads();
-    for (int q = tid; q < vol; q += 256) {
-      const unsigned long long v = acc[q];
-      if (!v) continue;
-      int gx = blo[0] + q % lx, gy = blo[1] + (q / lx) % ly, gz = blo[2] + q / (lx * ly);
-      if (mm.periodic) {
-        gx &= m;
-        gy &= m;
-        gz &= m;
-      }
-      atomicAdd(counts + lin(gx, gy, gz, mm.ng), v);
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < kDepPer; ++u) {
-      if (!ok[u]) continue;
+    } else {
       for (int dz = 0; dz < S; ++dz) {
-        const int kk = mm.periodic ? ((c[u].cell[2] + dz) & m) : c[u].cell[2] + dz;
+        int kk = ref[2] + c[u].cell[2] + dz;
+        if (mm.periodic) kk &= m;
         for (int dy = 0; dy < S; ++dy) {
-          const int jj = mm.periodic ? ((c[u].cell[1] + dy) & m) : c[u].cell[1] + dy;
-          const uint64_t wyz = c[u].w[1][dy] * c[u].w[2][dz];
+          int jj = ref[1] + c[u].cell[1] + dy;
+          if (mm.periodic) jj &= m;
+          const uint64_t wyz = wt[1][dy] * wt[2][dz];
           if (wyz == 0) continue;
           for (int dx = 0; dx < S; ++dx) {
-            const uint64_t wgt = c[u].w[0][dx] * wyz;
+            const uint64_t wgt = wt[0][dx] * wyz;
             if (wgt == 0) continue;
-            const int ii = mm.periodic ? ((c[u].cell[0] + dx) & m) : c[u].cell[0] + dx;
+            int ii = ref[0] + c[u].cell[0] + dx;
+            if (mm.periodic) ii &= m;
             atomicAdd(counts + lin(ii, jj, kk, mm.ng), (unsigned long long)wgt);
           }
         }
       }
     }
+  }
+  __syncthreads();
+  for (int q = tid; q < vol0 + vol1; q += kDepThreads) {
+    const unsigned long long v = acc[q];
+    if (!v) continue;
+    const bool second = q >= vol0;
+    const int r = second ? q - vol0 : q;
+    const int wx = second ? w1[0] : w0[0], wy = second ? w1[1] : w0[1];
+    int gx = ref[0] + (second ? lo1[0] : lo0[0]) + r % wx;
+    int gy = ref[1] + (second ? lo1[1] : lo0[1]) + (r / wx) % wy;
+    int gz = ref[2] + (second ? lo1[2] : lo0[2]) + r / (wx * wy);
+    if (mm.periodic) {
+      gx &= m;
+      gy &= m;
+      gz &= m;
+    }
+    atomicAdd(counts + lin(gx, gy, gz, mm.ng), v);
   }
 }
 
@@ -530,36 +741,28 @@ inline unsigned grid_for(int64_t n, int per_block) {
 
 template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
-                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, bool big_tile,
-                          hipStream_t st) {
+                          const MeshMap& mm, uint64_t* counts, uint32_t* flags, hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st, K_DEPOSIT);
-  const dim3 g(grid_for(pa.n, 256 * kDepPer));
+  const dim3 g(grid_for(pa.n, kDepThreads * kDepPer));
   unsigned long long* cu = (unsigned long long*)counts;
-#define SDPM_DEP(D, L, S)                                                                       \
-  hipLaunchKernelGGL((k_drift_deposit<PT, D, L, S>), g, dim3(256), 0, st, pa, drift_coef, mm, cu, \
-                     flags)
+#define SDPM_DEP(D, S)                                                                         \
+  hipLaunchKernelGGL((k_drift_deposit<PT, D, S>), g, dim3(kDepThreads), 0, st, pa, drift_coef, mm, \
+                     cu, flags)
   if (mm.tsc) {
-    if (drift) {
-      if (big_tile) SDPM_DEP(true, kDepLdsBig, 3); else SDPM_DEP(true, kDepLds, 3);
-    } else {
-      if (big_tile) SDPM_DEP(false, kDepLdsBig, 3); else SDPM_DEP(false, kDepLds, 3);
-    }
-  } else if (drift) {
-    if (big_tile) SDPM_DEP(true, kDepLdsBig, 2); else SDPM_DEP(true, kDepLds, 2);
+    if (drift) SDPM_DEP(true, 3); else SDPM_DEP(false, 3);
   } else {
-    if (big_tile) SDPM_DEP(false, kDepLdsBig, 2); else SDPM_DEP(false, kDepLds, 2);
+    if (drift) SDPM_DEP(true, 2); else SDPM_DEP(false, 2);
   }
 #undef SDPM_DEP
   const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
   prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
 }
 
-int64_t deposit_workgroups(int64_t n) { return (n + 256 * kDepPer - 1) / (256 * kDepPer); }
 template void launch_drift_deposit<float>(const ParticleArgs&, double, int, const MeshMap&,
-                                          uint64_t*, uint32_t*, bool, hipStream_t);
+                                          uint64_t*, uint32_t*, hipStream_t);
 template void launch_drift_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
-                                           uint64_t*, uint32_t*, bool, hipStream_t);
+                                           uint64_t*, uint32_t*, hipStream_t);
 
 template <typename PT>
 void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,

@@ -214,7 +214,7 @@ int power_spectrum(const double* const x[3], int64_t npart, double box, int n, i
   mm.box = box;
   mm.scale = (double)n * std::ldexp(1.0, frac_bits) / box;
   mm.active = full;
-  launch_drift_deposit<double>(pa, 0.0, 0, mm, (uint64_t*)mesh, dflags, false, st);
+  launch_drift_deposit<double>(pa, 0.0, 0, mm, (uint64_t*)mesh, dflags, st);
   uint32_t hflags = 0;
   if (hipMemcpyAsync(&hflags, dflags, sizeof(uint32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)

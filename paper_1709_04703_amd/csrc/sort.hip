@@ -1,6 +1,8 @@
-// Morton re-sort of the active particles: 32-bit Morton codes of the
-// particles' cells, a stable LSD radix sort of (code, index) pairs with 8-bit
-// digits, and a gather of the SoA particle arrays into sorted order.  The
+// Re-sort of the active particles: a 32-bit key per particle (the Morton
+// code of its block of 2^shift cells per axis, then its cell row inside the
+// block: z, then y), a stable LSD radix sort of (key, index) pairs with 8-bit
+// digits, and a gather of the SoA particle arrays into sorted order.  Inside
+// a row the particles keep their previous order.  The
 // physics of a step does not depend on particle order (the deposit is exact
 // integer arithmetic, every other pass is per particle, compaction is
 // stable); the sort only makes neighbouring particles touch neighbouring
@@ -40,9 +42,12 @@ k_morton_keys(const double* __restrict__ x0, const double* __restrict__ x1,
   for (int d = 0; d < 3; ++d) {
     double v = floor(xs[d] * inv_h);
     v = v < 0.0 ? 0.0 : (v > ng - 1 ? ng - 1 : v);   // NaN -> ng - 1: order only
-    c[d] = ((int)v) >> shift;
+    c[d] = (int)v;
   }
-  key[q] = spread3((uint32_t)c[0]) | (spread3((uint32_t)c[1]) << 1) | (spread3((uint32_t)c[2]) << 2);
+  const uint32_t in = (uint32_t)((1 << shift) - 1);
+  const uint32_t block = spread3((uint32_t)(c[0] >> shift)) | (spread3((uint32_t)(c[1] >> shift)) << 1) |
+                         (spread3((uint32_t)(c[2] >> shift)) << 2);
+  key[q] = (block << (2 * shift)) | (((uint32_t)c[2] & in) << shift) | ((uint32_t)c[1] & in);
   val[q] = (uint32_t)q;
 }
 
@@ -217,7 +222,7 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
   uint32_t* part = hist + tab;
   int lg = 0;
   while ((1 << lg) < ng) ++lg;
-  const int bits = 3 * (lg - shift);
+  const int bits = 3 * (lg - shift) + 2 * shift;
   const unsigned gp = (unsigned)((n + 255) / 256);
   prof_begin(st, K_SORT);
   hipLaunchKernelGGL(k_morton_keys, dim3(gp), dim3(256), 0, st, pa.x[0], pa.x[1], pa.x[2], n,

@@ -25,7 +25,8 @@ def oracle_config(cfg) -> pm.Config:
     return pm.Config(ng=cfg.ng, box=cfg.box, omega_m=cfg.omega_m, omega_l=cfg.omega_l,
                      c_light=cfg.c_light, c_grav=cfg.c_grav, x_obs=tuple(cfg.x_obs),
                      shrink=bool(cfg.shrink), margin=cfg.margin, align=cfg.box_align,
-                     frac_bits=cfg.frac_bits, n_initial=cfg.n_initial)
+                     frac_bits=cfg.frac_bits, n_initial=cfg.n_initial,
+                     assignment="tsc" if cfg.assignment == 1 else "cic")
 
 
 def make_sim(cfg, capacity):

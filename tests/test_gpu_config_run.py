@@ -1,0 +1,169 @@
+"""Run-level parity at the 128^3 shrinking configuration: 128^3 particles on
+a 128^3 mesh, 2000 Mpc/h, Zel'dovich ICs at z = 49 (seed 4703), z = 49 -> 0
+in 100 steps uniform in a, the paper's reduced gravity speed (Sec. 3.1.1
+Eq. 12), lightcone removal and the periodic -> frozen-exterior switch (Sec.
+2.4, Sec. 3), FP32 V-cycles in FP64 defect correction to 1e-8, re-sort every
+10 steps.
+
+Two comparisons with the FP64 oracle:
+ * every step, the library's run against the oracle's own run of the same
+   schedule from the same ICs (run level: the relative RMS error of the
+   potential and of the momenta, and the largest position difference);
+ * every tenth step (5, 15, ..., 95; no re-sort in them), one oracle step
+   from the library's exact state (particles, potential, domain): the
+   deposit counts bit for bit, the force the kick applied (from the change
+   of the FP32 momenta) within 1e-5 relative RMS plus the FP32 rounding of
+   the stored momenta, the potential within 2 cond(A) tol (two solves), the
+   positions, and
+   the removed set exactly (the library's decisions are the FP64 predicate
+   on its own positions; the oracle's set may differ only for particles
+   within 1e-6 Mpc/h of the sphere)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pm
+from synth import zeldovich_ics
+
+from helpers import lib_config, log, make_sim, oracle_config, periodic_delta, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+NG, BOX, SEED, NSTEPS, Z_INIT = 128, 2000.0, 4703, 100, 49.0
+
+
+def _by_id(arr, ids):
+    return arr[np.argsort(ids)]
+
+
+def _cond(kappa_h2, ng, periodic, lo=None, hi=None):
+    if periodic:
+        lam_min = kappa_h2 if kappa_h2 > 0 else 2.0 - 2.0 * np.cos(2 * np.pi / ng)
+    else:
+        lam_min = kappa_h2 + sum(2.0 - 2.0 * np.cos(np.pi / (h_ - l_ + 2)) for l_, h_ in zip(lo, hi))
+    return (12.0 + kappa_h2) / lam_min
+
+
+@pytest.mark.timeout(1500)
+def test_128_shrinking_run_against_oracle():
+    a0 = 1.0 / (1.0 + Z_INIT)
+    x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
+    n = NG**3
+    cfg = lib_config(NG, BOX, c_grav=-1.0, shrink=1, n_initial=n, sort_every=10)
+    ocfg = oracle_config(cfg)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    sim.init_potential(a0)
+    ost = pm.init_state(x, p, ids, ocfg, a0)
+    del x, p
+    edges = np.linspace(a0, 1.0, NSTEPS + 1)
+    h = BOX / NG
+    xo = np.full(3, 0.5 * BOX)
+    rows, samples = [], []
+    for s in range(NSTEPS):
+        a, da = edges[s], edges[s + 1] - edges[s]
+        sampled = s % 10 == 5
+        if sampled:
+            st_in = sim.state()
+            k0 = sim.n_active
+            gx0, gp0, gid0 = sim.particles()
+            ist = pm.State(gx0.copy(), gp0.copy(), gid0.copy(), k0, sim.phi_numpy().copy(), a,
+                           bool(st_in["periodic"]), np.array(st_in["lo"], dtype=np.int64),
+                           np.array(st_in["hi"], dtype=np.int64))
+        st = sim.step(a, da)
+        assert max(st["res"]) <= cfg.tol
+        ost = pm.step(ost, ocfg, da)
+        k = sim.n_active
+        gx_all, gp_all, gid_all = sim.particles(all_particles=True)
+        # run level: the library's run against the oracle's run
+        common = np.intersect1d(gid_all[:k], ost.ids[:ost.n_active])
+        gsel = np.isin(gid_all[:k], common)
+        osel = np.isin(ost.ids[:ost.n_active], common)
+        gx = _by_id(gx_all[:k][gsel], gid_all[:k][gsel])
+        ox = _by_id(ost.x[:ost.n_active][osel], ost.ids[:ost.n_active][osel])
+        gp = _by_id(gp_all[:k][gsel], gid_all[:k][gsel])
+        op = _by_id(ost.p[:ost.n_active][osel], ost.ids[:ost.n_active][osel])
+        phi_g = sim.phi_numpy()
+        if ost.periodic:
+            phi_err = rel_rms(phi_g, ost.phi)
+        else:
+            sl = tuple(slice(ost.lo[d], ost.hi[d] + 1) for d in (2, 1, 0))
+            phi_err = rel_rms(phi_g[sl], ost.phi[sl])
+        row = {"step": s, "a": a + da, "active": int(k), "oracle_active": int(ost.n_active),
+               "periodic": int(st["periodic"]),
+               "phi_rel_rms": phi_err,
+               "p_rel_rms": rel_rms(gp, op) if len(common) else 0.0,
+               "x_max_cells": float(np.abs(periodic_delta(gx, ox, BOX)).max() / h)
+               if len(common) else 0.0}
+        rows.append(row)
+        assert st["periodic"] == int(ost.periodic), row
+        assert abs(k - ost.n_active) <= max(2, 1e-5 * n), row
+        if sampled:
+            diag = {}
+            ist = pm.step(ist, ocfg, da, diag)
+            # the deposit of identical positions: bit for bit
+            assert np.array_equal(sim.counts_numpy(), diag["counts"]), s
+            # the force the kick applied, from the change of the stored momenta
+            # (the k0 particles active before the step were all kicked; the
+            # oracle's per-particle force is in the order of its input state)
+            kick = st["a_half"] * st["dtau"]
+            p1 = _by_id(gp_all[:k0], gid_all[:k0])
+            dp_g = p1 - _by_id(gp0, gid0)
+            dp_o = _by_id(diag["g_particles"], gid0) * kick
+            rms_dp = np.sqrt(np.mean(dp_o**2))
+            f32 = 2.0**-24 * np.sqrt(np.mean(p1**2)) / rms_dp
+            ferr = float(np.sqrt(np.mean((dp_g - dp_o) ** 2)) / rms_dp)
+            # the potential after the step (both half sub-steps), on the active cells
+            if ist.periodic:
+                perr = rel_rms(phi_g, ist.phi)
+                cond = _cond(st["kappa_h2"][1], NG, True)
+            else:
+                sl = tuple(slice(ist.lo[d], ist.hi[d] + 1) for d in (2, 1, 0))
+                perr = rel_rms(phi_g[sl], ist.phi[sl])
+                cond = _cond(st["kappa_h2"][1], NG, False, ist.lo, ist.hi)
+            # positions from the identical state (the oracle's kick in FP64)
+            xg = _by_id(gx_all[:k0], gid_all[:k0])
+            xi = _by_id(ist.x[:k0], ist.ids[:k0])
+            xerr = float(np.abs(periodic_delta(xg, xi, BOX)).max() / h) if k0 else 0.0
+            # removal: the library's decision is the FP64 predicate on its own
+            # positions; the oracle's set differs only on the sphere's edge
+            rem_g = np.sort(gid_all[k:k0])
+            rem_o = np.sort(diag["removed"])
+            if st["n_removed"] or len(rem_o):
+                assert not pm.outside_lightcone(gx_all[:k], xo, st["r_lc"]).any()
+                assert pm.outside_lightcone(gx_all[k:k0], xo, st["r_lc"]).all()
+                diff = np.setxor1d(rem_g, rem_o)
+                if len(diff):
+                    xe = ist.x[np.isin(ist.ids, diff)]
+                    d = np.sqrt(np.sum((xe - xo) ** 2, axis=1))
+                    assert np.all(np.abs(d - st["r_lc"]) < 1e-6), (s, d - st["r_lc"])
+            sample = {"step": s, "force_rel_rms": ferr, "fp32_allowance": f32,
+                      "phi_rel_rms": perr, "phi_bound": 2 * cond * cfg.tol, "x_max_cells": xerr,
+                      "removed": int(len(rem_g)), "removed_oracle": int(len(rem_o)),
+                      "removed_differ": int(len(np.setxor1d(rem_g, rem_o)))}
+            samples.append(sample)
+            log(f"  identical-state step {s}: {sample}")
+            assert ferr <= 1e-5 + f32, sample
+            # each of the two solves ends within cond(A) tol of its exact
+            # solution; the second inherits the first's error damped by
+            # kappa / (kappa + lam_min) < 1
+            assert perr <= 2 * cond * cfg.tol, sample
+            assert xerr <= 1e-6, sample
+        if s % 5 == 0 or s == NSTEPS - 1:
+            log(f"step {s} a={a + da:.4f} active={k} oracle={ost.n_active} "
+                f"phi={row['phi_rel_rms']:.2e} p={row['p_rel_rms']:.2e} x={row['x_max_cells']:.2e}")
+    sim.close()
+    assert sim.n_active == 0 and ost.n_active == 0          # r_lc(1) = 0
+    assert len(samples) == 10
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "config_run_128.json"), "w") as fh:
+        json.dump({"run": rows, "identical_state": samples}, fh)
+    live = [r for r in rows if r["active"] > 1000]
+    worst = {key: max(r[key] for r in live) for key in ("phi_rel_rms", "p_rel_rms", "x_max_cells")}
+    log(f"run level, worst over steps with > 1000 active particles: {worst}")
+    assert worst["x_max_cells"] < 1e-2
+    assert worst["p_rel_rms"] < 1e-3
+    assert worst["phi_rel_rms"] < 1e-3

@@ -140,14 +140,17 @@ def test_deposit_in_dirichlet_box_and_domain_error():
 
 
 def _morton_key(x, ng, box, shift=0):
-    """Independent Morton code of each particle's cell block (cells >> shift;
-    bit loop)."""
-    c = np.clip(np.floor(x * (ng / box)), 0, ng - 1).astype(np.int64) >> shift
+    """Independent sort key: the Morton code of each particle's cell block
+    (cells >> shift; bit loop), then the z and y index of its cell row inside
+    the block."""
+    cell = np.clip(np.floor(x * (ng / box)), 0, ng - 1).astype(np.int64)
+    c = cell >> shift
     key = np.zeros(x.shape[0], dtype=np.int64)
     for b in range(11):
         for d in range(3):
             key |= ((c[:, d] >> b) & 1) << (3 * b + d)
-    return key
+    inner = (1 << shift) - 1
+    return (key << (2 * shift)) | ((cell[:, 2] & inner) << shift) | (cell[:, 1] & inner)
 
 
 @pytest.mark.parametrize("ng,n,prec,shift", [(64, 100003, 0, 0), (64, 100003, 0, 4), (32, 5000, 1, 2)])
@@ -216,12 +219,10 @@ def test_step_run_twice_bit_identical():
 
 
 def test_deposit_exact_when_particles_fill_their_sort_blocks():
-    """Particles uniform over a 64^3 mesh and re-sorted by 16^3-cell blocks
-    before every step: a workgroup's 1024 particles spread over a whole block,
-    whose CIC cells span 17^3 = 4913 cells, more than the deposit's smaller
-    LDS tile, so the first step's deposit overflows it and the following
-    steps take the larger tile.  The counts of every step equal the oracle's
-    deposit of the drifted positions, bit for bit."""
+    """Particles uniform over a 64^3 mesh and re-sorted before every step:
+    the deposit's workgroups see compact rows of 16^3-cell blocks.  The
+    counts of every step equal the oracle's deposit of the drifted
+    positions, bit for bit."""
     def wrap(v, box):
         v = np.where(v < 0.0, v + box, v)
         return np.where(v >= box, v - box, v)
@@ -239,7 +240,52 @@ def test_deposit_exact_when_particles_fill_their_sort_blocks():
         xh = wrap(x0 + p0 * (0.5 * st["dtau"] / a), box)
         assert np.array_equal(sim.counts_numpy(), pm.deposit(xh, ng, box, B, True)), f"step {s}"
         a += da
-    log("  three steps of exact counts across both deposit tiles")
+    log("  three steps of exact counts")
+    sim.close()
+
+
+@pytest.mark.parametrize("assignment", [0, 1])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_deposit_exact_with_one_far_outlier_per_workgroup(assignment, periodic):
+    """A lattice in memory order (each deposit workgroup of 1024 particles
+    covers a compact slab) with one particle per 1024 moved far away, and a
+    few per workgroup spread over the whole domain: the outliers take global
+    atomics, the rest the workgroup's LDS window.  Counts equal the oracle's
+    bit for bit, for CIC and TSC, on the periodic mesh and on a
+    frozen-exterior box."""
+    ng, box = 64, 640.0
+    h = box / ng
+    rng = np.random.Generator(np.random.PCG64(12 + assignment + 2 * periodic))
+    if periodic:
+        x = lattice_positions(ng, box) + rng.normal(size=(ng**3, 3)) * 0.3 * h
+        x = np.mod(x, box)
+        x[x >= box] = 0.0
+    else:
+        # a lattice over cells 21 .. 42, inside the lightcone sphere of radius
+        # 200 about the centre (its index box is about cells 10 .. 54)
+        g = lattice_positions(22, 22 * h) + 21 * h
+        x = g + rng.uniform(-0.2, 0.2, size=g.shape) * h
+    n = x.shape[0]
+    far = np.arange(37, n, 1024)
+    if periodic:
+        x[far] = rng.uniform(0.0, box, size=(far.size, 3))
+        x[far[::3] + 5] = rng.uniform(0.0, box, size=(far[::3].size, 3))
+    else:
+        x[far] = rng.uniform(0.5 * box - 100.0, 0.5 * box + 100.0, size=(far.size, 3))
+    ids = np.arange(n, dtype=np.uint32)
+    log(f"deposit with outliers n={n} assignment={assignment} periodic={periodic}")
+    cfg = lib_config(ng, box, assignment=assignment, n_initial=n, shrink=0 if periodic else 1)
+    sim = make_sim(cfg, n)
+    sim.bind(x, np.zeros_like(x), ids)
+    if not periodic:
+        assert sim.shrink_radius(200.0) == 0
+        st = sim.state()
+        assert st["periodic"] == 0 and st["hi"][0] - st["lo"][0] < ng - 8, st
+    sim.deposit()
+    st = sim.state()
+    asg = "tsc" if assignment else "cic"
+    ref = pm.deposit(x, ng, box, B, bool(st["periodic"]), asg)
+    assert np.array_equal(sim.counts_numpy(), ref)
     sim.close()
 
 
@@ -268,7 +314,6 @@ def test_tsc_deposit_and_interpolation_in_a_dirichlet_box():
     ng, box, n = 64, 640.0, 4000
     cfg = lib_config(ng, box, shrink=1, n_initial=n, assignment=P.SDPM_ASSIGN_TSC, precision=1)
     ocfg = oracle_config(cfg)
-    ocfg.assignment = "tsc"
     x, p, ids = clustered_particles(n, box, 9, ng=ng, width_cells=1.0, lo=260.0, hi=380.0)
     rng = np.random.Generator(np.random.PCG64(21))
     phi = rng.normal(size=(ng, ng, ng))

@@ -6,13 +6,16 @@ whole step at this size in seconds, so it checks what it can compute one by
 one and properties that hold at any size, on one full sdpm_step (the first of
 the run, which also sorts):
 
- * sort: the particle order is exactly the stable sort by the Morton key of
-   the cell (a stable sort has one result);
+ * sort: the particle order is exactly the stable sort by the key (Morton
+   code of the 16^3-cell block, then the cell row inside it; a stable sort
+   has one result);
  * drift + deposit: positions after the first drift equal x + p c evaluated
    in FP64 (no fused multiply-add), so the total mass (sum of counts =
    n 2^(3B)) and the counts of whole z-planes (both periodic edges and the
    middle) are bit-exact against the oracle's deposit of the particles that
-   reach those planes;
+   reach those planes; a separate test checks the whole counts array
+   bit for bit at step 25 of the run, where the particles have moved off
+   their sorted rows;
  * both solves: the potentials against the oracle's exact FFT solves of the
    oracle's own source of those counts, within cond(A) * tol;
  * kick + second drift: sampled momenta within FP32 rounding plus a 1e-5
@@ -36,15 +39,43 @@ NG, BOX, Z_INIT, SEED, SCHEDULE, B = 512, 2000.0, 49.0, 512, 200, 14
 
 
 def morton_key(x, ng, box, shift):
-    """Cell Morton key: bit b of the cell's x, y, z index goes to bit 3b,
-    3b+1, 3b+2 of the key (a table of the bit spreading of 0..1023)."""
+    """Sort key: the Morton code of the cell's block (cells >> shift; bit b
+    of the block's x, y, z index goes to bit 3b, 3b+1, 3b+2, from a table of
+    the bit spreading of 0..1023), then the z and y index of the cell's row
+    inside the block."""
     table = np.array([sum(((v >> b) & 1) << (3 * b) for b in range(10)) for v in range(1024)],
                      dtype=np.int64)
     key = np.zeros(x.shape[0], dtype=np.int64)
+    inner = (1 << shift) - 1
+    rows = np.zeros(x.shape[0], dtype=np.int64)
     for d in range(3):
-        c = np.clip(np.floor(x[:, d] * (ng / box)), 0, ng - 1).astype(np.int64) >> shift
-        key |= table[c] << d
-    return key
+        c = np.clip(np.floor(x[:, d] * (ng / box)), 0, ng - 1).astype(np.int64)
+        key |= table[c >> shift] << d
+        if d == 1:
+            rows |= c & inner
+        elif d == 2:
+            rows |= (c & inner) << shift
+    return (key << (2 * shift)) | rows
+
+
+def exact_counts(x, periodic):
+    """The oracle's CIC deposit (its fixed-point coordinates and corner
+    weights) summed exactly at full size: np.add.at over 10^9 corner
+    contributions takes minutes, so each uint64 weight (< 2^42) is split
+    into two 21-bit halves accumulated by np.bincount in float64, where
+    every partial sum is an integer below 2^53 and hence exact in any order."""
+    u = pm.fixed_point_coords(x, NG, BOX, B, periodic)
+    lo_sum = np.zeros(NG**3)
+    hi_sum = np.zeros(NG**3)
+    mask = np.uint64((1 << 21) - 1)
+    for flat, wt in pm._corners(u, NG, B, periodic):
+        lo_sum += np.bincount(flat, weights=(wt & mask).astype(np.float64), minlength=NG**3)
+        hi_sum += np.bincount(flat, weights=(wt >> np.uint64(21)).astype(np.float64),
+                              minlength=NG**3)
+        del flat, wt
+    assert max(lo_sum.max(), hi_sum.max()) < 2.0**53
+    return ((hi_sum.astype(np.uint64) << np.uint64(21)) + lo_sum.astype(np.uint64)).reshape(
+        NG, NG, NG)
 
 
 def wrap(x, box):
@@ -81,7 +112,7 @@ def test_fullsize_step(big):
     assert max(st["res"]) <= cfg.tol
     x1, p1, ids1 = sim.particles()
 
-    # sort: exactly the stable sort by cell Morton key (ids are the initial
+    # sort: exactly the stable sort by the block Morton + row key (ids are the initial
     # indices): a permutation with non-decreasing keys, ties in index order
     assert np.array_equal(ids0, np.arange(n, dtype=np.uint32))
     order = ids1.astype(np.int64)
@@ -150,6 +181,41 @@ def test_fullsize_step(big):
     ferr = rel_rms(g_gpu, g_ref)
     log(f"  force rel rms {ferr:.2e}")
     assert ferr <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_deposit_whole_array_at_step_25():
+    """The whole 512^3 counts array of the deposit in step 25 (five steps
+    after the last sort, particles moved off their sorted rows, some deposit
+    workgroups with outliers) equals the oracle's deposit of the drifted
+    positions, bit for bit."""
+    import paper_1709_04703_amd as P
+    a0 = 1.0 / (1.0 + Z_INIT)
+    x, p, ids = zeldovich_ics(NG, BOX, a0, SEED)
+    n = x.shape[0]
+    cfg = lib_config(NG, BOX, c_grav=-1.0, shrink=1, precision=P.SDPM_MIXED, n_initial=n,
+                     sort_every=10, warm_start=P.SDPM_WS_PREV | P.SDPM_WS_EXTRAP)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    del x, p, ids
+    sim.init_potential(a0)
+    edges = np.linspace(a0, 1.0, SCHEDULE + 1)
+    log("full size: 25 steps, then the whole counts array of step 25")
+    for s_ in range(25):
+        sim.step(edges[s_], edges[s_ + 1] - edges[s_])
+    x0, p0, _ = sim.particles()
+    a, da = edges[25], edges[26] - edges[25]
+    st = sim.step(a, da)
+    assert st["periodic"] == 1
+    xh = wrap(x0 + p0 * (0.5 * st["dtau"] / a), BOX)
+    del x0, p0
+    got = sim.counts_numpy().reshape(NG, NG, NG)
+    sim.close()
+    ref = exact_counts(xh, True)
+    del xh
+    bad = int(np.count_nonzero(got != ref))
+    log(f"  cells differing: {bad}")
+    assert bad == 0
 
 
 def test_fullsize_removal(big):

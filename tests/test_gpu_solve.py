@@ -138,3 +138,34 @@ def test_zero_rhs_gives_zero_potential():
     assert not sim.rhs.cpu().numpy().any()
     assert not sim.phi_numpy().any()
     sim.close()
+
+
+@pytest.mark.parametrize("ng", [16, 32])
+@pytest.mark.parametrize("kappa", [0.01, 0.1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vcycles_per_solve_on_small_periodic_meshes(ng, kappa, prec):
+    # the coarsest level is swept until its slowest mode (the constant one
+    # when kappa > 0) is reduced 1e3-fold, so each V-cycle converges at the
+    # two-grid rate and a solve to 1e-10 takes at most 10 cycles; in mixed
+    # precision one FP64 correction cannot reduce the residual below the
+    # rounding floor of its FP32 correction, (12 + kappa h^2) 2^-24 /
+    # (kappa h^2) (7e-5 at kappa h^2 = 0.01), so 1e-10 needs at least
+    # ceil(log 1e-10 / log floor) corrections of up to four cycles each
+    box = 100.0
+    n = ng**3
+    x, p, ids = clustered_particles(n, box, 31 + ng, ng=ng, width_cells=1.5, n_halo=6)
+    log(f"small-mesh solve ng={ng} kappa={kappa} precision={prec}")
+    cfg = lib_config(ng, box, precision=prec, tol=1e-10, n_initial=n)
+    sim = make_sim(cfg, n)
+    rng = np.random.Generator(np.random.PCG64(3 * ng))
+    sim.bind(x, p, ids, phi=rng.normal(size=(ng, ng, ng)) * 1e-3)
+    sim.deposit()
+    st = sim.solve(kappa, 1.5 * 0.3 / 0.4)
+    log(f"  vcycles={st['vcycles']} outer={st['outer_iters'][0]} res={st['res'][0]:.2e}")
+    assert st["res"][0] <= 1e-10
+    bound = 10
+    if prec == 0:
+        floor = (12.0 + kappa) * 2.0**-24 / kappa
+        bound = max(10, 4 * int(np.ceil(np.log(1e-10) / np.log(floor))))
+    assert st["vcycles"] <= bound
+    sim.close()

@@ -81,13 +81,16 @@ def test_periodic_poisson_run_20_steps():
     sim.close()
 
 
-def test_shrinking_run_against_oracle():
+@pytest.mark.parametrize("assignment", [0, 1])
+def test_shrinking_run_against_oracle(assignment):
     # 64^3 particles, 2000 Mpc/h, z = 49 -> 0 in 32 steps, gravity with the
-    # paper's reduced speed, mixed precision
+    # paper's reduced speed, mixed precision; CIC and TSC assignment (the
+    # latter through the periodic -> frozen-exterior switch and removal too)
     ng, box, nsteps = 64, 2000.0, 32
     a0 = 1.0 / 50.0
     x, p, ids = zeldovich_ics(ng, box, a0, 4703)
-    cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3)
+    log(f"shrinking run 64^3 assignment={'tsc' if assignment else 'cic'}")
+    cfg = lib_config(ng, box, c_grav=-1.0, shrink=1, n_initial=ng**3, assignment=assignment)
     ocfg = oracle_config(cfg)
     sim = make_sim(cfg, ng**3)
     sim.bind(x, p, ids)
@@ -283,7 +286,6 @@ def test_one_tsc_step_from_identical_state(prec):
     cfg = lib_config(ng, box, precision=prec, c_grav=-1.0, tol=1e-10, n_initial=ng**3,
                      assignment=P.SDPM_ASSIGN_TSC)
     ocfg = oracle_config(cfg)
-    ocfg.assignment = "tsc"
     sim = make_sim(cfg, ng**3)
     sim.bind(x, p, ids)
     sim.init_potential(a0)

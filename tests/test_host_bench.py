@@ -56,3 +56,10 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode == 2
     assert "one GPU only" in p.stderr
     assert p.stdout == ""
+
+
+def test_net_flops_per_voxel():
+    # method: 3 -> 16, 16 -> 16 (x3), 16 -> 1 channels of 3^3 taps, 2 flop per tap
+    assert bench.NET_METHOD_FLOPS_PER_VOXEL == 2 * 27 * (48 + 768 + 16) == 44928
+    # kernels: every layer padded to 16 x 16 channels
+    assert bench.NET_KERNEL_FLOPS_PER_VOXEL == 5 * 13824 == 69120
