@@ -158,28 +158,21 @@ __device__ inline int wave_sum(int v) {
 }
 
 // Window of at most cap cells for the cnt particles with offsets in [mn, mx]
-// (sums sm and sums of squares sq per axis), support S: the bounding box
-// when it fits; else per axis the extent of a uniform spread of the same
-// variance (sqrt(12 var) + S, which a few far particles hardly change),
-// reduced to fit cap (the axes with the smallest extent kept whole first),
+// (sums sm per axis), support S: the bounding box when it fits; else a box
+// of at most cap cells (the axes with the smallest extent kept whole first)
 // centred on the mean.  Returns its volume.
 template <int S>
-__device__ inline int dep_window(const int mn[3], const int mx[3], const int sm[3],
-                                 const unsigned long long sq[3], int cnt, int cap, int lo[3],
-                                 int w[3]) {
+__device__ inline int dep_window(const int mn[3], const int mx[3], const int sm[3], int cnt,
+                                 int cap, int lo[3], int w[3]) {
   int ext[3];
+  double mean[3];
   for (int d = 0; d < 3; ++d) {
     ext[d] = mx[d] - mn[d] + S;
     lo[d] = mn[d];
     w[d] = ext[d];
+    mean[d] = (double)sm[d] / cnt;
   }
   if ((int64_t)ext[0] * ext[1] * ext[2] <= cap) return ext[0] * ext[1] * ext[2];
-  double mean[3];
-  for (int d = 0; d < 3; ++d) {
-    mean[d] = (double)sm[d] / cnt;
-    const double var = fmax(0.0, (double)sq[d] / cnt - mean[d] * mean[d]);
-    ext[d] = min(ext[d], (int)ceil(sqrt(12.0 * var)) + S);
-  }
   int k = 1;
   while ((k + 1) * (k + 1) * (k + 1) <= cap) ++k;
 #pragma unroll
@@ -210,24 +203,40 @@ __device__ inline int dep_window(const int mn[3], const int mx[3], const int sm[
   return w[0] * w[1] * w[2];
 }
 
+// Bounding box (min, max, sum of offsets, count) of the particles a lane
+// selects, reduced over the workgroup into the shared slots.
+__device__ inline void dep_reduce(const int mn[3], const int mx[3], const int sm[3], int cnt,
+                                  int* s_mn, int* s_mx, int* s_sum, int* s_cnt) {
+  const bool lead = (threadIdx.x & 63) == 0;
+  for (int d = 0; d < 3; ++d) {
+    const int a = wave_min(mn[d]), b = wave_max(mx[d]), t = wave_sum(sm[d]);
+    if (lead) {
+      atomicMin(s_mn + d, a);
+      atomicMax(s_mx + d, b);
+      atomicAdd(s_sum + d, t);
+    }
+  }
+  const int t = wave_sum(cnt);
+  if (lead && t) atomicAdd(s_cnt, t);
+}
+
 template <typename PT, bool DRIFT, int S>
 __global__ void __launch_bounds__(kDepThreads)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
   __shared__ unsigned long long acc[kDepTile];
   __shared__ int s_ref[6];                       // reference cell, its re-sort block
-  __shared__ int s_mn[2][3], s_mx[2][3], s_sum[2][3], s_cnt[2];
-  __shared__ unsigned long long s_sq[2][3];
+  // [0]: all particles; [1], [2]: the two groups (only when [0] overflows)
+  __shared__ int s_mn[3][3], s_mx[3][3], s_sum[3][3], s_cnt[3];
   const int tid = threadIdx.x;
   const int64_t base = xcd_block() * (kDepThreads * kDepPer);
   for (int q = tid; q < kDepTile; q += kDepThreads) acc[q] = 0ull;
-  if (tid < 6) {
+  if (tid < 9) {
     s_mn[tid / 3][tid % 3] = 0x7fffffff;
     s_mx[tid / 3][tid % 3] = -0x7fffffff;
     s_sum[tid / 3][tid % 3] = 0;
-    s_sq[tid / 3][tid % 3] = 0ull;
   }
-  if (tid < 2) s_cnt[tid] = 0;
+  if (tid < 3) s_cnt[tid] = 0;
   Frac c[kDepPer];
   bool ok[kDepPer];
   uint32_t bad_all = 0;
@@ -279,86 +288,96 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
   __syncthreads();
   const int ref[3] = {s_ref[0], s_ref[1], s_ref[2]};
   const int m = mm.ng - 1, half = mm.ng >> 1;
-  // from here on c[u].cell holds the offset from ref; grp[u]: 0 in the
-  // reference block, 1 elsewhere
-  int mn[2][3], mx[2][3], sm[2][3], sq[2][3], cnt[2] = {0, 0};
-  for (int g = 0; g < 2; ++g)
-    for (int d = 0; d < 3; ++d) {
-      mn[g][d] = 0x7fffffff;
-      mx[g][d] = -0x7fffffff;
-      sm[g][d] = 0;
-      sq[g][d] = 0;
-    }
-  int grp[kDepPer];
+  // from here on c[u].cell holds the offset from ref
+  {
+    int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+    int sm[3] = {0, 0, 0};
+    int cnt = 0;
 #pragma unroll
-  for (int u = 0; u < kDepPer; ++u) {
-    grp[u] = 1;
-    if (!ok[u]) continue;
-    bool same = true;
-    for (int d = 0; d < 3; ++d) same = same && (home_cell<S>(c[u], d) >> mm.block_shift) == s_ref[3 + d];
-    grp[u] = same ? 0 : 1;
-    ++cnt[grp[u]];
-    for (int d = 0; d < 3; ++d) {
-      int o = c[u].cell[d] - ref[d];
-      if (mm.periodic) o = ((o + half) & m) - half;
-      c[u].cell[d] = o;
-      // |o| <= ng / 2 <= 1024: a thread's kDepPer squares fit an int
-      if (same) {
-        mn[0][d] = min(mn[0][d], o);
-        mx[0][d] = max(mx[0][d], o);
-        sm[0][d] += o;
-        sq[0][d] += o * o;
-      } else {
-        mn[1][d] = min(mn[1][d], o);
-        mx[1][d] = max(mx[1][d], o);
-        sm[1][d] += o;
-        sq[1][d] += o * o;
+    for (int u = 0; u < kDepPer; ++u) {
+      if (!ok[u]) continue;
+      ++cnt;
+      for (int d = 0; d < 3; ++d) {
+        int o = c[u].cell[d] - ref[d];
+        if (mm.periodic) o = ((o + half) & m) - half;
+        c[u].cell[d] = o;
+        mn[d] = min(mn[d], o);
+        mx[d] = max(mx[d], o);
+        sm[d] += o;
       }
     }
-  }
-  for (int g = 0; g < 2; ++g) {
-    for (int d = 0; d < 3; ++d) {
-      const int a = wave_min(mn[g][d]), b = wave_max(mx[g][d]), t = wave_sum(sm[g][d]);
-      // 64 lanes x kDepPer squares of at most 2^20: below 2^31
-      const int q2 = wave_sum(sq[g][d]);
-      if ((tid & 63) == 0) {
-        atomicMin(&s_mn[g][d], a);
-        atomicMax(&s_mx[g][d], b);
-        atomicAdd(&s_sum[g][d], t);
-        atomicAdd(&s_sq[g][d], (unsigned long long)(unsigned)q2);
-      }
-    }
-    const int t = wave_sum(cnt[g]);
-    if ((tid & 63) == 0 && t) atomicAdd(&s_cnt[g], t);
+    dep_reduce(mn, mx, sm, cnt, s_mn[0], s_mx[0], s_sum[0], s_cnt);
   }
   __syncthreads();
-  const int n0 = s_cnt[0], n1 = s_cnt[1];
-  if (n0 + n1 == 0) return;                    // no valid particle in the workgroup
-  // the two windows (the second empty when one window takes every particle);
+  const int total = s_cnt[0];
+  if (total == 0) return;                      // no valid particle in the workgroup
+  // the windows (the second empty when one window takes every particle),
   // kept in separately named registers: a window chosen per particle by a
   // runtime index would put them in scratch memory
   int lo0[3], w0[3], lo1[3] = {0, 0, 0}, w1[3] = {S, S, S};
   int vol0 = 0, vol1 = 0;
-  {
-    int umn[3], umx[3], usm[3];
-    unsigned long long usq[3];
-    for (int d = 0; d < 3; ++d) {
-      umn[d] = min(s_mn[0][d], s_mn[1][d]);
-      umx[d] = max(s_mx[0][d], s_mx[1][d]);
-      usm[d] = s_sum[0][d] + s_sum[1][d];
-      usq[d] = s_sq[0][d] + s_sq[1][d];
-    }
-    const int64_t uvol = (int64_t)(umx[0] - umn[0] + S) * (umx[1] - umn[1] + S) * (umx[2] - umn[2] + S);
-    if (uvol <= kDepTile || n0 == 0 || n1 == 0) {
-      // one window for every particle
-      vol0 = dep_window<S>(umn, umx, usm, usq, n0 + n1, kDepTile, lo0, w0);
+  bool grp[kDepPer];
 #pragma unroll
-      for (int u = 0; u < kDepPer; ++u) grp[u] = 0;
+  for (int u = 0; u < kDepPer; ++u) grp[u] = false;
+  const int64_t uvol = (int64_t)(s_mx[0][0] - s_mn[0][0] + S) * (s_mx[0][1] - s_mn[0][1] + S) *
+                       (s_mx[0][2] - s_mn[0][2] + S);
+  if (uvol <= kDepTile) {
+    for (int d = 0; d < 3; ++d) {
+      lo0[d] = s_mn[0][d];
+      w0[d] = s_mx[0][d] - s_mn[0][d] + S;
+    }
+    vol0 = (int)uvol;
+  } else {
+    // rare: the two groups' boxes (a uniform branch: every thread read the
+    // same shared values)
+    int mn[2][3], mx[2][3], sm[2][3], cnt[2] = {0, 0};
+    for (int g = 0; g < 2; ++g)
+      for (int d = 0; d < 3; ++d) {
+        mn[g][d] = 0x7fffffff;
+        mx[g][d] = -0x7fffffff;
+        sm[g][d] = 0;
+      }
+#pragma unroll
+    for (int u = 0; u < kDepPer; ++u) {
+      if (!ok[u]) continue;
+      // the particle's block from its cell (reference + offset, back in
+      // [0, ng) on a periodic mesh), as for the reference particle
+      bool same = true;
+      for (int d = 0; d < 3; ++d) {
+        int home = ref[d] + c[u].cell[d] + (S == 3 && c[u].f[d] >= 0 ? 1 : 0);
+        if (mm.periodic) home &= m;
+        same = same && (home >> mm.block_shift) == s_ref[3 + d];
+      }
+      grp[u] = !same;
+      for (int d = 0; d < 3; ++d) {
+        const int o = c[u].cell[d];
+        if (same) {
+          mn[0][d] = min(mn[0][d], o);
+          mx[0][d] = max(mx[0][d], o);
+          sm[0][d] += o;
+        } else {
+          mn[1][d] = min(mn[1][d], o);
+          mx[1][d] = max(mx[1][d], o);
+          sm[1][d] += o;
+        }
+      }
+      if (same) ++cnt[0]; else ++cnt[1];
+    }
+    dep_reduce(mn[0], mx[0], sm[0], cnt[0], s_mn[1], s_mx[1], s_sum[1], s_cnt + 1);
+    dep_reduce(mn[1], mx[1], sm[1], cnt[1], s_mn[2], s_mx[2], s_sum[2], s_cnt + 2);
+    __syncthreads();
+    const int n0 = s_cnt[1], n1 = s_cnt[2];
+    if (n0 == 0 || n1 == 0) {
+      // one group only: one window of tile size over all particles
+      const int g = n0 ? 1 : 2;
+      vol0 = dep_window<S>(s_mn[g], s_mx[g], s_sum[g], n0 + n1, kDepTile, lo0, w0);
+#pragma unroll
+      for (int u = 0; u < kDepPer; ++u) grp[u] = false;
     } else {
       int64_t need[2];
       for (int g = 0; g < 2; ++g)
-        need[g] = (int64_t)(s_mx[g][0] - s_mn[g][0] + S) * (s_mx[g][1] - s_mn[g][1] + S) *
-                  (s_mx[g][2] - s_mn[g][2] + S);
+        need[g] = (int64_t)(s_mx[g + 1][0] - s_mn[g + 1][0] + S) *
+                  (s_mx[g + 1][1] - s_mn[g + 1][1] + S) * (s_mx[g + 1][2] - s_mn[g + 1][2] + S);
       int cap0 = kDepTile / 2, cap1 = kDepTile / 2;
       if (need[0] + need[1] <= kDepTile) {
         cap0 = (int)need[0];
@@ -370,8 +389,8 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
         cap0 = (int)need[0];
         cap1 = kDepTile - cap0;
       }
-      vol0 = dep_window<S>(s_mn[0], s_mx[0], s_sum[0], s_sq[0], n0, cap0, lo0, w0);
-      vol1 = dep_window<S>(s_mn[1], s_mx[1], s_sum[1], s_sq[1], n1, cap1, lo1, w1);
+      vol0 = dep_window<S>(s_mn[1], s_mx[1], s_sum[1], n0, cap0, lo0, w0);
+      vol1 = dep_window<S>(s_mn[2], s_mx[2], s_sum[2], n1, cap1, lo1, w1);
     }
   }
 #pragma unroll
@@ -379,7 +398,7 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     if (!ok[u]) continue;
     uint64_t wt[3][S];
     for (int d = 0; d < 3; ++d) axis_weights<S>(c[u].f[d], mm.frac_bits, wt[d]);
-    const bool second = grp[u] != 0;
+    const bool second = grp[u];
     const int wx = second ? w1[0] : w0[0], wy = second ? w1[1] : w0[1], wz = second ? w1[2] : w0[2];
     const int r0 = c[u].cell[0] - (second ? lo1[0] : lo0[0]);
     const int r1 = c[u].cell[1] - (second ? lo1[1] : lo0[1]);

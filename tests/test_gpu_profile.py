@@ -39,10 +39,11 @@ def test_full_and_selected_profiles_agree():
         assert sel[k]["launches"] == full[k]["launches"] > 0
         assert sel[k]["bytes"] == full[k]["bytes"]
         assert sel[k]["ms"] > 0.0
-    # unit costs: the rhs pass moves 24 B per cell, a finest-level half sweep
-    # 6 B per cell of the level (4 B read of the other colour, 4 B source and
-    # 4 B written per cell of its colour)
-    assert full["rhs"]["bytes"] == 24.0 * ng**3 * full["rhs"]["launches"]
+    # unit costs: the rhs pass, fused with the solve's first FP64 residual,
+    # moves 28 B per cell (counts, phi and rhs 8 B each, the FP32 residual
+    # 4 B), a finest-level half sweep 6 B per cell of the level (4 B read of
+    # the other colour, 4 B source and 4 B written per cell of its colour)
+    assert full["rhs"]["bytes"] == 28.0 * ng**3 * full["rhs"]["launches"]
     assert full["smooth_color"]["bytes"] == 6.0 * ng**3 * full["smooth_color"]["launches"]
     # an unknown name is rejected and the selection stays as it was
     with pytest.raises(P.SdpmError, match="EINVAL"):
