@@ -431,6 +431,18 @@ int sdpm_net_prep(int32_t n, const float* r, const float* phi, float s_r, float 
  * BF16 ng^3 x 16 buffers for the hidden layers.                            */
 int sdpm_net_forward(int32_t n, const float* params, const void* act0, void* act_a, void* act_b,
                      float* out, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the net
+ * forward of sdpm_net_forward, same kernels and the same result, with the
+ * two hidden-layer buffers taken from a static device array inside the
+ * library (16 MiB per GPU, held until the process ends) instead of act_a /
+ * act_b.  It calls no allocating routine.  n: a power of two in [16, 64]
+ * (SDPM_EINVAL beyond 64: the array's size); params, act0, out and stream as
+ * for sdpm_net_forward.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller.                                    */
+int sdpm_net_forward_noalloc(int32_t n, const float* params, const void* act0, float* out,
+                             void* stream);
 /* One training step on one sample: forward, loss = mean((out - target_scale
  * target)^2)
  * written to *loss_dev (device FP32), backward through all layers, Adam

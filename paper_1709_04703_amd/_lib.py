@@ -36,7 +36,7 @@ EXPORTS = [
     "sdpm_shrink", "sdpm_shrink_radius", "sdpm_get_state", "sdpm_deposit", "sdpm_solve",
     "sdpm_interp_force", "sdpm_sort", "sdpm_set_warmstart_weights", "sdpm_conv3d",
     "sdpm_conv3d_wgrad", "sdpm_net_scratch_bytes", "sdpm_net_prep", "sdpm_net_forward",
-    "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
+    "sdpm_net_forward_noalloc", "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
     "sdpm_ade_sweep", "sdpm_pk_workspace_bytes", "sdpm_power_spectrum", "sdpm_profile_kernels",
 ]
@@ -147,6 +147,7 @@ def library() -> ctypes.CDLL:
         "sdpm_net_scratch_bytes": [i32, P(i64)],
         "sdpm_net_prep": [i32, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp],
         "sdpm_net_forward": [i32, vp, vp, vp, vp, vp, vp],
+        "sdpm_net_forward_noalloc": [i32, vp, vp, vp, vp],
         "sdpm_net_train_step": [i32, vp, vp, vp, i32, ctypes.c_float, vp, vp, ctypes.c_float, vp,
                                 i64, vp, vp],
         "sdpm_record": [vp, vp, i64],
@@ -289,6 +290,10 @@ def net_prep(n, r, phi, s_r, s_phi, kappa_h2, act0):
 def net_forward(n, params, act0, act_a, act_b, out):
     check(library().sdpm_net_forward(n, _ptr(params), _ptr(act0), _ptr(act_a), _ptr(act_b),
                                      _ptr(out), _stream()))
+
+
+def net_forward_noalloc(n, params, act0, out):
+    check(library().sdpm_net_forward_noalloc(n, _ptr(params), _ptr(act0), _ptr(out), _stream()))
 
 
 def net_train_step(n, params, m1, m2, step, lr, act0, target, target_scale, scratch, loss):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 #include <utility>
 
@@ -1461,6 +1462,57 @@ int sdpm_net_forward(int32_t n, const float* params, const void* act0, void* act
   net_forward(n, params, (const uint16_t*)act0, (uint16_t*)act_a, (uint16_t*)act_b, out,
               (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "net_forward failed");
+}
+
+// Allocation-free net forward.  The two hidden-layer activation buffers live
+// in `scratch`, a file-scope device array of two kNoAllocMaxN^3 x 16 BF16
+// buffers (16 MiB), of which each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): its device
+// address is looked up once per device with hipGetSymbolAddress, with that
+// device current, on the entry point's first call there, and kept.
+namespace {
+constexpr int kNoAllocMaxN = 64;
+constexpr size_t kNoAllocActBytes =
+    (size_t)kNoAllocMaxN * kNoAllocMaxN * kNoAllocMaxN * 16 * sizeof(uint16_t);
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[2 * kNoAllocActBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return fail(nullptr, SDPM_EHIP, "net_forward_noalloc: hipGetSymbolAddress failed");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SDPM_OK;
+}
+}  // namespace
+
+int sdpm_net_forward_noalloc(int32_t n, const float* params, const void* act0, float* out,
+                             void* stream) {
+  if (!net_size_ok(n) || !params || !act0 || !out)
+    return fail(nullptr, SDPM_EINVAL, "net_forward_noalloc: bad arguments");
+  if (n > kNoAllocMaxN)
+    return fail(nullptr, SDPM_EINVAL,
+                "net_forward_noalloc: n = %d exceeds the static scratch (n <= %d)", n,
+                kNoAllocMaxN);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(nullptr, SDPM_EHIP, "net_forward_noalloc: no current device below %d",
+                kNoAllocMaxDevices);
+  void* base = nullptr;
+  const int rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  uint16_t* act_a = (uint16_t*)base;
+  uint16_t* act_b = (uint16_t*)((char*)base + kNoAllocActBytes);
+  net_forward(n, params, (const uint16_t*)act0, act_a, act_b, out, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK
+                                         : fail(nullptr, SDPM_EHIP, "net_forward_noalloc failed");
 }
 
 int sdpm_net_train_step(int32_t n, float* params, float* m1, float* m2, int32_t step, float lr,
