@@ -85,12 +85,6 @@ __device__ inline uint32_t assign_frac(const double x[3], const MeshMap& mm, Fra
   return bad;
 }
 
-// The cell a particle lies in along axis d, floor(x_d / h).
-template <int S>
-__device__ inline int home_cell(const Frac& c, int d) {
-  return S == 2 ? c.cell[d] : c.cell[d] + (c.f[d] < 0 ? 0 : 1);
-}
-
 // The same with the weights expanded.
 template <int S>
 __device__ inline uint32_t assign_setup(const double x[3], const MeshMap& mm, Stencil<S>& c) {
@@ -133,14 +127,15 @@ __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0,
 // a few stray particles never push a whole workgroup onto global atomics.
 // Cells are taken relative to a reference cell (thread 0's first valid
 // particle; on a periodic mesh offsets wrap into [-ng/2, ng/2)).  One window
-// is the workgroup's bounding box when that fits the tile.  Otherwise the
-// particles split in two groups, those in the reference particle's re-sort
-// block and the rest (a workgroup of sorted particles straddles at most two
-// blocks, which need not be neighbours in every axis), each with its own
-// window: its bounding box if both fit, else boxes of a share of the tile
-// centred on the group's mean offset, the axes with the smallest extent
-// kept whole first.  Integer sums: the result is exact and the same in any
-// order and for any routing.
+// is the workgroup's bounding box when that fits the tile.  Otherwise (a
+// workgroup of re-sorted particles that straddles two blocks, which need
+// not be neighbours along every axis) the particles split in two groups at
+// the first particle in memory order that lies in the last particle's
+// block, each group with its own window: its bounding box if both fit, else
+// boxes of a share of the tile centred on the group's mean offset, the axes
+// with the smallest extent kept whole first; only those workgroups pay for
+// the split's two further reductions.  Integer sums: the result is
+// exact and the same in any order and for any routing.
 constexpr int kDepThreads = 512, kDepPer = 2;
 constexpr int kDepTile = 4096;       // 32 KB
 
@@ -225,7 +220,10 @@ __global__ void __launch_bounds__(kDepThreads)
 k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __restrict__ counts,
                 uint32_t* __restrict__ flags) {
   __shared__ unsigned long long acc[kDepTile];
-  __shared__ int s_ref[6];                       // reference cell, its re-sort block
+  // [0..2] reference cell (thread 0's first valid particle), [3..5] the
+  // re-sort block of the last valid particle, [6] whether there is one
+  __shared__ int s_ref[7];
+  __shared__ int s_split;
   // [0]: all particles; [1], [2]: the two groups (only when [0] overflows)
   __shared__ int s_mn[3][3], s_mx[3][3], s_sum[3][3], s_cnt[3];
   const int tid = threadIdx.x;
@@ -266,23 +264,36 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     ok[u] = true;
   }
   if (bad_all) atomicOr(flags, bad_all);
-  // a particle's block is that of the cell it lies in, floor(x / h), as in
-  // the re-sort's key (CIC: the first node; TSC: the nearest node, less one
-  // below its centre), which lies in [0, ng) on every axis
-  if (tid == 0) {
-    // the first valid particle, by constant indices (a runtime index into
-    // c[] would put it in scratch memory)
-    int rc[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
+  // the reference cell (the first valid particle of thread 0) and the block
+  // of the last valid particle of the last thread (the workgroup's two ends
+  // in memory order), chosen by constant indices (a runtime index into c[]
+  // would put it in scratch memory)
+  if (tid == 0 || tid == kDepThreads - 1) {
+    const bool last = tid != 0;
+    int r[3] = {0, 0, 0};
+    bool any = false;
 #pragma unroll
-    for (int u = kDepPer - 1; u >= 0; --u)
-      if (ok[u])
-        for (int d = 0; d < 3; ++d) {
-          rc[d] = c[u].cell[d];
-          rb[d] = home_cell<S>(c[u], d) >> mm.block_shift;
-        }
-    for (int d = 0; d < 3; ++d) {
-      s_ref[d] = rc[d];
-      s_ref[3 + d] = rb[d];
+    for (int q = 0; q < kDepPer; ++q) {
+      // thread 0 ends on its first valid particle, the last thread on its last
+      const int u = last ? q : kDepPer - 1 - q;
+      if (ok[u]) {
+        any = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          r[d] = last ? (c[u].cell[d] + (S == 3 && c[u].f[d] >= 0 ? 1 : 0)) >> mm.block_shift
+                      : c[u].cell[d];
+      }
+    }
+    if (last) {
+      s_ref[3] = r[0];
+      s_ref[4] = r[1];
+      s_ref[5] = r[2];
+      s_ref[6] = any ? 1 : 0;
+    } else {
+      s_ref[0] = r[0];
+      s_ref[1] = r[1];
+      s_ref[2] = r[2];
+      s_split = 0x7fffffff;
     }
   }
   __syncthreads();
@@ -328,8 +339,30 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     }
     vol0 = (int)uvol;
   } else {
-    // rare: the two groups' boxes (a uniform branch: every thread read the
-    // same shared values)
+    // rare: the particles split in two groups at the first particle (in
+    // memory order) that lies in the last particle's re-sort block: a
+    // workgroup of sorted particles straddles at most two blocks, the first
+    // rows of the second following the last rows of the first; particles
+    // that drifted over the shared face since the sort stay next to the group
+    // they join.  Then the two groups' boxes (a uniform branch: every thread
+    // read the same shared values)
+    int split = 0x7fffffff;
+#pragma unroll
+    for (int u = 0; u < kDepPer; ++u) {
+      if (!ok[u] || !s_ref[6]) continue;
+      bool inb = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int home = ref[d] + c[u].cell[d] + (S == 3 && c[u].f[d] >= 0 ? 1 : 0);
+        if (mm.periodic) home &= m;
+        inb = inb && (home >> mm.block_shift) == s_ref[3 + d];
+      }
+      if (inb) split = min(split, u * kDepThreads + tid);
+    }
+    split = wave_min(split);
+    if ((tid & 63) == 0) atomicMin(&s_split, split);
+    __syncthreads();
+    split = s_split;
     int mn[2][3], mx[2][3], sm[2][3], cnt[2] = {0, 0};
     for (int g = 0; g < 2; ++g)
       for (int d = 0; d < 3; ++d) {
@@ -340,15 +373,9 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
 #pragma unroll
     for (int u = 0; u < kDepPer; ++u) {
       if (!ok[u]) continue;
-      // the particle's block from its cell (reference + offset, back in
-      // [0, ng) on a periodic mesh), as for the reference particle
-      bool same = true;
-      for (int d = 0; d < 3; ++d) {
-        int home = ref[d] + c[u].cell[d] + (S == 3 && c[u].f[d] >= 0 ? 1 : 0);
-        if (mm.periodic) home &= m;
-        same = same && (home >> mm.block_shift) == s_ref[3 + d];
-      }
+      const bool same = u * kDepThreads + tid < split;
       grp[u] = !same;
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int o = c[u].cell[d];
         if (same) {

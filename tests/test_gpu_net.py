@@ -270,7 +270,7 @@ def test_train_step_matches_oracle_adam():
     # the two sides round the same FP32 sums to BF16; they differ only where a
     # sum falls within FP32 accumulation error of a rounding boundary
     assert abs(loss_g - loss_o) <= 1e-4 * loss_o
-    assert rel_rms(g_from_m1[live], g[live]) < 1e-3
-    assert rel_rms(m2_g[live], m2_o[live]) < 1e-3
-    assert rel_rms((th_g - vec32)[live], (th_o - vec32)[live]) < 1e-3
+    assert rel_rms(g_from_m1[live], g[live]) < 1e-4
+    assert rel_rms(m2_g[live], m2_o[live]) < 1e-4
+    assert rel_rms((th_g - vec32)[live], (th_o - vec32)[live]) < 1e-4
     assert np.all(th_g[mask] == 0.0)
