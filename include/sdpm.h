@@ -244,14 +244,18 @@ int sdpm_init_potential(sdpm_ctx* ctx, double a, sdpm_step_stats* out);
  * CIC deposit, solve to a_half, FD force, CIC interpolation, kick with
  * a_half (Eq. 8), drift dtau/2 with a + da (Eq. 9), second field half
  * sub-step (skipped for static gravity), lightcone and elimination at
- * a + da.  out may be NULL.  Errors: SDPM_EINVAL / SDPM_ESTATE before any
- * device work (nothing changed); SDPM_ENOCONV, SDPM_EDOMAIN, SDPM_EOVERFLOW
- * and SDPM_EFULL after the whole step has been applied (positions, momenta,
- * potential and time advanced; ENOCONV keeps the best iterate of the solve
- * that missed tol; with EDOMAIN / EOVERFLOW the offending particles took
- * the first drift only, without deposit, kick or second drift, and the
- * lightcone is not applied in that step: no particle removed, the domain
- * not shrunk); SDPM_EHIP as above.                                         */
+ * a + da.  The deposit reads the drifted positions without storing them;
+ * the interpolation pass evaluates the same first drift again and stores
+ * only the positions at a + da.  out may be NULL.  Errors: SDPM_EINVAL /
+ * SDPM_ESTATE before any device work (nothing changed); SDPM_ENOCONV,
+ * SDPM_EDOMAIN, SDPM_EOVERFLOW and SDPM_EFULL after the whole step has been
+ * applied (positions, momenta, potential and time advanced; ENOCONV keeps
+ * the best iterate of the solve that missed tol; with EDOMAIN / EOVERFLOW
+ * the offending particles took the first drift only, without deposit, kick
+ * or second drift, and the lightcone is not applied in that step: no
+ * particle removed, the domain not shrunk); SDPM_EHIP as above (a failure
+ * in the first solve returns before the kick, with positions and momenta
+ * as they were at a).                                                      */
 int sdpm_step(sdpm_ctx* ctx, double a, double da, sdpm_step_stats* out);
 
 /* "Shrink domain": lightcone at a; stable-partitions the active particles

@@ -1090,7 +1090,9 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
                                           : lightcone_radius(a, g.omega_m, g.omega_l, g.c_light);
     launch_lc_mark(particle_args(c), g.x_obs, r0 * r0, c->lc_mark, c->st);
   }
-  // drift dtau/2 with a(t), then density at t + dt/2   (Table 2 rows 1-2)
+  // drift dtau/2 with a(t), then density at t + dt/2   (Table 2 rows 1-2);
+  // the deposit does not store the drifted positions, the interpolation pass
+  // recomputes them: an error before it leaves the particles untouched
   deposit(c, 0.5 * sc.dtau / a, 1);
   HIP_TRY(c, hipEventRecord(c->ev[1], c->st));
   // Phi from t to t + dt/2                              (row 3)
@@ -1115,17 +1117,19 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   {
     const ParticleArgs pa = particle_args(c);
     const MeshMap mm = mesh_map(c);
+    // the first drift is applied here (the deposit only used it)
+    const double drift0 = 0.5 * sc.dtau / a;
     const double kick = sc.a_half * sc.dtau, drift = 0.5 * sc.dtau / (a + da);
     if (g.precision == SDPM_MIXED) {
       // FP32 force mesh (FP64 differences), then 12-byte gathers per CIC cell
       launch_force_mesh(c->fields.phi, c->gmesh, g.ng, mm.active, 0.5 / h, c->st);
-      launch_interp_kick_drift<float>(pa, c->fields.phi, c->gmesh, mm, 0.5 / h, kick, drift,
+      launch_interp_kick_drift<float>(pa, c->fields.phi, c->gmesh, mm, 0.5 / h, drift0, kick, drift,
                                       g.x_obs, sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
                                       c->dflags, c->st);
     } else {
-      launch_interp_kick_drift<double>(pa, c->fields.phi, nullptr, mm, 0.5 / h, kick, drift,
-                                       g.x_obs, sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
-                                       c->dflags, c->st);
+      launch_interp_kick_drift<double>(pa, c->fields.phi, nullptr, mm, 0.5 / h, drift0, kick,
+                                       drift, g.x_obs, sc.r_lc_end * sc.r_lc_end, removal,
+                                       c->dflags + 1, c->dflags, c->st);
     }
   }
   HIP_TRY(c, hipEventRecord(c->ev[4], c->st));

@@ -187,8 +187,9 @@ struct MeshMap {
   int tsc;            // 0: CIC, 1: TSC assignment
   int block_shift;    // the re-sort's blocks: 2^block_shift cells per axis
 };
-// Drift (when drift != 0) and fixed-point CIC / TSC deposit into counts.
-// flags[0] collects error bits.
+// Fixed-point CIC / TSC deposit into counts, at the positions drifted by
+// drift_coef p when drift != 0 (the drifted positions are not stored: the
+// step's interpolation pass recomputes them).  flags[0] collects error bits.
 template <typename PT>
 void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
                           const MeshMap& mm, uint64_t* counts, uint32_t* flags, hipStream_t st);
@@ -218,13 +219,16 @@ void launch_lc_cross(const ParticleArgs& pa, const double* x_obs, double r2, dou
                      double light, double disp, double a1, double da, const uint8_t* mark,
                      const LcArgs& out, int64_t base, int64_t capacity,
                      unsigned long long* counter, hipStream_t st);
-// With g3 != nullptr the force is interpolated from that mesh (made by
+// First drift (drift0_coef p, the positions the deposit used), force
+// interpolation, kick and second drift of the active particles.  With g3 !=
+// nullptr the force is interpolated from that mesh (made by
 // launch_force_mesh), else from phi directly (FP64 differences).
 template <typename PT>
 void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,
-                              const MeshMap& mm, double inv2h, double kick_coef, double drift_coef,
-                              const double* x_obs, double r2, int count_removed,
-                              uint32_t* removed_count, uint32_t* flags, hipStream_t st);
+                              const MeshMap& mm, double inv2h, double drift0_coef,
+                              double kick_coef, double drift_coef, const double* x_obs, double r2,
+                              int count_removed, uint32_t* removed_count, uint32_t* flags,
+                              hipStream_t st);
 void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMap& mm,
                          double inv2h, double* g0, double* g1, double* g2, uint32_t* flags,
                          hipStream_t st);

@@ -87,6 +87,19 @@ __device__ inline int block_linear() {
   return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
 }
 
+// x neighbours across lanes.  The vector kernels give each lane 4
+// consecutive entries of a row and lay a row segment over the W = blockDim.x
+// lanes of one wave (W <= 64), so the entry just before a lane's vector is
+// the last entry of the lane before it and the entry just after is the
+// first of the lane after it.  Taking them from those lanes' registers
+// spares two narrow loads per lane and row that touch the same cache lines
+// as the vector loads (FP64 residual at 512^3: 679 -> 541 us).  Lanes at a
+// segment's ends, or whose neighbour lane lies outside the box, still load.
+template <int W, typename T>
+__device__ inline T lane_prev(T v) { return __shfl_up(v, 1u, W); }
+template <int W, typename T>
+__device__ inline T lane_next(T v) { return __shfl_down(v, 1u, W); }
+
 // Workgroup -> tile mapping.  Box kernels launch a 1-D grid of gx*gy*gz
 // workgroups.  The hardware hands consecutive workgroup ids to the 8 XCDs in
 // turn; the ids are remapped so that each XCD receives one contiguous run of
@@ -226,6 +239,7 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
     const int k1 = min(k0 + kResKz - 1, b.hi[2]);
     const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
     const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
+    const bool lane_l = threadIdx.x > 0, lane_r = threadIdx.x + 1 < TXV && i0 + 4 <= b.hi[0];
     const int hn = n >> 1;
     const int64_t hc = half_cells(n);
     Vec4<double> below = *(const Vec4<double>*)(phi + lin(i0, j, (k0 - 1) & m, n));
@@ -237,7 +251,9 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
       // (the hint measured slower here: the rhs rows are read while the
       // neighbouring phi rows are still being reused)
       const Vec4<double> rv = *(const Vec4<double>*)(rhs + lin(i0, j, k, n));
-      const double xl = phi[lin(il, j, k, n)], xr = phi[lin(ir, j, k, n)];
+      double xl = lane_prev<TXV>(ctr.v[3]), xr = lane_next<TXV>(ctr.v[0]);
+      if (!lane_l) xl = phi[lin(il, j, k, n)];
+      if (!lane_r) xr = phi[lin(ir, j, k, n)];
       double res[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -331,6 +347,7 @@ k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict_
     const int k1 = min(k0 + kResKz - 1, b.hi[2]);
     const int jp = (j + 1) & m, jm = (j - 1) & m, il = (i0 - 1) & m, ir = (i0 + 4) & m;
     const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
+    const bool lane_l = threadIdx.x > 0, lane_r = threadIdx.x + 1 < TXV && i0 + 4 <= b.hi[0];
     const int hn = n >> 1;
     const int64_t hc = half_cells(n);
     Vec4<double> raw, below, ctr, ctr_raw;
@@ -353,7 +370,9 @@ k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict_
       start4(lin(i0, jp, k, n), raw, d);
 #pragma unroll
       for (int q = 0; q < 4; ++q) yp.v[q] = raw.v[q] + (double)d.v[q];
-      const double xl = start1(lin(il, j, k, n)), xr = start1(lin(ir, j, k, n));
+      double xl = lane_prev<TXV>(ctr.v[3]), xr = lane_next<TXV>(ctr.v[0]);
+      if (!lane_l) xl = start1(lin(il, j, k, n));
+      if (!lane_r) xr = start1(lin(ir, j, k, n));
       const int64_t c = lin(i0, j, k, n);
       Vec4<uint64_t> cnt;
       {
@@ -595,7 +614,9 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
       const Vec4<T> zm = *(const Vec4<T>*)(ex + ((int64_t)km * n + j) * hn + h0);
       const Vec4<T> zp = *(const Vec4<T>*)(ex + ((int64_t)kp * n + j) * hn + h0);
       // x neighbours i -+ 1 sit at half index h - 1 + p and h + p; the one
-      // outside the vector: cell 2 h0 - 1 (p = 0) or 2 h0 + 8 (p = 1)
+      // outside the vector: cell 2 h0 - 1 (p = 0) or 2 h0 + 8 (p = 1), read
+      // from memory (taking it from the neighbour lane, as the residual
+      // kernels do, measured no faster here)
       const T xs = ex[row + ((p ? (2 * h0 + 8) : (2 * h0 - 1)) & m) / 2];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -638,6 +659,7 @@ k_resid_red_v4(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__
   const int k0 = b.lo[2] + tl.bz * kVecKz;
   const int k1 = min(k0 + kVecKz - 1, b.hi[2]);
   const int jp = (j + 1) & m, jm = (j - 1) & m;
+  const bool lane_l = threadIdx.x > 0, lane_r = threadIdx.x + 1 < TXV && h0 + 4 <= hhi;
   for (int k = k0; k <= k1; ++k) {
     const int p = (j + k) & 1;
     const int kp = (k + 1) & m, km = (k - 1) & m;
@@ -649,7 +671,9 @@ k_resid_red_v4(const T* __restrict__ e, const T* __restrict__ r, T* __restrict__
     const Vec4<T> yp = *(const Vec4<T>*)(e + oth + ((int64_t)k * n + jp) * hn + h0);
     const Vec4<T> zm = *(const Vec4<T>*)(e + oth + ((int64_t)km * n + j) * hn + h0);
     const Vec4<T> zp = *(const Vec4<T>*)(e + oth + ((int64_t)kp * n + j) * hn + h0);
-    const T xs = e[oth + row + ((p ? (2 * h0 + 8) : (2 * h0 - 1)) & m) / 2];
+    const T sl = lane_prev<TXV>(xc.v[3]), sr = lane_next<TXV>(xc.v[0]);
+    T xs = p ? sr : sl;
+    if (p ? !lane_r : !lane_l) xs = e[oth + row + ((p ? (2 * h0 + 8) : (2 * h0 - 1)) & m) / 2];
     T out[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1245,13 +1269,16 @@ k_force_mesh_v4(const double* __restrict__ phi, float* __restrict__ g3, int n, B
   const bool full = i0 >= b.lo[0] && i0 + 3 <= b.hi[0];
   const int seg0 = ib + tl.bx * TXV * 4;          // first cell of this row segment
   const bool row_full = seg0 >= b.lo[0] && seg0 + 4 * TXV - 1 <= b.hi[0];
+  const bool lane_l = threadIdx.x > 0, lane_r = threadIdx.x + 1 < TXV && i0 + 4 <= b.hi[0];
   Vec4<double> below = *(const Vec4<double>*)(phi + lin(i0, j, (k0 - 1) & m, n));
   Vec4<double> ctr = *(const Vec4<double>*)(phi + lin(i0, j, k0, n));
   for (int k = k0; k <= k1; ++k) {
     const Vec4<double> above = *(const Vec4<double>*)(phi + lin(i0, j, (k + 1) & m, n));
     const Vec4<double> ym = *(const Vec4<double>*)(phi + lin(i0, jm, k, n));
     const Vec4<double> yp = *(const Vec4<double>*)(phi + lin(i0, jp, k, n));
-    const double xl = phi[lin(il, j, k, n)], xr = phi[lin(ir, j, k, n)];
+    double xl = lane_prev<TXV>(ctr.v[3]), xr = lane_next<TXV>(ctr.v[0]);
+    if (!lane_l) xl = phi[lin(il, j, k, n)];
+    if (!lane_r) xr = phi[lin(ir, j, k, n)];
     float out[12];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

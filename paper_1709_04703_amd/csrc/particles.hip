@@ -107,6 +107,16 @@ __device__ inline double drift_nofma(double x, double p, double c) {
   return x + dp;
 }
 
+// Drift with the periodic wrap into [0, L) (a drift is far below L).
+__device__ inline double drift_wrap(double x, double p, double c, const MeshMap& mm) {
+  double v = drift_nofma(x, p, c);
+  if (mm.periodic) {
+    if (v < 0.0) v += mm.box;
+    if (v >= mm.box) v -= mm.box;
+  }
+  return v;
+}
+
 // Squared distance ((dx^2 + dy^2) + dz^2) without fused multiply-adds, so
 // that the lightcone test is the same FP64 expression everywhere.
 __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0, double o1,
@@ -119,7 +129,8 @@ __device__ inline double dist2_nofma(double x0, double x1, double x2, double o0,
   return (a + b) + c;
 }
 
-// Drift + deposit, kDepThreads x kDepPer particles per workgroup, with the
+// Deposit at the drifted positions (computed here, not stored),
+// kDepThreads x kDepPer particles per workgroup, with the
 // weights summed in LDS windows (at most kDepTile cells together) and each
 // nonzero window cell added to the mesh with one global 64-bit atomic.
 // Every particle is routed on its own: one whose S^3 support lies inside its
@@ -246,14 +257,10 @@ k_drift_deposit(ParticleArgs pa, double coef, MeshMap mm, unsigned long long* __
     double x[3];
     for (int d = 0; d < 3; ++d) {
       double v = __builtin_nontemporal_load(pa.x[d] + i);
-      if (DRIFT) {
-        v = drift_nofma(v, (double)__builtin_nontemporal_load((const PT*)pa.p[d] + i), coef);
-        if (mm.periodic) {
-          if (v < 0.0) v += mm.box;
-          if (v >= mm.box) v -= mm.box;
-        }
-        __builtin_nontemporal_store(v, pa.x[d] + i);
-      }
+      // the drifted position is used here and not stored: the interpolation
+      // pass of the step evaluates the same expression again and stores the
+      // step's final position
+      if (DRIFT) v = drift_wrap(v, (double)__builtin_nontemporal_load((const PT*)pa.p[d] + i), coef, mm);
       x[d] = v;
     }
     const uint32_t bad = assign_frac<S>(x, mm, c[u]);
@@ -541,10 +548,14 @@ __device__ inline void interp_g3(const float* __restrict__ g3, const MeshMap& mm
   }
 }
 
+// One particle per thread: the step's first drift by drift0_coef p (Eq. 7;
+// the deposit used these positions without storing them), the force
+// interpolated there, the kick with kick_coef (Eq. 8) and the second drift
+// by drift_coef p (Eq. 9); only the final momenta and positions are stored.
 template <typename PT, bool G3, int S>
 __global__ void __launch_bounds__(256)
 k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float* __restrict__ g3,
-                    MeshMap mm, double inv2h,
+                    MeshMap mm, double inv2h, double drift0_coef,
                     double kick_coef, double drift_coef, double o0, double o1, double o2,
                     double r2, int count_removed, uint32_t* __restrict__ removed_count,
                     uint32_t* __restrict__ flags) {
@@ -557,10 +568,14 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
     const PT p_old[3] = {__builtin_nontemporal_load((const PT*)pa.p[0] + i),
                          __builtin_nontemporal_load((const PT*)pa.p[1] + i),
                          __builtin_nontemporal_load((const PT*)pa.p[2] + i)};
+    // the step's first drift (Eq. 7), the same expression the deposit used
+    for (int d = 0; d < 3; ++d) x[d] = drift_wrap(x[d], (double)p_old[d], drift0_coef, mm);
     Stencil<S> c;
     const uint32_t bad = assign_setup<S>(x, mm, c);
     if (bad) {
+      // outside the mesh: the particle keeps the first drift only
       atomicOr(flags, bad);
+      for (int d = 0; d < 3; ++d) __builtin_nontemporal_store(x[d], pa.x[d] + i);
     } else {
       double g[3];
       if (G3)
@@ -571,13 +586,8 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
         PT* p = (PT*)pa.p[d];
         const PT pn = (PT)((double)p_old[d] + g[d] * kick_coef);
         __builtin_nontemporal_store(pn, p + i);
-        double v = drift_nofma(x[d], (double)pn, drift_coef);
-        if (mm.periodic) {
-          if (v < 0.0) v += mm.box;
-          if (v >= mm.box) v -= mm.box;
-        }
-        __builtin_nontemporal_store(v, pa.x[d] + i);
-        x[d] = v;
+        x[d] = drift_wrap(x[d], (double)pn, drift_coef, mm);
+        __builtin_nontemporal_store(x[d], pa.x[d] + i);
       }
       if (count_removed) out = dist2_nofma(x[0], x[1], x[2], o0, o1, o2) > r2;
     }
@@ -801,7 +811,9 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
     if (drift) SDPM_DEP(true, 2); else SDPM_DEP(false, 2);
   }
 #undef SDPM_DEP
-  const double per = drift ? 48.0 + 3.0 * sizeof(PT) : 24.0;
+  // positions (and with the drift the momenta) read; the drifted positions
+  // are not written back
+  const double per = drift ? 24.0 + 3.0 * sizeof(PT) : 24.0;
   prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
 }
 
@@ -812,14 +824,16 @@ template void launch_drift_deposit<double>(const ParticleArgs&, double, int, con
 
 template <typename PT>
 void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const float* g3,
-                              const MeshMap& mm, double inv2h, double kick_coef, double drift_coef,
-                              const double* x_obs, double r2, int count_removed,
-                              uint32_t* removed_count, uint32_t* flags, hipStream_t st) {
+                              const MeshMap& mm, double inv2h, double drift0_coef,
+                              double kick_coef, double drift_coef, const double* x_obs, double r2,
+                              int count_removed, uint32_t* removed_count, uint32_t* flags,
+                              hipStream_t st) {
   if (pa.n <= 0) return;
   prof_begin(st, K_INTERP_KICK_DRIFT);
 #define SDPM_IKD(G, S)                                                                          \
   hipLaunchKernelGGL((k_interp_kick_drift<PT, G, S>), dim3(grid_for(pa.n, 256)), dim3(256), 0, st, \
-                     pa, phi, g3, mm, inv2h, kick_coef, drift_coef, x_obs[0], x_obs[1], x_obs[2],  \
+                     pa, phi, g3, mm, inv2h, drift0_coef, kick_coef, drift_coef, x_obs[0],        \
+                     x_obs[1], x_obs[2],                                                          \
                      r2, count_removed, removed_count, flags)
   if (mm.tsc) {
     if (g3) SDPM_IKD(true, 3); else SDPM_IKD(false, 3);
@@ -832,11 +846,11 @@ void launch_interp_kick_drift(const ParticleArgs& pa, const double* phi, const f
            (48.0 + 6.0 * sizeof(PT)) * pa.n + (g3 ? 12.0 : 8.0) * box_cells(mm.active));
 }
 template void launch_interp_kick_drift<float>(const ParticleArgs&, const double*, const float*,
-                                              const MeshMap&, double, double, double,
+                                              const MeshMap&, double, double, double, double,
                                               const double*, double, int, uint32_t*, uint32_t*,
                                               hipStream_t);
 template void launch_interp_kick_drift<double>(const ParticleArgs&, const double*, const float*,
-                                               const MeshMap&, double, double, double,
+                                               const MeshMap&, double, double, double, double,
                                                const double*, double, int, uint32_t*, uint32_t*,
                                                hipStream_t);
 
