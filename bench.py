@@ -580,7 +580,9 @@ def main():
     ap.add_argument("--seed", type=int, default=512)
     ap.add_argument("--modes", default="plain,mixed,extrap,learned,learned_always,ade,fft,tsc")
     ap.add_argument("--train-ng", type=int, default=128)
-    ap.add_argument("--train-seeds", default=",".join(str(10001 + i) for i in range(10)))
+    # the periodic phase of a 100-step 128^3 run holds 77 steps (154 solves):
+    # 13 runs give the 2000 pairs
+    ap.add_argument("--train-seeds", default=",".join(str(10001 + i) for i in range(13)))
     ap.add_argument("--train-schedule", type=int, default=100,
                     help="steps of the training runs' schedule (z_init -> 0)")
     ap.add_argument("--train-pairs", type=int, default=2000)
