@@ -582,6 +582,11 @@ k_interp_kick_drift(ParticleArgs pa, const double* __restrict__ phi, const float
         interp_g3<S>(g3, mm, c, g);
       else
         interp_g<S>(phi, mm, c, inv2h, g);
+      // finish all three sums here: otherwise the compiler sinks the sums of
+      // g[1], g[2] to the kick of their component and keeps every node's
+      // loaded force and weight live until then (TSC: 186 registers).  The
+      // empty asm only pins the three values to this point.
+      asm volatile("" : "+v"(g[0]), "+v"(g[1]), "+v"(g[2]));
       for (int d = 0; d < 3; ++d) {
         PT* p = (PT*)pa.p[d];
         const PT pn = (PT)((double)p_old[d] + g[d] * kick_coef);

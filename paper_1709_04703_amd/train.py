@@ -11,6 +11,8 @@ of the runs (the net pads periodically).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import _lib as L
@@ -79,16 +81,21 @@ class Trainer:
     def _prep(self, pair, kap, rms_r, rms_phi):
         L.net_prep(self.ng, pair[0], pair[1], 1.0 / rms_r, 1.0 / rms_phi, kap, self.act0)
 
-    def train(self, buf, kap, rms_r, rms_phi, iters: int, seed: int = 0, log_every: int = 0):
-        """Adam steps, one recorded pair each, drawn uniformly at random;
-        returns [(iteration, loss)] every log_every iterations."""
+    def train(self, buf, kap, rms_r, rms_phi, iters: int, seed: int = 0, log_every: int = 0,
+              cosine: bool = True):
+        """Adam steps, one recorded pair each, drawn uniformly at random, the
+        step size decaying from lr to 0 along half a cosine (cosine=False:
+        constant), so that the weights at the end are not one noisy
+        single-pair step away from where the loss is lowest; returns
+        [(iteration, loss)] every log_every iterations."""
         rng = np.random.Generator(np.random.PCG64(seed))
         losses = []
         for it in range(iters):
             q = int(rng.integers(0, buf.shape[0]))
             self._prep(buf[q], kap[q], rms_r[q], rms_phi[q])
             self.step_count += 1
-            L.net_train_step(self.ng, self.params, self.m1, self.m2, self.step_count, self.lr,
+            lr = self.lr * 0.5 * (1.0 + math.cos(math.pi * it / iters)) if cosine else self.lr
+            L.net_train_step(self.ng, self.params, self.m1, self.m2, self.step_count, lr,
                              self.act0, buf[q, 2], float(1.0 / rms_r[q]), self.scratch, self.loss)
             if log_every and (it % log_every == 0 or it == iters - 1):
                 losses.append((it, float(self.loss.item())))
