@@ -118,7 +118,11 @@ ROOFLINE_KERNEL = "smooth_color"
 
 def roofline_of(prof, prof_full=None, full_steps=0):
     """Roofline entry of ROOFLINE_KERNEL from the timed steps' events, plus
-    every kernel's time per step and rate from the fully profiled steps."""
+    every kernel's time per step and rate from the fully profiled steps
+    (None when the mode never launched that kernel, as the FFT and ADE
+    solvers do not)."""
+    if not prof.get(ROOFLINE_KERNEL, {}).get("launches"):
+        return None
     out = kernel_roofline(ROOFLINE_KERNEL, prof[ROOFLINE_KERNEL])
     if prof_full:
         out["largest_kernel_in_full_profile"] = max(prof_full, key=lambda k: prof_full[k]["ms"])
