@@ -5,7 +5,7 @@ Lambda-CDM Zel'dovich initial conditions at z = 49 (seed 512), steps of the
 200-step schedule uniform in a to z = 0, shrinking domain with the paper's
 reduced gravity speed, multigrid to 1e-8 relative residual.  A step is one
 sdpm_step (all of Table 2, lightcone elimination included) on inputs resident
-in HBM.  Three solver modes are timed on the same inputs, each to the same
+in HBM.  These modes are timed on the same inputs, each implicit one to the same
 1e-8 relative residual:
   plain:   FP64 V-cycles warm-started from the previous potential, FP64 momenta;
   mixed:   FP32 V(2,2) cycles (6 levels) inside FP64 defect correction, FP32
@@ -28,8 +28,8 @@ in HBM.  Three solver modes are timed on the same inputs, each to the same
            both ways).
 The net is trained once before the timed regions, on the GPU, on solves
 recorded (with the extrapolated start) from the periodic phase of 128^3 runs
-(2000 Mpc/h, z = 49 -> 0 in 100 steps, seeds 10001-10010: every solve, up to
-2000), and applied both at 512^3 (the learned modes above) and at 256^3
+(2000 Mpc/h, z = 49 -> 0 in 100 steps, seeds 10001-10013: every solve, the
+first 2000), and applied both at 512^3 (the learned modes above) and at 256^3
 (learned_transfer: seeds 20001-20003, steps 5-24 of the 100-step schedule,
 the extrapolated start with and without the learned guess).
 The shrinking phase of the same run (steps 160-164 by default: lightcone
@@ -575,8 +575,8 @@ def cpu_baseline(ics, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ng", type=int, default=512)
     ap.add_argument("--box", type=float, default=2000.0)
     ap.add_argument("--z-init", type=float, default=49.0)

@@ -130,7 +130,12 @@ def test_net_forward_matches_oracle():
     P.net_forward(n, torch.as_tensor(vec).cuda(), act0, a, b, out)
     err = rel_rms(out.cpu().numpy().reshape(n, n, n), ref)
     log(f"  net forward rel rms vs oracle = {err:.2e}")
-    assert err < 2e-2
+    # each layer's BF16 outputs may differ from the oracle's by one BF16 step
+    # (2^-8 relative) where the two FP32 sums straddle a rounding boundary,
+    # in under 1 % of them (the single-layer test): per layer at most
+    # sqrt(0.01) 2^-8 = 3.9e-4 relative RMS, over five layers at most 2e-3
+    # (measured 7.4e-4)
+    assert err < 2e-3
 
 
 def test_training_reduces_loss_on_one_sample():
