@@ -307,12 +307,15 @@ struct Profiler {
   size_t used = 0;
   std::vector<int> pend_id;
   std::vector<double> pend_bytes;
+  std::vector<int> pend_launches;
   double ms[K_NKERNELS] = {};
   double bytes[K_NKERNELS] = {};
   int64_t launches[K_NKERNELS] = {};
   void reset();
   void begin(hipStream_t st);
-  void end(hipStream_t st, int id, double bytes);
+  // closes the bracket opened by begin: `launches` launches of kernel id,
+  // together `bytes` algorithmic bytes
+  void end(hipStream_t st, int id, double bytes, int launches = 1);
   void collect();       // call after the stream has been synchronised
   void release();
 };
@@ -322,8 +325,8 @@ extern thread_local Profiler* g_prof;
 inline void prof_begin(hipStream_t st, int id) {
   if (g_prof && g_prof->wants(id)) g_prof->begin(st);
 }
-inline void prof_end(hipStream_t st, int id, double bytes) {
-  if (g_prof && g_prof->wants(id)) g_prof->end(st, id, bytes);
+inline void prof_end(hipStream_t st, int id, double bytes, int launches = 1) {
+  if (g_prof && g_prof->wants(id)) g_prof->end(st, id, bytes, launches);
 }
 
 }  // namespace sdpm

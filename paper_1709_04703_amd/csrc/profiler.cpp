@@ -17,6 +17,7 @@ void Profiler::reset() {
   used = 0;
   pend_id.clear();
   pend_bytes.clear();
+  pend_launches.clear();
   for (int k = 0; k < K_NKERNELS; ++k) {
     ms[k] = 0.0;
     bytes[k] = 0.0;
@@ -35,12 +36,13 @@ void Profiler::begin(hipStream_t st) {
   (void)hipEventRecord(ev[used], st);
 }
 
-void Profiler::end(hipStream_t st, int id, double b) {
+void Profiler::end(hipStream_t st, int id, double b, int nl) {
   if (used + 2 > ev.size()) return;
   (void)hipEventRecord(ev[used + 1], st);
   used += 2;
   pend_id.push_back(id);
   pend_bytes.push_back(b);
+  pend_launches.push_back(nl);
 }
 
 void Profiler::collect() {
@@ -49,12 +51,13 @@ void Profiler::collect() {
     if (hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]) == hipSuccess) {
       ms[pend_id[q]] += t;
       bytes[pend_id[q]] += pend_bytes[q];
-      launches[pend_id[q]] += 1;
+      launches[pend_id[q]] += pend_launches[q];
     }
   }
   used = 0;
   pend_id.clear();
   pend_bytes.clear();
+  pend_launches.clear();
 }
 
 void Profiler::release() {
