@@ -132,6 +132,47 @@ def test_shrinking_run_against_oracle(assignment):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_with_a_particle_outside_the_box(prec):
+    """A particle outside the frozen-exterior box: sdpm_step returns EDOMAIN
+    after the whole step.  That particle took the first drift only (Eq. 7;
+    momentum unchanged), every other particle the whole step (its final
+    position is the first drift followed by the second with its new momentum,
+    Eqs. 7-9, bit for bit; kicked), and the lightcone was not
+    applied (nothing removed, the box unchanged)."""
+    import paper_1709_04703_amd as P
+    from synth import clustered_particles
+    ng, box, n = 64, 640.0, 4000
+    cfg = lib_config(ng, box, shrink=1, n_initial=n, precision=prec, c_grav=0.0, sort_every=0)
+    x, p, ids = clustered_particles(n, box, 9, ng=ng, width_cells=1.0, lo=260.0, hi=380.0)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    sim.shrink_radius(150.0)
+    st0 = sim.state()
+    assert st0["periodic"] == 0 and st0["lo"][0] > 2
+    k = sim.n_active
+    sim.x[0, 0] = 5.0                          # far outside the box, on the low side
+    x0, p0, id0 = sim.particles()
+    x0, p0 = x0.astype(np.float64), p0.astype(np.float64)
+    a, da = 0.5, 0.01
+    st = sim.step(a, da, raise_on_error=False)
+    assert st["rc"] == P.SDPM_EDOMAIN
+    assert sim.n_active == k and st["n_removed"] == 0
+    st1 = sim.state()
+    assert list(st1["lo"]) == list(st0["lo"]) and list(st1["hi"]) == list(st0["hi"])
+    x1, p1, id1 = sim.particles()
+    assert np.array_equal(id1, id0)
+    x1, p1 = x1.astype(np.float64), p1.astype(np.float64)
+    c1 = 0.5 * st["dtau"] / a
+    c2 = 0.5 * st["dtau"] / (a + da)
+    first = x0 + p0 * c1
+    assert np.array_equal(x1[0], first[0]) and np.array_equal(p1[0], p0[0])
+    assert np.array_equal(x1[1:], first[1:] + p1[1:] * c2)
+    assert np.mean(np.any(p1[1:] != p0[1:], axis=1)) > 0.9      # kicked
+    log(f"domain error in step, precision {prec}: bad particle first drift only, {k - 1} stepped")
+    sim.close()
+
+
 def test_empty_particle_set_steps():
     ng, box = 16, 100.0
     cfg = lib_config(ng, box, c_grav=-1.0, n_initial=10)
