@@ -30,6 +30,11 @@ struct sdpm_ctx {
   uint32_t* boffsets = nullptr;
   void* scratch = nullptr;
   void* sort_scratch = nullptr;
+  // first sorted index of each re-sort block (block deposit), valid while
+  // the active count is the one it was built for (any positions: particles
+  // outside their block's window go to global atomics)
+  int64_t* blk_start = nullptr;
+  int64_t blk_n = -1;
   float* gmesh = nullptr;       // FP32 force mesh (mixed precision)
   FftPlan fft;                  // periodic FFT solver (SDPM_SOLVER_FFT)
   void* fft_work = nullptr;
@@ -217,6 +222,11 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   uint32_t* bo = (uint32_t*)take(nb * sizeof(uint32_t));
   void* scr = take((size_t)capacity * (3 * sizeof(double) + 3 * p_elem(c) + sizeof(uint32_t)));
   void* sscr = c.sort_every > 0 ? take(sort_scratch_bytes(capacity)) : nullptr;
+  int64_t* bst = nullptr;
+  if (c.sort_every > 0 && block_deposit_ok(c.ng, c.sort_shift)) {
+    const int64_t nb1 = c.ng >> kBlkShift;
+    bst = (int64_t*)take((size_t)(nb1 * nb1 * nb1 + 1) * sizeof(int64_t));
+  }
   // FP32 force mesh of the mixed-precision step (3 values per cell)
   float* g3 = c.precision == SDPM_MIXED ? (float*)take((size_t)c.ng * c.ng * c.ng * 3 * sizeof(float))
                                         : nullptr;
@@ -262,6 +272,7 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
   }
   if (ctx) {
     ctx->sort_scratch = sscr;
+    ctx->blk_start = bst;
     ctx->gmesh = g3;
     ctx->partial = partial;
     ctx->dscal = dscal;
@@ -737,10 +748,22 @@ int deposit(sdpm_ctx* c, double drift_coef, int drift) {
   c->counts_box = c->periodic ? full_box(c->cfg.ng) : c->box;
   const ParticleArgs pa = particle_args(c);
   const MeshMap mm = mesh_map(c);
-  if (c->cfg.precision == SDPM_MIXED)
+  // after a re-sort (and until particles are removed): one workgroup per
+  // block with a fixed window; otherwise windows from each workgroup's
+  // bounding box
+  const bool blocks = c->blk_start && c->blk_n == c->n_active && c->n_active > 0;
+  if (blocks) {
+    if (c->cfg.precision == SDPM_MIXED)
+      launch_block_deposit<float>(pa, drift_coef, drift, mm, c->blk_start, c->fields.counts,
+                                  c->dflags, c->st);
+    else
+      launch_block_deposit<double>(pa, drift_coef, drift, mm, c->blk_start, c->fields.counts,
+                                   c->dflags, c->st);
+  } else if (c->cfg.precision == SDPM_MIXED) {
     launch_drift_deposit<float>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
-  else
+  } else {
     launch_drift_deposit<double>(pa, drift_coef, drift, mm, c->fields.counts, c->dflags, c->st);
+  }
   return SDPM_OK;
 }
 
@@ -797,6 +820,7 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
       if (cnt < *n_removed) full = SDPM_EFULL;
     }
     c->n_active = kept;
+    c->blk_n = -1;
   }
   Box nb;
   int per = 1;
@@ -825,10 +849,11 @@ void sort_particles(sdpm_ctx* c) {
   const ParticleArgs pa = particle_args(c);
   if (c->cfg.precision == SDPM_MIXED)
     launch_morton_sort<float>(pa, c->cfg.ng, c->cfg.box, c->cfg.sort_shift, c->sort_scratch,
-                              c->scratch, c->st);
+                              c->scratch, c->blk_start, c->st);
   else
     launch_morton_sort<double>(pa, c->cfg.ng, c->cfg.box, c->cfg.sort_shift, c->sort_scratch,
-                               c->scratch, c->st);
+                               c->scratch, c->blk_start, c->st);
+  c->blk_n = c->blk_start ? c->n_active : -1;
 }
 
 void fill_state(sdpm_ctx* c, sdpm_step_stats* o) {
@@ -1019,6 +1044,7 @@ int sdpm_bind(sdpm_ctx* c, const sdpm_particles* parts, const sdpm_fields* field
   c->parts = *parts;
   c->fields = *fields;
   c->n_active = n_active;
+  c->blk_n = -1;
   c->periodic = 1;
   c->box = full_box(c->cfg.ng);
   c->counts_box = full_box(c->cfg.ng);

@@ -240,11 +240,25 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
                     hipStream_t st);
 
 // Morton re-sort (sort.hip): sort_scratch holds sort_scratch_bytes(capacity),
-// particle_scratch one particle set.
+// particle_scratch one particle set.  block_start (optional, (ng >> shift)^3
+// + 1 entries): the first sorted index of each block in Morton order, the
+// last entry n.
 size_t sort_scratch_bytes(int64_t capacity);
 template <typename PT>
 void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, void* sort_scratch,
-                        void* particle_scratch, hipStream_t st);
+                        void* particle_scratch, int64_t* block_start, hipStream_t st);
+
+// The deposit after a re-sort into blocks of kBlkCells^3 cells: one
+// workgroup per block (launch_block_deposit, particles.hip), usable while the
+// particles keep the sorted order and count of block_start.
+constexpr int kBlkShift = 4, kBlkCells = 1 << kBlkShift;
+inline bool block_deposit_ok(int ng, int sort_shift) {
+  return sort_shift == kBlkShift && ng >= 4 * kBlkCells;
+}
+template <typename PT>
+void launch_block_deposit(const ParticleArgs& pa, double drift_coef, int drift, const MeshMap& mm,
+                          const int64_t* block_start, uint64_t* counts, uint32_t* flags,
+                          hipStream_t st);
 
 // Learned warm start (net.hip).
 constexpr int kNetParams = 5 * (27 * 16 * 16 + 16);

@@ -794,6 +794,117 @@ k_scatter(ParticleArgs pa, double o0, double o1, double o2, double r2,
   }
 }
 
+// Deposit right after a re-sort into blocks of kBlkCells^3 cells: the
+// particles of a block are contiguous (block_start, in the blocks' Morton
+// order), and one workgroup of 1024 threads takes one block.  Its LDS window
+// is fixed in advance: the block, kBlkMargin<S> cells of drift on each side,
+// and the reach of the S^3 stencil; a particle whose nodes leave it (one
+// that drifted further since the sort) goes to global atomics, so every
+// routing gives the same integer sums.  Windows of neighbouring blocks
+// overlap only in those margins, and no workgroup needs a bounding box
+// (reductions, barriers) or straddles two blocks.
+template <int S>
+struct BlkWin {
+  static constexpr int M = S == 2 ? 2 : 1;                  // drift margin, cells
+  static constexpr int W = kBlkCells + 2 * M + 2 * S - 3;   // 21 for both stencils
+  static constexpr int L = M + S - 2;                       // window start below the block
+};
+
+__device__ inline uint32_t compact3(uint32_t v) {
+  // the inverse of spread3 on every third bit
+  v &= 0x49249249;
+  v = (v | (v >> 2)) & 0x430c30c3;
+  v = (v | (v >> 4)) & 0x0700f00f;
+  v = (v | (v >> 8)) & 0x070000ff;
+  v = (v | (v >> 16)) & 0x7ff;
+  return v;
+}
+
+template <typename PT, bool DRIFT, int S>
+__global__ void __launch_bounds__(1024)
+k_block_deposit(ParticleArgs pa, double coef, MeshMap mm, const int64_t* __restrict__ start,
+                unsigned long long* __restrict__ counts, uint32_t* __restrict__ flags) {
+  constexpr int W = BlkWin<S>::W;
+  __shared__ unsigned long long acc[W * W * W];
+  const int64_t b = xcd_block();
+  const int64_t s0 = start[b], s1 = start[b + 1];
+  if (s0 >= s1) return;                        // an empty block (uniform)
+  const uint32_t mb = (uint32_t)b;
+  const int lo0 = (int)compact3(mb) * kBlkCells - BlkWin<S>::L;
+  const int lo1 = (int)compact3(mb >> 1) * kBlkCells - BlkWin<S>::L;
+  const int lo2 = (int)compact3(mb >> 2) * kBlkCells - BlkWin<S>::L;
+  for (int q = threadIdx.x; q < W * W * W; q += 1024) acc[q] = 0ull;
+  __syncthreads();
+  const int m = mm.ng - 1, half = mm.ng >> 1;
+  uint32_t bad_all = 0;
+  for (int64_t i = s0 + threadIdx.x; i < s1; i += 1024) {
+    double x[3];
+    for (int d = 0; d < 3; ++d) {
+      double v = __builtin_nontemporal_load(pa.x[d] + i);
+      if (DRIFT) v = drift_wrap(v, (double)__builtin_nontemporal_load((const PT*)pa.p[d] + i), coef, mm);
+      x[d] = v;
+    }
+    Frac c;
+    const uint32_t bad = assign_frac<S>(x, mm, c);
+    if (bad) {
+      bad_all |= bad;
+      continue;
+    }
+    uint64_t wt[3][S];
+    for (int d = 0; d < 3; ++d) axis_weights<S>(c.f[d], mm.frac_bits, wt[d]);
+    int r0 = c.cell[0] - lo0, r1 = c.cell[1] - lo1, r2 = c.cell[2] - lo2;
+    if (mm.periodic) {
+      r0 = ((r0 + half) & m) - half;
+      r1 = ((r1 + half) & m) - half;
+      r2 = ((r2 + half) & m) - half;
+    }
+    if ((unsigned)r0 <= (unsigned)(W - S) && (unsigned)r1 <= (unsigned)(W - S) &&
+        (unsigned)r2 <= (unsigned)(W - S)) {
+      for (int dz = 0; dz < S; ++dz)
+        for (int dy = 0; dy < S; ++dy) {
+          const uint64_t wyz = wt[1][dy] * wt[2][dz];
+          if (wyz == 0) continue;
+          const int row = ((r2 + dz) * W + r1 + dy) * W + r0;
+          for (int dx = 0; dx < S; ++dx) {
+            const uint64_t wgt = wt[0][dx] * wyz;
+            if (wgt) atomicAdd(&acc[row + dx], (unsigned long long)wgt);
+          }
+        }
+    } else {
+      for (int dz = 0; dz < S; ++dz) {
+        int kk = c.cell[2] + dz;
+        if (mm.periodic) kk &= m;
+        for (int dy = 0; dy < S; ++dy) {
+          int jj = c.cell[1] + dy;
+          if (mm.periodic) jj &= m;
+          const uint64_t wyz = wt[1][dy] * wt[2][dz];
+          if (wyz == 0) continue;
+          for (int dx = 0; dx < S; ++dx) {
+            const uint64_t wgt = wt[0][dx] * wyz;
+            if (wgt == 0) continue;
+            int ii = c.cell[0] + dx;
+            if (mm.periodic) ii &= m;
+            atomicAdd(counts + lin(ii, jj, kk, mm.ng), (unsigned long long)wgt);
+          }
+        }
+      }
+    }
+  }
+  if (bad_all) atomicOr(flags, bad_all);
+  __syncthreads();
+  for (int q = threadIdx.x; q < W * W * W; q += 1024) {
+    const unsigned long long v = acc[q];
+    if (!v) continue;
+    int gx = lo0 + q % W, gy = lo1 + (q / W) % W, gz = lo2 + q / (W * W);
+    if (mm.periodic) {
+      gx &= m;
+      gy &= m;
+      gz &= m;
+    }
+    atomicAdd(counts + lin(gx, gy, gz, mm.ng), v);
+  }
+}
+
 inline unsigned grid_for(int64_t n, int per_block) {
   return (unsigned)((n + per_block - 1) / per_block);
 }
@@ -821,6 +932,33 @@ void launch_drift_deposit(const ParticleArgs& pa, double drift_coef, int drift,
   const double per = drift ? 24.0 + 3.0 * sizeof(PT) : 24.0;
   prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
 }
+
+template <typename PT>
+void launch_block_deposit(const ParticleArgs& pa, double drift_coef, int drift, const MeshMap& mm,
+                          const int64_t* block_start, uint64_t* counts, uint32_t* flags,
+                          hipStream_t st) {
+  if (pa.n <= 0) return;
+  const int64_t nb1 = mm.ng >> kBlkShift;
+  const dim3 g((unsigned)(nb1 * nb1 * nb1));
+  unsigned long long* cu = (unsigned long long*)counts;
+  prof_begin(st, K_DEPOSIT);
+#define SDPM_BDEP(D, S)                                                                         \
+  hipLaunchKernelGGL((k_block_deposit<PT, D, S>), g, dim3(1024), 0, st, pa, drift_coef, mm,      \
+                     block_start, cu, flags)
+  if (mm.tsc) {
+    if (drift) SDPM_BDEP(true, 3); else SDPM_BDEP(false, 3);
+  } else {
+    if (drift) SDPM_BDEP(true, 2); else SDPM_BDEP(false, 2);
+  }
+#undef SDPM_BDEP
+  // the same algorithmic bytes as launch_drift_deposit
+  const double per = drift ? 24.0 + 3.0 * sizeof(PT) : 24.0;
+  prof_end(st, K_DEPOSIT, per * pa.n + 8.0 * box_cells(mm.active));
+}
+template void launch_block_deposit<float>(const ParticleArgs&, double, int, const MeshMap&,
+                                          const int64_t*, uint64_t*, uint32_t*, hipStream_t);
+template void launch_block_deposit<double>(const ParticleArgs&, double, int, const MeshMap&,
+                                           const int64_t*, uint64_t*, uint32_t*, hipStream_t);
 
 template void launch_drift_deposit<float>(const ParticleArgs&, double, int, const MeshMap&,
                                           uint64_t*, uint32_t*, hipStream_t);

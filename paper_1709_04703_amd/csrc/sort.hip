@@ -51,6 +51,29 @@ k_morton_keys(const double* __restrict__ x0, const double* __restrict__ x1,
   val[q] = (uint32_t)q;
 }
 
+// First sorted index of each block (Morton index m): the lower bound of its
+// first key m << 2 shift in the sorted keys; start[nblk] = n.
+__global__ void __launch_bounds__(256)
+k_block_starts(const uint32_t* __restrict__ key, int64_t n, int shift, int64_t nblk,
+               int64_t* __restrict__ start) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m > nblk) return;
+  if (m == nblk) {
+    start[m] = n;
+    return;
+  }
+  const uint32_t target = (uint32_t)m << (2 * shift);
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (key[mid] < target)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[m] = lo;
+}
+
 __global__ void __launch_bounds__(256)
 k_radix_hist(const uint32_t* __restrict__ key, int64_t n, int bit, int nblocks,
              uint32_t* __restrict__ hist) {
@@ -209,7 +232,7 @@ size_t sort_scratch_bytes(int64_t capacity) {
 
 template <typename PT>
 void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, void* sort_scratch,
-                        void* particle_scratch, hipStream_t st) {
+                        void* particle_scratch, int64_t* block_start, hipStream_t st) {
   const int64_t n = pa.n;
   if (n <= 1) return;
   const int64_t nb = (n + kChunk - 1) / kChunk;
@@ -235,6 +258,11 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
     std::swap(k0, k1);
     std::swap(v0, v1);
   }
+  if (block_start) {
+    const int64_t nb1 = ng >> shift, nblk = nb1 * nb1 * nb1;
+    hipLaunchKernelGGL(k_block_starts, dim3((unsigned)((nblk + 256) / 256)), dim3(256), 0, st, k0, n,
+                       shift, nblk, block_start);
+  }
   const int passes = (bits + 7) / 8;
   prof_end(st, K_SORT, (double)n * (8.0 + passes * (4.0 + 16.0)));
   char* s = (char*)particle_scratch;
@@ -259,8 +287,8 @@ void launch_morton_sort(const ParticleArgs& pa, int ng, double box, int shift, v
   prof_end(st, K_COPY, 2.0 * pbytes);
 }
 template void launch_morton_sort<float>(const ParticleArgs&, int, double, int, void*, void*,
-                                        hipStream_t);
+                                        int64_t*, hipStream_t);
 template void launch_morton_sort<double>(const ParticleArgs&, int, double, int, void*, void*,
-                                         hipStream_t);
+                                         int64_t*, hipStream_t);
 
 }  // namespace sdpm

@@ -246,6 +246,55 @@ def test_deposit_exact_when_particles_fill_their_sort_blocks():
 
 @pytest.mark.parametrize("assignment", [0, 1])
 @pytest.mark.parametrize("periodic", [True, False])
+def test_block_deposit_after_sort_exact(assignment, periodic):
+    """After a re-sort the deposit runs one workgroup per 16^3-cell block with
+    a fixed window (the block, its drift margin, the stencil's reach): the
+    counts equal the oracle's deposit, bit for bit, for uniform and clustered
+    particles across the periodic wrap, again after a tenth of them moved 5
+    cells (beyond the margin: global atomics) without a new sort, and in a
+    frozen-exterior box."""
+    import torch
+    ng, box = 64, 640.0
+    h = box / ng
+    xu, pu, _ = uniform_particles(12000, box, 31)
+    xc, pc, _ = clustered_particles(8000, box, 32, ng=ng, width_cells=1.0)
+    x = np.concatenate([xu, xc])
+    p = np.concatenate([pu, pc])
+    n = x.shape[0]
+    ids = np.arange(n, dtype=np.uint32)
+    kind = "tsc" if assignment else "cic"
+    cfg = lib_config(ng, box, shrink=1, n_initial=n, assignment=assignment, sort_every=10)
+    sim = make_sim(cfg, n)
+    sim.bind(x, p, ids)
+    if not periodic:
+        sim.shrink_radius(150.0)
+        assert sim.state()["periodic"] == 0
+    sim.sort()
+    k = sim.n_active
+    log(f"block deposit {kind} periodic={periodic} n={k}")
+    sim.deposit()
+    gx, _, _ = sim.particles()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(gx, ng, box, B, periodic, kind))
+    # move every tenth particle 5 cells along each axis (towards the observer
+    # in the box, so that it stays inside it); the order and count are kept
+    rng = np.random.Generator(np.random.PCG64(33))
+    sel = np.arange(0, k, 10)
+    step = 5.0 * h * np.where(rng.uniform(size=(sel.size, 3)) < 0.5, -1.0, 1.0)
+    if not periodic:
+        step = 5.0 * h * np.sign(np.asarray(cfg.x_obs) - gx[sel])
+    moved = gx.copy()
+    moved[sel] = gx[sel] + step
+    if periodic:
+        moved = np.mod(moved, box)
+        moved[moved >= box] = 0.0
+    sim.x[:, :k] = torch.as_tensor(moved.T.copy()).to(sim.x.device)
+    sim.deposit()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(moved, ng, box, B, periodic, kind))
+    sim.close()
+
+
+@pytest.mark.parametrize("assignment", [0, 1])
+@pytest.mark.parametrize("periodic", [True, False])
 def test_deposit_exact_with_one_far_outlier_per_workgroup(assignment, periodic):
     """A lattice in memory order (each deposit workgroup of 1024 particles
     covers a compact slab) with one particle per 1024 moved far away, and a
