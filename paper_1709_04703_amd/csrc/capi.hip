@@ -788,10 +788,16 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
   const double r2 = r * r;
   if (n > 0 && r < corner_distance(c->cfg) * (1.0 + 1e-12) && known_removed != 0) {
     const ParticleArgs pa = particle_args(c);
+    // the block deposit's table follows the stable compaction
+    const bool blk = c->blk_start && c->blk_n == n;
+    const int64_t nb1 = c->cfg.ng >> kBlkShift;
+    int64_t* bst = blk ? c->blk_start : nullptr;
     if (c->cfg.precision == SDPM_MIXED)
-      launch_compact<float>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept, c->st);
+      launch_compact<float>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept,
+                            bst, nb1 * nb1 * nb1, c->st);
     else
-      launch_compact<double>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept, c->st);
+      launch_compact<double>(pa, c->cfg.x_obs, r2, c->scratch, c->bcounts, c->boffsets, c->dkept,
+                             bst, nb1 * nb1 * nb1, c->st);
     HIP_TRY(c, hipMemcpyAsync(c->hpin + 20, c->dkept, sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(c, hipStreamSynchronize(c->st));
     if (c->prof.on) c->prof.collect();
@@ -820,7 +826,7 @@ int shrink_impl(sdpm_ctx* c, double r, int64_t known_removed, int64_t* n_removed
       if (cnt < *n_removed) full = SDPM_EFULL;
     }
     c->n_active = kept;
-    c->blk_n = -1;
+    c->blk_n = blk ? kept : -1;
   }
   Box nb;
   int per = 1;

@@ -234,10 +234,12 @@ void launch_interp_force(const ParticleArgs& pa, const double* phi, const MeshMa
                          hipStream_t st);
 // Stable partition of the first n particles: kept (d^2 <= r2) first.
 // scratch must hold n particles; counts/offsets hold ceil(n / kChunk) entries.
+// block_start (optional): the block deposit's table of nblk + 1 first
+// indices, carried over to the compacted order.
 template <typename PT>
 void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
                     uint32_t* block_counts, uint32_t* block_offsets, uint64_t* kept_total,
-                    hipStream_t st);
+                    int64_t* block_start, int64_t nblk, hipStream_t st);
 
 // Morton re-sort (sort.hip): sort_scratch holds sort_scratch_bytes(capacity),
 // particle_scratch one particle set.  block_start (optional, (ng >> shift)^3

@@ -714,6 +714,32 @@ k_count_kept(ParticleArgs pa, double o0, double o1, double o2, double r2,
   if (tid == 0) block_counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+// The block-start table of the block deposit after a stable compaction: a
+// block's first index becomes the number of kept particles before it, the
+// kept count of the whole chunks before it plus those kept in its chunk ahead
+// of it (the same FP64 predicate as k_count_kept, one wave per block).  Runs
+// before the particles move; each wave reads and writes its own entry only.
+__global__ void __launch_bounds__(64)
+k_block_starts_compact(ParticleArgs pa, double o0, double o1, double o2, double r2,
+                       const uint32_t* __restrict__ offsets, const uint64_t* __restrict__ kept_total,
+                       int64_t nblk, int64_t* __restrict__ start) {
+  const int64_t m = blockIdx.x;
+  if (m > nblk) return;
+  const int64_t s0 = start[m];
+  if (s0 >= pa.n) {
+    if (threadIdx.x == 0) start[m] = (int64_t)*kept_total;
+    return;
+  }
+  const int64_t c0 = (s0 / kChunk) * kChunk;
+  uint64_t kept = 0;
+  for (int64_t i0 = c0; i0 < s0; i0 += 64) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool keep = i < s0 && !(dist2_nofma(pa.x[0][i], pa.x[1][i], pa.x[2][i], o0, o1, o2) > r2);
+    kept += (uint64_t)__popcll(__ballot(keep));
+  }
+  if (threadIdx.x == 0) start[m] = (int64_t)offsets[s0 / kChunk] + (int64_t)kept;
+}
+
 // Exclusive scan of nb block counts by one workgroup; total to *kept_total.
 __global__ void __launch_bounds__(1024)
 k_scan_counts(const uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets, int64_t nb,
@@ -1061,7 +1087,7 @@ template void launch_lc_cross<double>(const ParticleArgs&, const double*, double
 template <typename PT>
 void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void* scratch,
                     uint32_t* block_counts, uint32_t* block_offsets, uint64_t* kept_total,
-                    hipStream_t st) {
+                    int64_t* block_start, int64_t nblk, hipStream_t st) {
   if (pa.n <= 0) return;
   const int64_t nb = (pa.n + kChunk - 1) / kChunk;
   prof_begin(st, K_COUNT_KEPT);
@@ -1072,6 +1098,10 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, block_counts, block_offsets, nb,
                      kept_total);
   prof_end(st, K_SCAN, 8.0 * nb);
+  if (block_start)
+    hipLaunchKernelGGL(k_block_starts_compact, dim3((unsigned)(nblk + 1)), dim3(64), 0, st, pa,
+                       x_obs[0], x_obs[1], x_obs[2], r2, block_offsets, kept_total, nblk,
+                       block_start);
   char* s = (char*)scratch;
   const size_t n = (size_t)pa.n;
   double* sx0 = (double*)s;
@@ -1095,8 +1125,8 @@ void launch_compact(const ParticleArgs& pa, const double* x_obs, double r2, void
   prof_end(st, K_COPY, 2.0 * pbytes);
 }
 template void launch_compact<float>(const ParticleArgs&, const double*, double, void*, uint32_t*,
-                                    uint32_t*, uint64_t*, hipStream_t);
+                                    uint32_t*, uint64_t*, int64_t*, int64_t, hipStream_t);
 template void launch_compact<double>(const ParticleArgs&, const double*, double, void*, uint32_t*,
-                                     uint32_t*, uint64_t*, hipStream_t);
+                                     uint32_t*, uint64_t*, int64_t*, int64_t, hipStream_t);
 
 }  // namespace sdpm

@@ -251,8 +251,8 @@ def test_block_deposit_after_sort_exact(assignment, periodic):
     a fixed window (the block, its drift margin, the stencil's reach): the
     counts equal the oracle's deposit, bit for bit, for uniform and clustered
     particles across the periodic wrap, again after a tenth of them moved 5
-    cells (beyond the margin: global atomics) without a new sort, and in a
-    frozen-exterior box."""
+    cells (beyond the margin: global atomics) without a new sort, in a
+    frozen-exterior box, and after a removal compacted the particles."""
     import torch
     ng, box = 64, 640.0
     h = box / ng
@@ -290,6 +290,12 @@ def test_block_deposit_after_sort_exact(assignment, periodic):
     sim.x[:, :k] = torch.as_tensor(moved.T.copy()).to(sim.x.device)
     sim.deposit()
     assert np.array_equal(sim.counts_numpy(), pm.deposit(moved, ng, box, B, periodic, kind))
+    # a removal compacts the particles (stable): the block table follows it
+    nr = sim.shrink_radius(120.0)
+    assert nr > 0 and sim.n_active == k - nr
+    sim.deposit()
+    gx2, _, _ = sim.particles()
+    assert np.array_equal(sim.counts_numpy(), pm.deposit(gx2, ng, box, B, False, kind))
     sim.close()
 
 
