@@ -601,7 +601,12 @@ def main():
                     help="untimed steps after the timed ones with every kernel profiled")
     ap.add_argument("--cycles-per-outer", type=int, default=4, choices=(1, 2, 3, 4),
                     help="V-cycles per FP64 defect-correction iteration, at most")
-    ap.add_argument("--sort-every", type=int, default=10)
+    # re-sort period: the block deposit keeps the particles of a block in a
+    # window with a drift margin and routes the rest to global atomics, so
+    # a sort (~10 ms at 512^3) pays back only every ~20 steps (measured over
+    # steps 5-44: 25.5 / 24.5 / 24.1 / 23.8 ms per step for 5 / 10 / 20 / 40;
+    # over steps 100-139: 31.5 / 31.0 / 30.9 ms for 10 / 20 / 40)
+    ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--sort-shift", type=int, default=4,
                     help="Morton key of cell blocks of 2^shift cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -776,7 +781,8 @@ def main():
                          f"z={args.z_init:g}->0 in {args.schedule} steps (steps "
                          f"{args.warmup}..{args.warmup + args.steps - 1} timed), shrinking "
                          "domain, c_eff = 0.019 h c, multigrid V(2,2) (up to 6 levels, up to 4 "
-                         "cycles per FP64 defect correction) to 1e-8"),
+                         "cycles per FP64 defect correction) to 1e-8, particles re-sorted every "
+                         f"{args.sort_every} steps"),
             "global_batch": int(ics[0].shape[0]),
             "parallelism": "single GPU",
             "mode": head_mode,
