@@ -342,6 +342,24 @@ int sdpm_solve(sdpm_ctx* ctx, double kappa_h2, double s_h2_factor, sdpm_step_sta
  * launch per diagonal of rows (ny + nz - 1 launches).  SDPM_EINVAL for lam
  * not finite and positive.                                                  */
 int sdpm_ade_sweep(sdpm_ctx* ctx, double lam, int forward);
+/* The multigrid smoother of the implicit solve (Sec. 2.1 Eq. 4) on one
+ * periodic FP32 level: four red-black Gauss-Seidel half sweeps (red, black,
+ * red, black) of (Lap - kappa) e = scale r in colour-split storage (the
+ * n^3/2 red cells, (i+j+k) even, first, then the black ones, each in
+ * (k, j, i >> 1) row order), each cell set to
+ *   e = (sum of its 6 neighbours - scale r) * inv_diag
+ * with inv_diag = 1 / (6 + kappa h^2 scale).  first != 0: the red sweep
+ * starts from e = 0 (e is not read and may be NULL).  fused != 0: one
+ * z-marching pass that keeps the sweeps' planes in LDS (what the V-cycle
+ * runs on levels of at least 256^3 cells), reading e and writing e_out,
+ * which must differ unless first; fused == 0: e copied to e_out (unless
+ * first or the same) and four single-colour launches in place on e_out.
+ * Both forms give bit-identical e_out.  n: power of two in [64, 2048]; all
+ * arrays device memory of n^3 floats; runs on stream (hipStream_t, NULL =
+ * default), asynchronously.  SDPM_EINVAL for other sizes, NULL pointers or
+ * e == e_out with fused and not first.                                     */
+int sdpm_rb_sweeps(int32_t n, const float* e, float* e_out, const float* r, float scale,
+                   float inv_diag, int32_t first, int32_t fused, void* stream);
 /* Re-sort of the active particles (all SoA arrays permuted together by the
  * key of sort_shift: the Morton code of the cell's block, then its row
  * inside the block; stable LSD radix sort).  Results of the step do not

@@ -39,6 +39,7 @@ EXPORTS = [
     "sdpm_net_forward_noalloc", "sdpm_net_train_step", "sdpm_record", "sdpm_record_info", "sdpm_profile", "sdpm_profile_read",
     "sdpm_destroy", "sdpm_last_error", "sdpm_set_lightcone", "sdpm_lightcone_count",
     "sdpm_ade_sweep", "sdpm_pk_workspace_bytes", "sdpm_power_spectrum", "sdpm_profile_kernels",
+    "sdpm_rb_sweeps",
 ]
 NET_PARAMS = 5 * (27 * 16 * 16 + 16)
 CONV_RELU, CONV_OUT_FP32_CH0, CONV_BACKWARD_DATA, CONV_MASK = 1, 2, 4, 8
@@ -159,6 +160,7 @@ def library() -> ctypes.CDLL:
         "sdpm_set_lightcone": [vp, P(Lightcone)],
         "sdpm_lightcone_count": [vp, P(i64)],
         "sdpm_ade_sweep": [vp, dbl, i32],
+        "sdpm_rb_sweeps": [i32, vp, vp, vp, ctypes.c_float, ctypes.c_float, i32, i32, vp],
         "sdpm_pk_workspace_bytes": [i32, P(i64)],
         "sdpm_power_spectrum": [P(vp), i64, dbl, i32, i32, vp, i64, vp, P(dbl), P(dbl), P(dbl),
                                 P(i64)],
@@ -238,6 +240,14 @@ def conv3d(n, inp, w, bias, flags, mask, out):
     """One convolution layer (see sdpm_conv3d); torch device tensors."""
     check(library().sdpm_conv3d(n, _ptr(inp), _ptr(w), _ptr(bias), flags, _ptr(mask), _ptr(out),
                                 _stream()))
+
+
+def rb_sweeps(n, e, e_out, r, scale: float, inv_diag: float, first: bool, fused: bool):
+    """Four red-black half sweeps on a periodic FP32 level in colour-split
+    storage (see sdpm_rb_sweeps); torch device tensors of n^3 floats (e may
+    be None when first)."""
+    check(library().sdpm_rb_sweeps(n, _ptr(e), _ptr(e_out), _ptr(r), scale, inv_diag,
+                                   1 if first else 0, 1 if fused else 0, _stream()))
 
 
 def pk_workspace_bytes(ng: int) -> int:

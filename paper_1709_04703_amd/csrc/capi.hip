@@ -200,11 +200,13 @@ size_t carve(const sdpm_config& c, int64_t capacity, char* base, sdpm_ctx* ctx) 
     char* e = take(cells * el);
     char* r = take(cells * el);
     char* t = take(cells * el);
+    char* e_alt = el == 4 && n >= kSweep4Min ? take(cells * el) : nullptr;
     if (ctx) {
       ctx->lv[l].n = n;
       ctx->lv[l].e = e;
       ctx->lv[l].r = r;
       ctx->lv[l].t = t;
+      ctx->lv[l].e_alt = e_alt;
       ctx->lv[l].box = full_box(n);
     }
   }
@@ -1439,6 +1441,16 @@ int sdpm_conv3d(int32_t n, const void* in_bf16, const float* w, const float* bia
   launch_conv(n, (const uint16_t*)in_bf16, w, bias, flags, (const uint16_t*)mask_bf16, out,
               (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "conv3d launch failed");
+}
+
+int sdpm_rb_sweeps(int32_t n, const float* e, float* e_out, const float* r, float scale,
+                   float inv_diag, int32_t first, int32_t fused, void* stream) {
+  if (n < 64 || n > 2048 || (n & (n - 1)) || !e_out || !r || (!first && !e))
+    return fail(nullptr, SDPM_EINVAL, "rb_sweeps: n a power of two in [64, 2048], pointers non-NULL");
+  if (fused && !first && e == e_out)
+    return fail(nullptr, SDPM_EINVAL, "rb_sweeps: the fused form needs e_out != e");
+  launch_sweeps4(e, e_out, r, n, scale, inv_diag, first != 0, fused != 0, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "rb_sweeps launch failed");
 }
 
 int sdpm_pk_workspace_bytes(int32_t ng, int64_t* bytes) {

@@ -85,6 +85,9 @@ struct Level {
   void* e;    // correction     } all three stored split by colour:
   void* r;    // right-hand side } red cells ((i+j+k) even) first, then black,
   void* t;    // residual        } each in row order with x index i >> 1
+  void* e_alt;  // second correction array of the fused sweeps (FP32 levels of
+                // at least kSweep4Min cells a side; else null): they read one
+                // and write the other, and the two swap
 };
 
 // ---------------------------------------------------------------------------
@@ -163,10 +166,21 @@ void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool pe
                       bool forward, hipStream_t st);
 // One V-cycle for A_0 e = r_0; returns the level-0 buffer holding e.  With
 // fine_start the cycle improves the e already on level 0 (a further cycle on
-// the same r_0), else it starts from e = 0.
+// the same r_0), else it starts from e = 0.  Levels with the fused sweeps
+// swap e and e_alt.
 template <typename T>
-const T* vcycle(const Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
+const T* vcycle(Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
                 bool periodic, bool fine_start, hipStream_t st);
+// Whether a level of n cells a side takes the fused four-sweep kernel when
+// periodic (FP32 only; smaller levels run too few workgroups for it).
+constexpr int kSweep4Min = 256;
+// Four colour sweeps (red, black, red, black) of a periodic FP32 level of
+// n^3 cells, n a power of two >= 64: with fused, one k_sweep4 pass from e
+// (black colour; not read when first) into e_out (e_out == e allowed only
+// when first); otherwise e copied to e_out (not when first) and four
+// k_smooth_color_v4 launches in place on e_out.
+void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
+                    bool first, bool fused, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Launchers, particle kernels (particles.hip).
@@ -309,7 +323,7 @@ enum KernelId : int {
   K_SMOOTH_FIRST, K_SMOOTH, K_RESID_LEVEL, K_RESTRICT, K_PROLONG, K_COARSE,
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
-  K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK,
+  K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK, K_SWEEP4,
   K_NKERNELS
 };
 static_assert(K_NKERNELS <= 64, "the profiler's kernel mask holds 64 kernels");

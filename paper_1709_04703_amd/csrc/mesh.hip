@@ -645,6 +645,162 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
   }
 }
 
+// Four colour sweeps (red, black, red, black) of a periodic FP32 level in
+// one pass, with the arithmetic of four k_smooth_color_v4 launches (same
+// operands, same order: bit-identical results).  Four separate sweeps move
+// 24 bytes per cell (each half sweep reads the other colour and its own r,
+// writes its own colour); here each cell's r and input black value are read
+// once and its final red and black values written once: 10 bytes per cell
+// (8 with the zero initial guess, which reads no e).
+//
+// Each workgroup marches the planes of one column of the mesh: 64 cells in
+// x by TY rows, zc planes, widened by a halo of 8 cells in x and 4 rows in y
+// that the neighbouring columns also compute (sweep s needs sweep s - 1 one
+// cell further out, so the valid region shrinks by one cell per sweep).  In
+// step z the four sweeps work on planes z, z - 1, z - 2, z - 3 (each sweep
+// needs the previous one on its plane and the two planes next to it), with
+// a workgroup barrier between sweeps; their planes live in LDS rings (6
+// black, 5 red).  A chunk of zc planes takes zc + 6 steps (three planes of
+// warm-up on each side are recomputed by the chunks below and above).
+//
+// Thread t owns region unit t: 4 half-row entries of one row (8 cells in x,
+// both colours) in every sweep, so r and the input black values of its unit
+// are prefetched into register queues indexed by plane mod L (r L - 3
+// steps ahead, black e L steps ahead).  The outputs go out through buffer
+// stores that every lane issues in every step, with an offset past the
+// plane for lanes or steps without output (dropped by the hardware), so
+// that the number of memory operations per step is fixed and the compiler's
+// waits for the prefetched loads count exactly.
+//
+// Requires n a power of two >= 64, n % zc == 0.  FIRST: the red sweep starts
+// from e = 0 and ein is not read (eout may be the level's e); otherwise ein
+// supplies the black colour and must not alias eout (other workgroups still
+// read the input halo while this one writes).
+template <int V>
+struct StepPhase {
+  static constexpr int value = V;
+};
+
+template <bool FIRST, int TY, int NT, int L>
+__global__ void __launch_bounds__(NT)
+k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* __restrict__ r, int n,
+         int zc, float scale, float inv_diag) {
+  constexpr int U = 10, HW = 4 * U, RY = TY + 8, PL = RY * HW;   // region: U units x RY rows
+  constexpr int ITEMS = RY * U;
+  static_assert(ITEMS <= NT, "one region unit per thread");
+  constexpr int NB = 6, NR = 5, D = L - 3;
+  __shared__ __align__(16) float ldsb[NB * PL];
+  __shared__ __align__(16) float ldsr[NR * PL];
+  const int hn = n >> 1, m = n - 1, hm = hn - 1;
+  const int64_t oth = (int64_t)n * n * hn, pls = (int64_t)n * hn;
+  const Tile tl = tile_of(n >> 6, n / TY);
+  const int H0 = tl.bx * 32, Y0 = tl.by * TY, Z0 = tl.bz * zc;
+  const int tid = threadIdx.x;
+  const bool ok = tid < ITEMS;
+  const int y = ok ? tid / U : 0, u = ok ? tid % U : 0;
+  const int jj = (Y0 - 4 + y) & m;
+  const int jh = jj * hn + ((H0 - 4 + 4 * u) & hm);   // row and half index of the unit
+  const int base = 4 * tid;                            // its place in an LDS plane
+  // the other colour's entry next to the unit (clamped to the region: at
+  // its edge the value only feeds halo cells that no output depends on)
+  const int xlo = y * HW + max(4 * u - 1, 0);
+  const int xhi = y * HW + min(4 * u + 4, HW - 1);
+  const bool outp = y >= 4 && y < 4 + TY && u >= 1 && u <= 8;
+  auto bs = [&](int z) { return ldsb + ((z - Z0 + 24) % NB) * PL; };
+  auto rs = [&](int z) { return ldsr + ((z - Z0 + 25) % NR) * PL; };
+  // red r of plane P in qr[(P - zs) mod L], black r in qb, input black e in qe
+  Vec4<float> qr[L], qb[L], qe[L];
+  const int zs = Z0 - 3, ze = Z0 + zc + 2;
+  auto ld_r = [&](int c, int z) { return ld_stream4(r + c * oth + (int64_t)(z & m) * pls + jh); };
+  auto ld_e = [&](int z) { return *(const Vec4<float>*)(ein + oth + (int64_t)(z & m) * pls + jh); };
+  // colour c on plane z, rows [lo, RY - lo): s* = the other colour's planes
+  // z - 1, z, z + 1; the result goes to ov and (keep) to dst
+  auto sweep = [&](int c, int z, const float* sm, const float* s0, const float* sp, float* dst, int lo,
+                   bool zero, const Vec4<float>& rv, bool keep, Vec4<float>& ov) {
+    if (!ok || y < lo || y >= RY - lo) return;
+    const int p = (c + jj + (z & m)) & 1;   // cell q of the unit: x = 2 (h0 + q) + p
+    if (zero) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) ov.v[w] = -scale * rv.v[w] * inv_diag;
+    } else {
+      const Vec4<float> xc = *(const Vec4<float>*)(s0 + base);
+      const Vec4<float> ym = *(const Vec4<float>*)(s0 + base - HW);
+      const Vec4<float> yp = *(const Vec4<float>*)(s0 + base + HW);
+      const Vec4<float> zm = *(const Vec4<float>*)(sm + base);
+      const Vec4<float> zp = *(const Vec4<float>*)(sp + base);
+      const float xs = s0[p ? xhi : xlo];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const float xl = p ? xc.v[w] : (w == 0 ? xs : xc.v[w - 1]);
+        const float xr = p ? (w == 3 ? xs : xc.v[w + 1]) : xc.v[w];
+        ov.v[w] = (xl + xr + ym.v[w] + yp.v[w] + zm.v[w] + zp.v[w] - scale * rv.v[w]) * inv_diag;
+      }
+    }
+    if (keep) *(Vec4<float>*)(dst + base) = ov;
+  };
+  auto put = [&](int c, int z, bool valid, const Vec4<float>& ov) {
+    const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(
+        eout + c * oth + (int64_t)(z & m) * pls, (short)0, (int)(pls * 4), 0x00020000);
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f d;
+    d.x = ov.v[0], d.y = ov.v[1], d.z = ov.v[2], d.w = ov.v[3];
+    const unsigned off = (valid && outp) ? (unsigned)jh * 4u : 0x80000000u;
+    __builtin_amdgcn_raw_buffer_store_b128(d, rsc, off, 0, 2 /* non-temporal */);
+  };
+  // input black planes zs - 1 .. zs + 1 into LDS; queues: red r planes
+  // zs - 2 .. zs + D - 1, black r planes zs - 3 .. zs + D - 2, black e
+  // planes zs + 2 .. zs + L + 1 (all in bounds: plane indices wrap)
+  if (!FIRST && ok) {
+    for (int z = zs - 1; z <= zs + 1; ++z) *(Vec4<float>*)(bs(z) + base) = ld_e(z);
+  }
+#pragma unroll
+  for (int x = -2; x < D; ++x) qr[(x + L) % L] = ld_r(0, zs + x);
+#pragma unroll
+  for (int x = -3; x < D - 1; ++x) qb[(x + L) % L] = ld_r(1, zs + x);
+  if (!FIRST) {
+#pragma unroll
+    for (int x = 2; x < L + 2; ++x) qe[x % L] = ld_e(zs + x);
+  }
+  __syncthreads();
+  auto step = [&](int z, auto ph) {
+    constexpr int P = decltype(ph)::value;   // z = zs + P (mod L)
+    if (!FIRST) {
+      if (ok && z <= ze) *(Vec4<float>*)(bs(z + 2) + base) = qe[(P + 2) % L];
+      qe[(P + 2) % L] = ld_e(z + 2 + L);
+    }
+    qr[(P + D) % L] = ld_r(0, z + D);
+    qb[(P + D - 1 + L) % L] = ld_r(1, z - 1 + D);
+    Vec4<float> o1, o2, o3, o4;
+    if (z <= ze) sweep(0, z, bs(z - 1), bs(z), bs(z + 1), rs(z), 1, FIRST, qr[P % L], true, o1);
+    __syncthreads();
+    if (z - 1 >= Z0 - 2 && z - 1 <= ze - 1)
+      sweep(1, z - 1, rs(z - 2), rs(z - 1), rs(z), bs(z - 1), 2, false, qb[(P - 1 + L) % L], true, o2);
+    __syncthreads();
+    if (z - 2 >= Z0 - 1 && z - 2 <= ze - 2)
+      sweep(0, z - 2, bs(z - 3), bs(z - 2), bs(z - 1), rs(z - 2), 3, false, qr[(P - 2 + L) % L], true,
+            o3);
+    put(0, z - 2, z - 2 >= Z0 && z - 2 < Z0 + zc, o3);
+    __syncthreads();
+    const bool last = z - 3 >= Z0 && z - 3 < Z0 + zc;
+    if (last)
+      sweep(1, z - 3, rs(z - 4), rs(z - 3), rs(z - 2), nullptr, 4, false, qb[(P - 3 + L) % L], false, o4);
+    put(1, z - 3, last, o4);
+    __syncthreads();
+  };
+  // whole groups of L steps (steps past ze only load)
+  static_assert(L >= 4 && L <= 8, "queue length");
+  for (int z = zs; z <= ze; z += L) {
+    step(z, StepPhase<0>{});
+    step(z + 1, StepPhase<1>{});
+    step(z + 2, StepPhase<2>{});
+    step(z + 3, StepPhase<3 % L>{});
+    if constexpr (L > 4) step(z + 4, StepPhase<4 % L>{});
+    if constexpr (L > 5) step(z + 5, StepPhase<5 % L>{});
+    if constexpr (L > 6) step(z + 6, StepPhase<6 % L>{});
+    if constexpr (L > 7) step(z + 7, StepPhase<7 % L>{});
+  }
+}
+
 // k_resid_red with 4 red cells per thread (see k_smooth_color_v4).
 template <typename T, int TXV>
 __global__ void __launch_bounds__(256)
@@ -1595,6 +1751,64 @@ static void sweep_run(T* e, const T* r, const Level& L, int level, int c0, int n
   if (group) prof_end(st, K_SMOOTH, n * 1.5 * sizeof(T) * (double)box_cells(L.box), n);
 }
 
+// Planes per workgroup of the fused sweeps: the longest chunk (at most 128
+// planes; each chunk recomputes 6 warm-up planes) that still launches at
+// least 256 workgroups, one per compute unit (512^3: 128 planes, 512
+// workgroups; 256^3: 32 planes, 256 workgroups).
+static int sweep4_chunk(int n) {
+  int zc = std::min(128, n);
+  while (zc > 16 && (n / 64) * (n / 32) * (n / zc) < 256) zc >>= 1;
+  return zc;
+}
+
+static Box whole_mesh(int n) { return Box{{0, 0, 0}, {n - 1, n - 1, n - 1}}; }
+
+void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
+                    bool first, bool fused, hipStream_t st) {
+  if (fused) {
+    const int zc = sweep4_chunk(n);
+    const dim3 g((unsigned)((n / 64) * (n / 32) * (n / zc)));
+    if (first)
+      hipLaunchKernelGGL((k_sweep4<true, 32, 448, 8>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
+                         inv_diag);
+    else
+      hipLaunchKernelGGL((k_sweep4<false, 32, 448, 5>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
+                         inv_diag);
+    return;
+  }
+  if (!first && e != e_out)
+    hipMemcpyAsync(e_out, e, (size_t)n * n * n * sizeof(float), hipMemcpyDeviceToDevice, st);
+  Level L{};
+  L.n = n;
+  L.box = whole_mesh(n);
+  sweep_run<float>(e_out, r, L, 1, 0, 4, first, scale, inv_diag, st);
+}
+
+// The fused form of pre or post sweeps on level L when it applies (FP32,
+// nsweeps == 2 red-black pairs, a periodic level of at least kSweep4Min
+// cells a side with an e_alt array): from a zero guess it writes e, else it
+// reads e and writes e_alt, and the two swap.  False when it does not apply.
+template <typename T>
+static bool sweeps4(Level& L, bool periodic, int nsweeps, bool zero, T scale, T inv_diag,
+                    hipStream_t st) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    const Box fb = whole_mesh(L.n);
+    bool whole = true;
+    for (int d = 0; d < 3; ++d) whole = whole && L.box.lo[d] == fb.lo[d] && L.box.hi[d] == fb.hi[d];
+    if (nsweeps != 2 || !periodic || !whole || L.n < kSweep4Min || !L.e_alt) return false;
+    prof_begin(st, K_SWEEP4);
+    float* out = zero ? (float*)L.e : (float*)L.e_alt;
+    launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true, st);
+    if (!zero) std::swap(L.e, L.e_alt);
+    // r read, e written (4 + 4 bytes per cell); without the zero guess the
+    // black half of e read too (2 more)
+    prof_end(st, K_SWEEP4, (zero ? 8.0 : 10.0) * (double)box_cells(L.box));
+    return true;
+  }
+}
+
 template <typename T>
 static void resid_red(const T* e, const T* r, T* t, const Level& L, T inv_scale, T kappa,
                       hipStream_t st) {
@@ -1690,7 +1904,7 @@ static int sweeps_for_1e3(const Level& L, int l, double kappa, bool periodic) {
 }
 
 template <typename T>
-const T* vcycle(const Level* lv, int nlev_all, double kappa, int pre, int post, int coarse_sweeps,
+const T* vcycle(Level* lv, int nlev_all, double kappa, int pre, int post, int coarse_sweeps,
                 bool periodic, bool fine_start, hipStream_t st) {
   const dim3 blk(kBoxTx, kBoxTy);
   const double es = sizeof(T);
@@ -1708,17 +1922,18 @@ const T* vcycle(const Level* lv, int nlev_all, double kappa, int pre, int post, 
       break;
     }
   for (int l = 0; l < nlev - 1; ++l) {
-    const Level& L = lv[l];
+    Level& L = lv[l];
     const double cells = (double)box_cells(L.box);
     const T scale = (T)std::ldexp(1.0, 2 * l);
     const T inv_diag = (T)(1.0 / (6.0 + std::ldexp(1.0, 2 * l) * kappa));
-    T* e = (T*)L.e;
     const T* r = (const T*)L.r;
     // red, black, ... (pre pairs); the first red pass assumes e = 0, except
     // on the finest level when the cycle continues from the correction
     // already there
-    sweep_run<T>(e, r, L, l, 0, 2 * pre, !(l == 0 && fine_start), scale, inv_diag, st);
-    resid_red<T>(e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
+    const bool zero = !(l == 0 && fine_start);
+    if (!sweeps4<T>(L, periodic, pre, zero, scale, inv_diag, st))
+      sweep_run<T>((T*)L.e, r, L, l, 0, 2 * pre, zero, scale, inv_diag, st);
+    resid_red<T>((const T*)L.e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
     prof_begin(st, K_RESTRICT);
     restrict_level<T>(L, C, st);
@@ -1752,7 +1967,7 @@ const T* vcycle(const Level* lv, int nlev_all, double kappa, int pre, int post, 
     }
   }
   for (int l = nlev - 2; l >= 0; --l) {
-    const Level& L = lv[l];
+    Level& L = lv[l];
     const Level& C = lv[l + 1];
     const double cells = (double)box_cells(L.box);
     const T scale = (T)std::ldexp(1.0, 2 * l);
@@ -1760,13 +1975,12 @@ const T* vcycle(const Level* lv, int nlev_all, double kappa, int pre, int post, 
     prof_begin(st, K_PROLONG);
     prolong_level<T>(L, C, post == 0, st);
     prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
-    sweep_run<T>((T*)L.e, (const T*)L.r, L, l, 0, 2 * post, false, scale, inv_diag, st);
+    if (!sweeps4<T>(L, periodic, post, false, scale, inv_diag, st))
+      sweep_run<T>((T*)L.e, (const T*)L.r, L, l, 0, 2 * post, false, scale, inv_diag, st);
   }
   return (const T*)lv[0].e;
 }
-template const float* vcycle<float>(const Level*, int, double, int, int, int, bool, bool,
-                                    hipStream_t);
-template const double* vcycle<double>(const Level*, int, double, int, int, int, bool, bool,
-                                      hipStream_t);
+template const float* vcycle<float>(Level*, int, double, int, int, int, bool, bool, hipStream_t);
+template const double* vcycle<double>(Level*, int, double, int, int, int, bool, bool, hipStream_t);
 
 }  // namespace sdpm

@@ -8,7 +8,7 @@ const char* const kKernelNames[K_NKERNELS] = {
     "add_const", "smooth_red_zero_guess", "smooth_color", "resid_red", "restrict_fw", "prolong_black",
     "coarse_lds", "interp_kick_drift", "interp_force", "count_kept", "scan_counts", "scatter",
     "copy_back", "morton_radix_sort", "gather", "conv3d_mfma", "conv3d_wgrad_mfma", "net_misc", "force_mesh", "lightcone",
-    "smooth_color_coarse", "ade_sweep", "fft_3d", "fft_divide", "power_spectrum",
+    "smooth_color_coarse", "ade_sweep", "fft_3d", "fft_divide", "power_spectrum", "sweep4_fused",
 };
 
 thread_local Profiler* g_prof = nullptr;

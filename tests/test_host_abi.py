@@ -135,3 +135,15 @@ def test_defaults(P):
     assert cfg.mg_levels == 6 and cfg.box_align == 32 and cfg.tol == 1e-8
     assert P.config_default(1024, 4000.0).mg_levels == 7
     assert P.config_default(32, 100.0).mg_levels == 2
+
+
+def test_rb_sweeps_argument_checks(P):
+    # rejected before any launch: sizes outside [64, 2048] or not powers of
+    # two, NULL arrays, and the fused form writing the array it reads
+    lib = P.library()
+    buf = ctypes.c_void_p(16)
+    for n in (32, 96, 4096):
+        assert lib.sdpm_rb_sweeps(n, buf, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, None, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, None, buf, 1.0, 0.1, 1, 1, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
