@@ -35,8 +35,9 @@ the extrapolated start with and without the learned guess).
 The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
-In the timed steps only the launches of the roofline kernel (the finest-level
-colour sweeps; the net's layers in the learned modes) carry HIP event pairs;
+In the timed steps only the launches of the roofline kernel (the finest level's
+fused four-sweep smoothing passes; the net's layers in the learned modes) carry HIP
+event pairs;
 --profile-steps further untimed steps (3) have every kernel bracketed for the
 per-kernel breakdown (kernel_ms_per_step, roofline.kernels).
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
@@ -78,10 +79,8 @@ def log(msg):
 # HBM bytes per dispatch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE passes, each
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
-# Valid only for the kernel source it was measured on: smooth_color is the finest-level
-# non-first sweep, 266260.0 KiB fetched (x 2.0 for the copy's 524308 KiB per GiB) and
-# 262144.0 KiB written per dispatch.
-MEASURED_TRAFFIC = {"smooth_color": 813715135}
+# Valid only for the kernel source it was measured on.
+MEASURED_TRAFFIC = {}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
@@ -108,12 +107,13 @@ def kernel_roofline(name, d):
             "avg_launch_ms": avg_ms, "launches": d["launches"]}
 
 
-# The kernel with the largest share of GPU time in the step (the finest-level
-# red-black half sweeps); its launches alone carry HIP events in the timed
-# steps, since an event pair around every launch (~900 per step) would slow
-# the timed step itself by ~12 %.  The full per-kernel profile comes from
-# further, untimed steps, and names its own largest kernel.
-ROOFLINE_KERNEL = "smooth_color"
+# The kernel with the largest share of GPU time in the step (the finest
+# level's fused four-sweep smoothing passes that continue from a correction:
+# 10 bytes per cell); its launches alone carry HIP events in the timed
+# steps, since an event pair around every launch (~300 per step) would slow
+# the timed step itself.  The full per-kernel profile comes from further,
+# untimed steps, and names its own largest kernel.
+ROOFLINE_KERNEL = "sweep4_fused"
 
 
 def roofline_of(prof, prof_full=None, full_steps=0):

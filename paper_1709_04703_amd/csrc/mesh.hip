@@ -1789,7 +1789,7 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
 // cells a side with an e_alt array): from a zero guess it writes e, else it
 // reads e and writes e_alt, and the two swap.  False when it does not apply.
 template <typename T>
-static bool sweeps4(Level& L, bool periodic, int nsweeps, bool zero, T scale, T inv_diag,
+static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, T scale, T inv_diag,
                     hipStream_t st) {
   if constexpr (sizeof(T) != 4) {
     return false;
@@ -1798,13 +1798,14 @@ static bool sweeps4(Level& L, bool periodic, int nsweeps, bool zero, T scale, T 
     bool whole = true;
     for (int d = 0; d < 3; ++d) whole = whole && L.box.lo[d] == fb.lo[d] && L.box.hi[d] == fb.hi[d];
     if (nsweeps != 2 || !periodic || !whole || L.n < kSweep4Min || !L.e_alt) return false;
-    prof_begin(st, K_SWEEP4);
+    const int id = level > 0 ? K_SWEEP4_COARSE : zero ? K_SWEEP4_FIRST : K_SWEEP4;
+    prof_begin(st, id);
     float* out = zero ? (float*)L.e : (float*)L.e_alt;
     launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true, st);
     if (!zero) std::swap(L.e, L.e_alt);
     // r read, e written (4 + 4 bytes per cell); without the zero guess the
     // black half of e read too (2 more)
-    prof_end(st, K_SWEEP4, (zero ? 8.0 : 10.0) * (double)box_cells(L.box));
+    prof_end(st, id, (zero ? 8.0 : 10.0) * (double)box_cells(L.box));
     return true;
   }
 }
@@ -1931,7 +1932,7 @@ const T* vcycle(Level* lv, int nlev_all, double kappa, int pre, int post, int co
     // on the finest level when the cycle continues from the correction
     // already there
     const bool zero = !(l == 0 && fine_start);
-    if (!sweeps4<T>(L, periodic, pre, zero, scale, inv_diag, st))
+    if (!sweeps4<T>(L, l, periodic, pre, zero, scale, inv_diag, st))
       sweep_run<T>((T*)L.e, r, L, l, 0, 2 * pre, zero, scale, inv_diag, st);
     resid_red<T>((const T*)L.e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
     const Level& C = lv[l + 1];
@@ -1975,7 +1976,7 @@ const T* vcycle(Level* lv, int nlev_all, double kappa, int pre, int post, int co
     prof_begin(st, K_PROLONG);
     prolong_level<T>(L, C, post == 0, st);
     prof_end(st, K_PROLONG, es * ((post > 0 ? 1.0 : 2.0) * cells + (double)box_cells(C.box)));
-    if (!sweeps4<T>(L, periodic, post, false, scale, inv_diag, st))
+    if (!sweeps4<T>(L, l, periodic, post, false, scale, inv_diag, st))
       sweep_run<T>((T*)L.e, (const T*)L.r, L, l, 0, 2 * post, false, scale, inv_diag, st);
   }
   return (const T*)lv[0].e;

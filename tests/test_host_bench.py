@@ -36,15 +36,17 @@ def test_mfma_roofline_of_the_net():
 
 
 def test_roofline_entry_and_kernel_table():
-    timed = {"smooth_color": {"launches": 540, "ms": 78.5, "bytes": 540 * 805.3e6}}
-    full = {"smooth_color": {"launches": 162, "ms": 23.6, "bytes": 162 * 805.3e6},
+    per = 10.0 * 512**3                 # fused sweeps: 10 bytes per cell
+    timed = {"sweep4_fused": {"launches": 240, "ms": 112.6, "bytes": 240 * per}}
+    full = {"sweep4_fused": {"launches": 36, "ms": 16.9, "bytes": 36 * per},
             "rhs": {"launches": 6, "ms": 5.8, "bytes": 6 * 3.22e9},
             "unused": {"launches": 0, "ms": 0.0, "bytes": 0.0}}
     r = bench.roofline_of(timed, full, 3)
-    assert r["kernel"] == bench.ROOFLINE_KERNEL == "smooth_color"
-    assert r["launches"] == 540
-    assert r["largest_kernel_in_full_profile"] == "smooth_color"
-    assert set(r["kernels"]) == {"smooth_color", "rhs"}          # unused kernels left out
+    assert r["kernel"] == bench.ROOFLINE_KERNEL == "sweep4_fused"
+    assert r["launches"] == 240
+    assert r["achieved"] == pytest.approx(per / (112.6e-3 / 240) / 1e9, rel=1e-12)
+    assert r["largest_kernel_in_full_profile"] == "sweep4_fused"
+    assert set(r["kernels"]) == {"sweep4_fused", "rhs"}          # unused kernels left out
     assert r["kernels"]["rhs"]["ms_per_step"] == pytest.approx(5.8 / 3, abs=1e-3)
     assert r["kernels"]["rhs"]["launches_per_step"] == 2.0
     assert r["kernels"]["rhs"]["GB/s"] == pytest.approx(6 * 3.22e9 / 5.8e-3 / 1e9, abs=0.1)
