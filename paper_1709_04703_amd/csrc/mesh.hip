@@ -659,14 +659,18 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
 // cell further out, so the valid region shrinks by one cell per sweep).  In
 // step z the four sweeps work on planes z, z - 1, z - 2, z - 3 (each sweep
 // needs the previous one on its plane and the two planes next to it), with
-// a workgroup barrier between sweeps; their planes live in LDS rings (6
-// black, 5 red).  A chunk of zc planes takes zc + 6 steps (three planes of
-// warm-up on each side are recomputed by the chunks below and above).
+// a workgroup barrier between sweeps; their planes live in LDS rings of 6
+// planes per colour.  A chunk of zc planes takes zc + 6 steps (three planes
+// of warm-up on each side are recomputed by the chunks below and above).
 //
 // Thread t owns region unit t: 4 half-row entries of one row (8 cells in x,
 // both colours) in every sweep, so r and the input black values of its unit
-// are prefetched into register queues indexed by plane mod L (r L - 3
-// steps ahead, black e L steps ahead).  The outputs go out through buffer
+// are prefetched into register queues indexed by plane mod 6 (r 3 steps
+// ahead, black e 6 steps ahead); the step loop is unrolled by 6, so that
+// queue entries and LDS slots are compile-time constants.  r is read with
+// ordinary (cached) loads: the neighbouring columns read the same halo
+// lines, and the non-temporal hint cost those hits (512^3: 0.51 -> 0.42 ms
+// per pass).  The outputs go out through buffer
 // stores that every lane issues in every step, with an offset past the
 // plane for lanes or steps without output (dropped by the hardware), so
 // that the number of memory operations per step is fixed and the compiler's
@@ -681,16 +685,16 @@ struct StepPhase {
   static constexpr int value = V;
 };
 
-template <bool FIRST, int TY, int NT, int L>
+template <bool FIRST, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* __restrict__ r, int n,
          int zc, float scale, float inv_diag) {
   constexpr int U = 10, HW = 4 * U, RY = TY + 8, PL = RY * HW;   // region: U units x RY rows
   constexpr int ITEMS = RY * U;
   static_assert(ITEMS <= NT, "one region unit per thread");
-  constexpr int NB = 6, NR = 5, D = L - 3;
-  __shared__ __align__(16) float ldsb[NB * PL];
-  __shared__ __align__(16) float ldsr[NR * PL];
+  constexpr int L = 6, NS = 6, D = L - 3;   // queue length = unroll = LDS ring slots
+  __shared__ __align__(16) float ldsb[NS * PL];
+  __shared__ __align__(16) float ldsr[NS * PL];
   const int hn = n >> 1, m = n - 1, hm = hn - 1;
   const int64_t oth = (int64_t)n * n * hn, pls = (int64_t)n * hn;
   const Tile tl = tile_of(n >> 6, n / TY);
@@ -706,12 +710,12 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   const int xlo = y * HW + max(4 * u - 1, 0);
   const int xhi = y * HW + min(4 * u + 4, HW - 1);
   const bool outp = y >= 4 && y < 4 + TY && u >= 1 && u <= 8;
-  auto bs = [&](int z) { return ldsb + ((z - Z0 + 24) % NB) * PL; };
-  auto rs = [&](int z) { return ldsr + ((z - Z0 + 25) % NR) * PL; };
+  // plane z of either ring in slot (z - Z0 + 24) mod 6
+  auto bs = [&](int z) { return ldsb + ((z - Z0 + 24) % NS) * PL; };
   // red r of plane P in qr[(P - zs) mod L], black r in qb, input black e in qe
   Vec4<float> qr[L], qb[L], qe[L];
   const int zs = Z0 - 3, ze = Z0 + zc + 2;
-  auto ld_r = [&](int c, int z) { return ld_stream4(r + c * oth + (int64_t)(z & m) * pls + jh); };
+  auto ld_r = [&](int c, int z) { return *(const Vec4<float>*)(r + c * oth + (int64_t)(z & m) * pls + jh); };
   auto ld_e = [&](int z) { return *(const Vec4<float>*)(ein + oth + (int64_t)(z & m) * pls + jh); };
   // colour c on plane z, rows [lo, RY - lo): s* = the other colour's planes
   // z - 1, z, z + 1; the result goes to ov and (keep) to dst
@@ -731,9 +735,11 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
       const float xs = s0[p ? xhi : xlo];
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        const float xl = p ? xc.v[w] : (w == 0 ? xs : xc.v[w - 1]);
-        const float xr = p ? (w == 3 ? xs : xc.v[w + 1]) : xc.v[w];
-        ov.v[w] = (xl + xr + ym.v[w] + yp.v[w] + zm.v[w] + zp.v[w] - scale * rv.v[w]) * inv_diag;
+        // x neighbours: xc[w] and the one on the p side, in this order
+        // (k_smooth_color_v4 adds them the other way round for p = 0; the
+        // sum of two floats does not depend on the order)
+        const float side = p ? (w == 3 ? xs : xc.v[w + 1]) : (w == 0 ? xs : xc.v[w - 1]);
+        ov.v[w] = (xc.v[w] + side + ym.v[w] + yp.v[w] + zm.v[w] + zp.v[w] - scale * rv.v[w]) * inv_diag;
       }
     }
     if (keep) *(Vec4<float>*)(dst + base) = ov;
@@ -763,41 +769,46 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   }
   __syncthreads();
   auto step = [&](int z, auto ph) {
-    constexpr int P = decltype(ph)::value;   // z = zs + P (mod L)
+    constexpr int P = decltype(ph)::value;   // z = zs + P (mod 6): plane z + X in slot (P + X + 3) mod 6
+    auto B = [&](auto x) { return ldsb + ((P + decltype(x)::value + 3 + NS) % NS) * PL; };
+    auto R = [&](auto x) { return ldsr + ((P + decltype(x)::value + 3 + NS) % NS) * PL; };
+    using M4 = StepPhase<-4>;
+    using M3 = StepPhase<-3>;
+    using M2 = StepPhase<-2>;
+    using M1 = StepPhase<-1>;
+    using Z = StepPhase<0>;
+    using P1 = StepPhase<1>;
+    using P2 = StepPhase<2>;
     if (!FIRST) {
-      if (ok && z <= ze) *(Vec4<float>*)(bs(z + 2) + base) = qe[(P + 2) % L];
+      if (ok && z <= ze) *(Vec4<float>*)(B(P2{}) + base) = qe[(P + 2) % L];
       qe[(P + 2) % L] = ld_e(z + 2 + L);
     }
     qr[(P + D) % L] = ld_r(0, z + D);
     qb[(P + D - 1 + L) % L] = ld_r(1, z - 1 + D);
     Vec4<float> o1, o2, o3, o4;
-    if (z <= ze) sweep(0, z, bs(z - 1), bs(z), bs(z + 1), rs(z), 1, FIRST, qr[P % L], true, o1);
+    if (z <= ze) sweep(0, z, B(M1{}), B(Z{}), B(P1{}), R(Z{}), 1, FIRST, qr[P % L], true, o1);
     __syncthreads();
     if (z - 1 >= Z0 - 2 && z - 1 <= ze - 1)
-      sweep(1, z - 1, rs(z - 2), rs(z - 1), rs(z), bs(z - 1), 2, false, qb[(P - 1 + L) % L], true, o2);
+      sweep(1, z - 1, R(M2{}), R(M1{}), R(Z{}), B(M1{}), 2, false, qb[(P - 1 + L) % L], true, o2);
     __syncthreads();
     if (z - 2 >= Z0 - 1 && z - 2 <= ze - 2)
-      sweep(0, z - 2, bs(z - 3), bs(z - 2), bs(z - 1), rs(z - 2), 3, false, qr[(P - 2 + L) % L], true,
-            o3);
+      sweep(0, z - 2, B(M3{}), B(M2{}), B(M1{}), R(M2{}), 3, false, qr[(P - 2 + L) % L], true, o3);
     put(0, z - 2, z - 2 >= Z0 && z - 2 < Z0 + zc, o3);
     __syncthreads();
     const bool last = z - 3 >= Z0 && z - 3 < Z0 + zc;
     if (last)
-      sweep(1, z - 3, rs(z - 4), rs(z - 3), rs(z - 2), nullptr, 4, false, qb[(P - 3 + L) % L], false, o4);
+      sweep(1, z - 3, R(M4{}), R(M3{}), R(M2{}), nullptr, 4, false, qb[(P - 3 + L) % L], false, o4);
     put(1, z - 3, last, o4);
     __syncthreads();
   };
-  // whole groups of L steps (steps past ze only load)
-  static_assert(L >= 4 && L <= 8, "queue length");
+  // whole groups of 6 steps (steps past ze only load)
   for (int z = zs; z <= ze; z += L) {
     step(z, StepPhase<0>{});
     step(z + 1, StepPhase<1>{});
     step(z + 2, StepPhase<2>{});
-    step(z + 3, StepPhase<3 % L>{});
-    if constexpr (L > 4) step(z + 4, StepPhase<4 % L>{});
-    if constexpr (L > 5) step(z + 5, StepPhase<5 % L>{});
-    if constexpr (L > 6) step(z + 6, StepPhase<6 % L>{});
-    if constexpr (L > 7) step(z + 7, StepPhase<7 % L>{});
+    step(z + 3, StepPhase<3>{});
+    step(z + 4, StepPhase<4>{});
+    step(z + 5, StepPhase<5>{});
   }
 }
 
@@ -1751,12 +1762,13 @@ static void sweep_run(T* e, const T* r, const Level& L, int level, int c0, int n
   if (group) prof_end(st, K_SMOOTH, n * 1.5 * sizeof(T) * (double)box_cells(L.box), n);
 }
 
-// Planes per workgroup of the fused sweeps: the longest chunk (at most 128
+// Planes per workgroup of the fused sweeps: the longest chunk (at most 64
 // planes; each chunk recomputes 6 warm-up planes) that still launches at
-// least 256 workgroups, one per compute unit (512^3: 128 planes, 512
-// workgroups; 256^3: 32 planes, 256 workgroups).
+// least 256 workgroups, one per compute unit (512^3: 64 planes, 1024
+// workgroups, measured 3 % faster than 128 planes; 256^3: 32 planes, 256
+// workgroups, 20 % faster than 16).
 static int sweep4_chunk(int n) {
-  int zc = std::min(128, n);
+  int zc = std::min(64, n);
   while (zc > 16 && (n / 64) * (n / 32) * (n / zc) < 256) zc >>= 1;
   return zc;
 }
@@ -1769,10 +1781,10 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
     const int zc = sweep4_chunk(n);
     const dim3 g((unsigned)((n / 64) * (n / 32) * (n / zc)));
     if (first)
-      hipLaunchKernelGGL((k_sweep4<true, 32, 448, 8>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
+      hipLaunchKernelGGL((k_sweep4<true, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
                          inv_diag);
     else
-      hipLaunchKernelGGL((k_sweep4<false, 32, 448, 5>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
+      hipLaunchKernelGGL((k_sweep4<false, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
                          inv_diag);
     return;
   }
