@@ -79,7 +79,7 @@ struct sdpm_ctx {
   std::vector<double> rec_kappa, rec_rms_r, rec_rms_phi;
   int64_t steps_done = 0;
   double* hpin = nullptr;       // host copies of device scalars
-  hipEvent_t ev[12] = {};      // [0..6] step phases, [8..11] gate timing
+  hipEvent_t ev[12] = {};      // [0..6] step phases, [7] solve-start norms, [8..11] gate timing
   Profiler prof;
   bool bound = false;
   sdpm_particles parts{};
@@ -534,8 +534,29 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
                        &nb, c->st);
     launch_reduce_final(c->partial, nb, 1, c->dscal + 1, c->st);
   }
-  int rc = sync_scalars(c, 2);
-  if (rc) return rc;
+  const bool recording = c->rec_buf && c->rec_count < c->rec_max;
+  const bool gated = (g.warm_start & ~SDPM_WS_EXTRAP) == SDPM_WS_LEARNED_GATED;
+  // The first V-cycle of the first outer iteration does not depend on the
+  // norms read next (they decide whether it is used and how many cycles
+  // follow it), so when no learned guess or recording can come before it, it
+  // is enqueued before the wait and the GPU runs it meanwhile; when the start
+  // already meets tol its result is left unused.
+  // The copies of the norms go first, the host waits for them alone (event 7).
+  const bool spec = !recording && (!c->net_ready || (gated && c->gate_skip[slot] > 0));
+  const T* e_spec = nullptr;
+  int rc = SDPM_OK;
+  if (spec) {
+    HIP_TRY(c, hipMemcpyAsync(c->hpin, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipMemcpyAsync(c->hpin + 16, c->dflags, 16, hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(c, hipEventRecord(c->ev[7], c->st));
+    if (gated) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
+    e_spec = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
+                       false, c->st);
+    HIP_TRY(c, hipEventSynchronize(c->ev[7]));
+  } else {
+    rc = sync_scalars(c, 2);
+    if (rc) return rc;
+  }
   const double bn = std::sqrt(c->hpin[0]);
   const double denom = std::max(bn, 1e-300);
   double rn = std::sqrt(c->hpin[1]);
@@ -543,10 +564,8 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
   so->res0 = rn / denom;
   so->warm = 0;
   const double cells = (double)box_cells(b);
-  const bool recording = c->rec_buf && c->rec_count < c->rec_max;
   float* rec = recording ? c->rec_buf + (size_t)c->rec_count * 3 * (size_t)g.ng * g.ng * g.ng : nullptr;
   double rms_phi = 0.0;
-  const bool gated = (g.warm_start & ~SDPM_WS_EXTRAP) == SDPM_WS_LEARNED_GATED;
   bool try_net = c->net_ready && rn > thresh && rn > 0.0;
   if (try_net && gated && c->gate_skip[slot] > 0) {
     --c->gate_skip[slot];
@@ -644,9 +663,10 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
       pred_next *= c->rho_est;
       factor *= c->rho_est;
     }
-    if (time_it) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
-    const T* e0 = nullptr;
-    for (int q = 0; q < ncyc; ++q)
+    const bool ahead = it == 0 && e_spec;   // first cycle already enqueued
+    if (time_it && !ahead) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
+    const T* e0 = ahead ? e_spec : nullptr;
+    for (int q = ahead ? 1 : 0; q < ncyc; ++q)
       e0 = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
                      q > 0, c->st);
     launch_correct<T>(c->fields.phi, e0, chg, pending, g.ng, b, c->st);
@@ -1170,14 +1190,20 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
   // Phi from t + dt/2 to t + dt with the same density    (row 7)
   SolveOut s2;
   int src2 = SDPM_OK;
+  // a multigrid solve waits for the GPU at least once, after the particle
+  // pass above: the flags and the removal count it copied to the host are
+  // then already those of this step
+  bool flags_read = false;
   if (ade) {
     // the same source, the sweep in the other direction
     launch_ade_sweep(c->fields.phi, c->fields.rhs, g.ng, c->lv[0].box, c->periodic != 0,
                      1.0 / sc.kappa2_h2, false, c->st);
   } else if (sc.kappa2_h2 > 0.0) {
-    const RhsOut rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, mg_solve(c));
+    const bool mg = mg_solve(c);
+    const RhsOut rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, mg);
     src2 = solve(c, sc.kappa2_h2, 1, &s2, rh2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
+    flags_read = mg;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], c->st));
   if (lc_fixed) {
@@ -1203,8 +1229,10 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
                               hipMemcpyDeviceToHost, c->st));
   }
   c->lc_prev_r = sc.r_lc_end;
-  rc = sync_scalars(c, 1);
-  if (rc) return rc;
+  if (lc_fixed || !flags_read) {
+    rc = sync_scalars(c, 1);
+    if (rc) return rc;
+  }
   int lc_full = SDPM_OK;
   if (lc_fixed) {
     const int64_t crossed = (int64_t)((const unsigned long long*)(c->hpin + kHostLcCount))[0];

@@ -653,10 +653,14 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
 // once and its final red and black values written once: 10 bytes per cell
 // (8 with the zero initial guess, which reads no e).
 //
-// Each workgroup marches the planes of one column of the mesh: 64 cells in
+// Each workgroup marches the planes of one column of the mesh: 8 UX cells in
 // x by TY rows, zc planes, widened by a halo of 8 cells in x and 4 rows in y
 // that the neighbouring columns also compute (sweep s needs sweep s - 1 one
-// cell further out, so the valid region shrinks by one cell per sweep).  In
+// cell further out, so the valid region shrinks by one cell per sweep).
+// Wide columns pay: a region row starts and ends 16 bytes into the cache
+// lines of the neighbouring columns, whose reads hit in L2 only as far as
+// the columns keep pace with each other (512^3: 128 x 32-cell columns,
+// 0.31 ms per pass, against 0.41 ms for 64 x 32 and 0.36 ms for 64 x 64).  In
 // step z the four sweeps work on planes z, z - 1, z - 2, z - 3 (each sweep
 // needs the previous one on its plane and the two planes next to it), with
 // a workgroup barrier between sweeps; their planes live in LDS rings of 6
@@ -676,7 +680,7 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
 // that the number of memory operations per step is fixed and the compiler's
 // waits for the prefetched loads count exactly.
 //
-// Requires n a power of two >= 64, n % zc == 0.  FIRST: the red sweep starts
+// Requires n a power of two >= 8 UX, n % zc == 0.  FIRST: the red sweep starts
 // from e = 0 and ein is not read (eout may be the level's e); otherwise ein
 // supplies the black colour and must not alias eout (other workgroups still
 // read the input halo while this one writes).
@@ -685,11 +689,11 @@ struct StepPhase {
   static constexpr int value = V;
 };
 
-template <bool FIRST, int TY, int NT>
+template <bool FIRST, int UX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* __restrict__ r, int n,
          int zc, float scale, float inv_diag) {
-  constexpr int U = 10, HW = 4 * U, RY = TY + 8, PL = RY * HW;   // region: U units x RY rows
+  constexpr int U = UX + 2, HW = 4 * U, RY = TY + 8, PL = RY * HW;   // region: U units x RY rows
   constexpr int ITEMS = RY * U;
   static_assert(ITEMS <= NT, "one region unit per thread");
   constexpr int L = 6, NS = 6, D = L - 3;   // queue length = unroll = LDS ring slots
@@ -697,8 +701,8 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   __shared__ __align__(16) float ldsr[NS * PL];
   const int hn = n >> 1, m = n - 1, hm = hn - 1;
   const int64_t oth = (int64_t)n * n * hn, pls = (int64_t)n * hn;
-  const Tile tl = tile_of(n >> 6, n / TY);
-  const int H0 = tl.bx * 32, Y0 = tl.by * TY, Z0 = tl.bz * zc;
+  const Tile tl = tile_of(n / (8 * UX), n / TY);
+  const int H0 = tl.bx * 4 * UX, Y0 = tl.by * TY, Z0 = tl.bz * zc;
   const int tid = threadIdx.x;
   const bool ok = tid < ITEMS;
   const int y = ok ? tid / U : 0, u = ok ? tid % U : 0;
@@ -709,7 +713,7 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   // its edge the value only feeds halo cells that no output depends on)
   const int xlo = y * HW + max(4 * u - 1, 0);
   const int xhi = y * HW + min(4 * u + 4, HW - 1);
-  const bool outp = y >= 4 && y < 4 + TY && u >= 1 && u <= 8;
+  const bool outp = y >= 4 && y < 4 + TY && u >= 1 && u <= UX;
   // plane z of either ring in slot (z - Z0 + 24) mod 6
   auto bs = [&](int z) { return ldsb + ((z - Z0 + 24) % NS) * PL; };
   // red r of plane P in qr[(P - zs) mod L], black r in qb, input black e in qe
@@ -1762,14 +1766,14 @@ static void sweep_run(T* e, const T* r, const Level& L, int level, int c0, int n
   if (group) prof_end(st, K_SMOOTH, n * 1.5 * sizeof(T) * (double)box_cells(L.box), n);
 }
 
-// Planes per workgroup of the fused sweeps: the longest chunk (at most 64
-// planes; each chunk recomputes 6 warm-up planes) that still launches at
-// least 256 workgroups, one per compute unit (512^3: 64 planes, 1024
-// workgroups, measured 3 % faster than 128 planes; 256^3: 32 planes, 256
-// workgroups, 20 % faster than 16).
-static int sweep4_chunk(int n) {
-  int zc = std::min(64, n);
-  while (zc > 16 && (n / 64) * (n / 32) * (n / zc) < 256) zc >>= 1;
+// Planes per workgroup of the fused sweeps on columns tx cells wide and 32
+// rows: one workgroup per compute unit (256; each chunk recomputes 6
+// warm-up planes), at least 16 planes (512^3: 128 planes, 0.31 ms against
+// 0.33 ms with 64; 256^3: 16 planes, 48 us against 65 us with 32).
+static int sweep4_chunk(int n, int tx) {
+  const int64_t per = (int64_t)n * n * n / ((int64_t)tx * 32 * 256);
+  int zc = 16;
+  while (zc < n && zc < per) zc <<= 1;
   return zc;
 }
 
@@ -1778,14 +1782,26 @@ static Box whole_mesh(int n) { return Box{{0, 0, 0}, {n - 1, n - 1, n - 1}}; }
 void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
                     bool first, bool fused, hipStream_t st) {
   if (fused) {
-    const int zc = sweep4_chunk(n);
-    const dim3 g((unsigned)((n / 64) * (n / 32) * (n / zc)));
-    if (first)
-      hipLaunchKernelGGL((k_sweep4<true, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
-                         inv_diag);
-    else
-      hipLaunchKernelGGL((k_sweep4<false, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc, scale,
-                         inv_diag);
+    // 128 x 32-cell columns (one 768-thread workgroup per compute unit: 138
+    // KB of LDS); 64 x 32 on a 64^3 mesh
+    const int tx = n >= 128 ? 128 : 64;
+    const int zc = sweep4_chunk(n, tx);
+    const dim3 g((unsigned)((n / tx) * (n / 32) * (n / zc)));
+    if (tx == 128) {
+      if (first)
+        hipLaunchKernelGGL((k_sweep4<true, 16, 32, 768>), g, dim3(768), 0, st, e, e_out, r, n, zc,
+                           scale, inv_diag);
+      else
+        hipLaunchKernelGGL((k_sweep4<false, 16, 32, 768>), g, dim3(768), 0, st, e, e_out, r, n, zc,
+                           scale, inv_diag);
+    } else {
+      if (first)
+        hipLaunchKernelGGL((k_sweep4<true, 8, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc,
+                           scale, inv_diag);
+      else
+        hipLaunchKernelGGL((k_sweep4<false, 8, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc,
+                           scale, inv_diag);
+    }
     return;
   }
   if (!first && e != e_out)
