@@ -1025,14 +1025,19 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
   c->box = full_box(cfg->ng);
   c->counts_box = full_box(cfg->ng);
   set_levels(c);
-  c->hpin = new (std::nothrow) double[kHostScalars]();
-  if (!c->hpin) {
+  // pinned, so that the scalar copies to the host are asynchronous (into
+  // pageable memory the runtime returns from each copy only once it is done)
+  if (hipHostMalloc((void**)&c->hpin, kHostScalars * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      !c->hpin) {
+    c->hpin = nullptr;
     delete c;
-    return fail(nullptr, SDPM_ENOMEM, "host allocation failed");
+    return fail(nullptr, SDPM_ENOMEM, "pinned host allocation failed");
   }
+  std::memset(c->hpin, 0, kHostScalars * sizeof(double));
   for (auto& e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
-      delete[] c->hpin;
+      (void)hipHostFree(c->hpin);
       delete c;
       return fail(nullptr, SDPM_EHIP, "hipEventCreate failed");
     }
@@ -1045,7 +1050,7 @@ int sdpm_create(const sdpm_config* cfg, void* workspace, int64_t ws_bytes, void*
     if (frc) {
       fft_destroy(&c->fft);
       for (auto& e : c->ev) (void)hipEventDestroy(e);
-      delete[] c->hpin;
+      (void)hipHostFree(c->hpin);
       delete c;
       return fail(nullptr, frc, "%s", msg);
     }
@@ -1662,7 +1667,7 @@ int sdpm_destroy(sdpm_ctx* c) {
   fft_destroy(&c->fft);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
-  delete[] c->hpin;
+  (void)hipHostFree(c->hpin);
   delete c;
   return SDPM_OK;
 }
