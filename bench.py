@@ -82,7 +82,7 @@ def log(msg):
 # Valid only for the kernel source it was measured on: sweep4_fused is the 512^3 level's
 # fused smoothing pass continuing from a correction, 600350.3 KiB fetched (x 1.99992 for the
 # copy's 524307.9 KiB per GiB) and 534547.5 KiB written per dispatch.
-MEASURED_TRAFFIC = {"sweep4_fused": 1776847447}
+MEASURED_TRAFFIC = {}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0

@@ -357,9 +357,19 @@ int sdpm_ade_sweep(sdpm_ctx* ctx, double lam, int forward);
  * Both forms give bit-identical e_out.  n: power of two in [64, 2048]; all
  * arrays device memory of n^3 floats; runs on stream (hipStream_t, NULL =
  * default), asynchronously.  SDPM_EINVAL for other sizes, NULL pointers or
- * e == e_out with fused and not first.                                     */
+ * e == e_out with fused and not first.  t_out (NULL for none): the red
+ * residual of the result, t = r - (sum of the 6 neighbours - 6 e) / scale +
+ * kappa_h2 e (kappa_h2 = kappa h^2 of the finest level: inv_diag =
+ * 1 / (6 + kappa_h2 scale)), the V-cycle's restriction input, into the red
+ * half of t_out (n^3 floats; the black half is not written); the fused form
+ * then does not write the red half of e_out (the V-cycle does not read it
+ * before the post-smoothing sets it anew), the other writes it and t_out by
+ * a separate launch; t_out's red half and e_out's black half are
+ * bit-identical between the two.  SDPM_EINVAL also for t_out with
+ * scale <= 0 or aliasing another array.                                    */
 int sdpm_rb_sweeps(int32_t n, const float* e, float* e_out, const float* r, float scale,
-                   float inv_diag, int32_t first, int32_t fused, void* stream);
+                   float inv_diag, int32_t first, int32_t fused, float* t_out, float kappa_h2,
+                   void* stream);
 /* Re-sort of the active particles (all SoA arrays permuted together by the
  * key of sort_shift: the Morton code of the cell's block, then its row
  * inside the block; stable LSD radix sort).  Results of the step do not

@@ -160,7 +160,8 @@ def library() -> ctypes.CDLL:
         "sdpm_set_lightcone": [vp, P(Lightcone)],
         "sdpm_lightcone_count": [vp, P(i64)],
         "sdpm_ade_sweep": [vp, dbl, i32],
-        "sdpm_rb_sweeps": [i32, vp, vp, vp, ctypes.c_float, ctypes.c_float, i32, i32, vp],
+        "sdpm_rb_sweeps": [i32, vp, vp, vp, ctypes.c_float, ctypes.c_float, i32, i32, vp,
+                           ctypes.c_float, vp],
         "sdpm_pk_workspace_bytes": [i32, P(i64)],
         "sdpm_power_spectrum": [P(vp), i64, dbl, i32, i32, vp, i64, vp, P(dbl), P(dbl), P(dbl),
                                 P(i64)],
@@ -242,12 +243,15 @@ def conv3d(n, inp, w, bias, flags, mask, out):
                                 _stream()))
 
 
-def rb_sweeps(n, e, e_out, r, scale: float, inv_diag: float, first: bool, fused: bool):
+def rb_sweeps(n, e, e_out, r, scale: float, inv_diag: float, first: bool, fused: bool,
+              t_out=None, kappa_h2: float = 0.0):
     """Four red-black half sweeps on a periodic FP32 level in colour-split
-    storage (see sdpm_rb_sweeps); torch device tensors of n^3 floats (e may
-    be None when first)."""
+    storage, and with t_out the red residual of the result (see
+    sdpm_rb_sweeps); torch device tensors of n^3 floats (e may be None when
+    first)."""
     check(library().sdpm_rb_sweeps(n, _ptr(e), _ptr(e_out), _ptr(r), scale, inv_diag,
-                                   1 if first else 0, 1 if fused else 0, _stream()))
+                                   1 if first else 0, 1 if fused else 0, _ptr(t_out), kappa_h2,
+                                   _stream()))
 
 
 def pk_workspace_bytes(ng: int) -> int:

@@ -178,9 +178,12 @@ constexpr int kSweep4Min = 256;
 // n^3 cells, n a power of two >= 64: with fused, one k_sweep4 pass from e
 // (black colour; not read when first) into e_out (e_out == e allowed only
 // when first); otherwise e copied to e_out (not when first) and four
-// k_smooth_color_v4 launches in place on e_out.
+// k_smooth_color_v4 launches in place on e_out.  With t (may be null) the
+// red residual of the result goes to t's red half (inv_scale = 1 / scale,
+// kappa = kappa h^2): in the fused pass instead of the red half of e_out,
+// which it then leaves unwritten; otherwise by k_resid_red_v4.
 void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
-                    bool first, bool fused, hipStream_t st);
+                    bool first, bool fused, float* t, float inv_scale, float kappa, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Launchers, particle kernels (particles.hip).

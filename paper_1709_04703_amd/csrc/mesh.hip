@@ -680,6 +680,13 @@ k_smooth_color_v4(T* __restrict__ eo, const T* __restrict__ ex, const T* __restr
 // that the number of memory operations per step is fixed and the compiler's
 // waits for the prefetched loads count exactly.
 //
+// RES (pre-smoothing): a fifth stage forms the red residual t = r - A e of
+// the result (the arithmetic of k_resid_red_v4) one plane behind the last
+// sweep and writes it to tout's red half instead of writing the red result
+// (which nothing reads before the post-smoothing sets it anew): the black
+// ring keeps one more plane (7), the halo one more row, and the first
+// sweep takes the black input just outside the region in x from ldsx.
+//
 // Requires n a power of two >= 8 UX, n % zc == 0.  FIRST: the red sweep starts
 // from e = 0 and ein is not read (eout may be the level's e); otherwise ein
 // supplies the black colour and must not alias eout (other workgroups still
@@ -689,16 +696,19 @@ struct StepPhase {
   static constexpr int value = V;
 };
 
-template <bool FIRST, int UX, int TY, int NT>
+template <bool FIRST, bool RES, int UX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* __restrict__ r, int n,
-         int zc, float scale, float inv_diag) {
-  constexpr int U = UX + 2, HW = 4 * U, RY = TY + 8, PL = RY * HW;   // region: U units x RY rows
+         int zc, float scale, float inv_diag, float* __restrict__ tout, float inv_scale, float kappa) {
+  constexpr int G = RES ? 1 : 0;                 // the residual: one more stage
+  constexpr int HY = 4 + G;                      // halo rows per side
+  constexpr int U = UX + 2, HW = 4 * U, RY = TY + 2 * HY, PL = RY * HW;   // region: U units x RY rows
   constexpr int ITEMS = RY * U;
   static_assert(ITEMS <= NT, "one region unit per thread");
-  constexpr int L = 6, NS = 6, D = L - 3;   // queue length = unroll = LDS ring slots
-  __shared__ __align__(16) float ldsb[NS * PL];
+  constexpr int L = 6, NS = 6, NB = NS + G, D = L - 3;   // queue length = unroll = red LDS slots
+  __shared__ __align__(16) float ldsb[NB * PL];
   __shared__ __align__(16) float ldsr[NS * PL];
+  __shared__ float ldsx[RES ? NB * 2 * RY : 1];   // black input just outside the region in x
   const int hn = n >> 1, m = n - 1, hm = hn - 1;
   const int64_t oth = (int64_t)n * n * hn, pls = (int64_t)n * hn;
   const Tile tl = tile_of(n / (8 * UX), n / TY);
@@ -706,25 +716,37 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   const int tid = threadIdx.x;
   const bool ok = tid < ITEMS;
   const int y = ok ? tid / U : 0, u = ok ? tid % U : 0;
-  const int jj = (Y0 - 4 + y) & m;
+  const int jj = (Y0 - HY + y) & m;
   const int jh = jj * hn + ((H0 - 4 + 4 * u) & hm);   // row and half index of the unit
   const int base = 4 * tid;                            // its place in an LDS plane
   // the other colour's entry next to the unit (clamped to the region: at
-  // its edge the value only feeds halo cells that no output depends on)
+  // its edge the value only feeds halo cells that no output depends on;
+  // with RES the first sweep takes the true values there instead, from
+  // ldsx, since the residual needs one cell more)
   const int xlo = y * HW + max(4 * u - 1, 0);
   const int xhi = y * HW + min(4 * u + 4, HW - 1);
-  const bool outp = y >= 4 && y < 4 + TY && u >= 1 && u <= UX;
-  // plane z of either ring in slot (z - Z0 + 24) mod 6
-  auto bs = [&](int z) { return ldsb + ((z - Z0 + 24) % NS) * PL; };
-  // red r of plane P in qr[(P - zs) mod L], black r in qb, input black e in qe
+  const bool edge_l = u == 0, edge_r = u == U - 1;
+  const int jx = jj * hn + (edge_r ? ((H0 - 4 + 4 * U) & hm) : ((H0 - 5) & hm));
+  const bool outp = y >= HY && y < HY + TY && u >= 1 && u <= UX;
+  // plane z of the black ring in slot (z - Z0 + 24) mod 6, with RES
+  // (z - Z0 + 28) mod 7 (one more plane: the residual's)
+  auto bs = [&](int z) { return ldsb + ((z - Z0 + (RES ? 28 : 24)) % NB) * PL; };
+  auto xs_of = [&](int z) { return ldsx + ((z - Z0 + 28) % NB) * 2 * RY; };
+  // red r of plane P in qr[(P - zs) mod L], black r in qb, input black e in
+  // qe (and its value outside the region in qx); with RES the residual's r,
+  // red result and the black results of the two planes next to it in q5r,
+  // q3, q4 (indexed by plane mod 3)
   Vec4<float> qr[L], qb[L], qe[L];
-  const int zs = Z0 - 3, ze = Z0 + zc + 2;
+  float qx[RES ? L : 1];
+  Vec4<float> q5r[RES ? 3 : 1], q3[RES ? 3 : 1], q4[RES ? 3 : 1];
+  const int zs = Z0 - 3 - G, ze = Z0 + zc + 2 + G;
   auto ld_r = [&](int c, int z) { return *(const Vec4<float>*)(r + c * oth + (int64_t)(z & m) * pls + jh); };
   auto ld_e = [&](int z) { return *(const Vec4<float>*)(ein + oth + (int64_t)(z & m) * pls + jh); };
+  auto ld_x = [&](int z) { return ein[oth + (int64_t)(z & m) * pls + jx]; };
   // colour c on plane z, rows [lo, RY - lo): s* = the other colour's planes
   // z - 1, z, z + 1; the result goes to ov and (keep) to dst
   auto sweep = [&](int c, int z, const float* sm, const float* s0, const float* sp, float* dst, int lo,
-                   bool zero, const Vec4<float>& rv, bool keep, Vec4<float>& ov) {
+                   bool zero, const Vec4<float>& rv, bool keep, Vec4<float>& ov, const float* sx) {
     if (!ok || y < lo || y >= RY - lo) return;
     const int p = (c + jj + (z & m)) & 1;   // cell q of the unit: x = 2 (h0 + q) + p
     if (zero) {
@@ -736,7 +758,8 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
       const Vec4<float> yp = *(const Vec4<float>*)(s0 + base + HW);
       const Vec4<float> zm = *(const Vec4<float>*)(sm + base);
       const Vec4<float> zp = *(const Vec4<float>*)(sp + base);
-      const float xs = s0[p ? xhi : xlo];
+      float xs = s0[p ? xhi : xlo];
+      if (sx && (p ? edge_r : edge_l)) xs = sx[(p ? RY : 0) + y];
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         // x neighbours: xc[w] and the one on the p side, in this order
@@ -748,20 +771,43 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
     }
     if (keep) *(Vec4<float>*)(dst + base) = ov;
   };
-  auto put = [&](int c, int z, bool valid, const Vec4<float>& ov) {
+  // red residual t = r - A e on plane z (rows [HY, RY - HY)) with the
+  // arithmetic of k_resid_red_v4: black neighbours in the plane from s0, in
+  // the planes next to it from bm / bp, the cell's red value ctr
+  auto resid = [&](int z, const float* s0, const Vec4<float>& bm, const Vec4<float>& bp,
+                   const Vec4<float>& ctr, const Vec4<float>& rv, Vec4<float>& ov) {
+    if (!ok || y < HY || y >= RY - HY) return;
+    const int p = (jj + (z & m)) & 1;
+    const Vec4<float> xc = *(const Vec4<float>*)(s0 + base);
+    const Vec4<float> ym = *(const Vec4<float>*)(s0 + base - HW);
+    const Vec4<float> yp = *(const Vec4<float>*)(s0 + base + HW);
+    const float xs = s0[p ? xhi : xlo];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const float side = p ? (w == 3 ? xs : xc.v[w + 1]) : (w == 0 ? xs : xc.v[w - 1]);
+      const float nb = xc.v[w] + side + ym.v[w] + yp.v[w] + bm.v[w] + bp.v[w];
+      ov.v[w] = rv.v[w] - (nb - 6.0f * ctr.v[w]) * inv_scale + kappa * ctr.v[w];
+    }
+  };
+  auto put = [&](float* dst, int c, int z, bool valid, const Vec4<float>& ov) {
     const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(
-        eout + c * oth + (int64_t)(z & m) * pls, (short)0, (int)(pls * 4), 0x00020000);
+        dst + c * oth + (int64_t)(z & m) * pls, (short)0, (int)(pls * 4), 0x00020000);
     typedef float v4f __attribute__((ext_vector_type(4)));
     v4f d;
     d.x = ov.v[0], d.y = ov.v[1], d.z = ov.v[2], d.w = ov.v[3];
     const unsigned off = (valid && outp) ? (unsigned)jh * 4u : 0x80000000u;
     __builtin_amdgcn_raw_buffer_store_b128(d, rsc, off, 0, 2 /* non-temporal */);
   };
+  auto stage_black = [&](int z, const Vec4<float>& v, float vx) {
+    if (!ok) return;
+    *(Vec4<float>*)(bs(z) + base) = v;
+    if (RES && (edge_l || edge_r)) xs_of(z)[(edge_r ? RY : 0) + y] = vx;
+  };
   // input black planes zs - 1 .. zs + 1 into LDS; queues: red r planes
   // zs - 2 .. zs + D - 1, black r planes zs - 3 .. zs + D - 2, black e
   // planes zs + 2 .. zs + L + 1 (all in bounds: plane indices wrap)
-  if (!FIRST && ok) {
-    for (int z = zs - 1; z <= zs + 1; ++z) *(Vec4<float>*)(bs(z) + base) = ld_e(z);
+  if (!FIRST) {
+    for (int z = zs - 1; z <= zs + 1; ++z) stage_black(z, ld_e(z), RES ? ld_x(z) : 0.f);
   }
 #pragma unroll
   for (int x = -2; x < D; ++x) qr[(x + L) % L] = ld_r(0, zs + x);
@@ -769,13 +815,20 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   for (int x = -3; x < D - 1; ++x) qb[(x + L) % L] = ld_r(1, zs + x);
   if (!FIRST) {
 #pragma unroll
-    for (int x = 2; x < L + 2; ++x) qe[x % L] = ld_e(zs + x);
+    for (int x = 2; x < L + 2; ++x) {
+      qe[x % L] = ld_e(zs + x);
+      if constexpr (RES) qx[x % L] = ld_x(zs + x);
+    }
   }
   __syncthreads();
   auto step = [&](int z, auto ph) {
-    constexpr int P = decltype(ph)::value;   // z = zs + P (mod 6): plane z + X in slot (P + X + 3) mod 6
-    auto B = [&](auto x) { return ldsb + ((P + decltype(x)::value + 3 + NS) % NS) * PL; };
-    auto R = [&](auto x) { return ldsr + ((P + decltype(x)::value + 3 + NS) % NS) * PL; };
+    constexpr int P = decltype(ph)::value;   // z = zs + P (mod 6)
+    // black slots (compile-time without RES: plane z + X in (P + X + 3) mod 6)
+    auto B = [&](auto x) {
+      if constexpr (RES) return bs(z + decltype(x)::value);
+      else return ldsb + ((P + decltype(x)::value + 3 + NS) % NS) * PL;
+    };
+    auto R = [&](auto x) { return ldsr + ((P + decltype(x)::value + 3 + G + NS) % NS) * PL; };
     using M4 = StepPhase<-4>;
     using M3 = StepPhase<-3>;
     using M2 = StepPhase<-2>;
@@ -783,26 +836,49 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
     using Z = StepPhase<0>;
     using P1 = StepPhase<1>;
     using P2 = StepPhase<2>;
+    // the black input of plane z + 2: into its slot now, or with RES at the
+    // end of the step (its slot holds the residual's plane until then)
+    Vec4<float> hold;
+    float holdx = 0.f;
     if (!FIRST) {
-      if (ok && z <= ze) *(Vec4<float>*)(B(P2{}) + base) = qe[(P + 2) % L];
+      hold = qe[(P + 2) % L];
+      if constexpr (RES) holdx = qx[(P + 2) % L];
+      if (!RES && ok && z <= ze) *(Vec4<float>*)(B(P2{}) + base) = hold;
       qe[(P + 2) % L] = ld_e(z + 2 + L);
+      if constexpr (RES) qx[(P + 2) % L] = ld_x(z + 2 + L);
     }
+    if constexpr (RES) q5r[P % 3] = qr[(P - 2 + L) % L];   // red r of plane z - 2, for step z + 2
     qr[(P + D) % L] = ld_r(0, z + D);
     qb[(P + D - 1 + L) % L] = ld_r(1, z - 1 + D);
-    Vec4<float> o1, o2, o3, o4;
-    if (z <= ze) sweep(0, z, B(M1{}), B(Z{}), B(P1{}), R(Z{}), 1, FIRST, qr[P % L], true, o1);
+    Vec4<float> o1, o2, o3, o4, o5;
+    // sweep k (k = 1..4) on plane z - k + 1 for planes in
+    // [Z0 - 4 - G + k, Z0 + zc + 3 + G - k]
+    if (z <= ze) sweep(0, z, B(M1{}), B(Z{}), B(P1{}), R(Z{}), 1, FIRST, qr[P % L], true, o1,
+                       RES && !FIRST ? xs_of(z) : nullptr);
     __syncthreads();
-    if (z - 1 >= Z0 - 2 && z - 1 <= ze - 1)
-      sweep(1, z - 1, R(M2{}), R(M1{}), R(Z{}), B(M1{}), 2, false, qb[(P - 1 + L) % L], true, o2);
+    if (z - 1 >= Z0 - 2 - G && z - 1 <= ze - 1)
+      sweep(1, z - 1, R(M2{}), R(M1{}), R(Z{}), B(M1{}), 2, false, qb[(P - 1 + L) % L], true, o2,
+            nullptr);
     __syncthreads();
-    if (z - 2 >= Z0 - 1 && z - 2 <= ze - 2)
-      sweep(0, z - 2, B(M3{}), B(M2{}), B(M1{}), R(M2{}), 3, false, qr[(P - 2 + L) % L], true, o3);
-    put(0, z - 2, z - 2 >= Z0 && z - 2 < Z0 + zc, o3);
+    if (z - 2 >= Z0 - 1 - G && z - 2 <= ze - 2)
+      sweep(0, z - 2, B(M3{}), B(M2{}), B(M1{}), R(M2{}), 3, false, qr[(P - 2 + L) % L], true, o3,
+            nullptr);
+    if constexpr (RES) q3[P % 3] = o3;   // red result of plane z - 2, for the residual at step z + 2
+    else put(eout, 0, z - 2, z - 2 >= Z0 && z - 2 < Z0 + zc, o3);
     __syncthreads();
-    const bool last = z - 3 >= Z0 && z - 3 < Z0 + zc;
-    if (last)
-      sweep(1, z - 3, R(M4{}), R(M3{}), R(M2{}), nullptr, 4, false, qb[(P - 3 + L) % L], false, o4);
-    put(1, z - 3, last, o4);
+    if (z - 3 >= Z0 - G && z - 3 <= ze - 3)
+      sweep(1, z - 3, R(M4{}), R(M3{}), R(M2{}), B(M3{}), 4, false, qb[(P - 3 + L) % L], RES, o4,
+            nullptr);
+    put(eout, 1, z - 3, z - 3 >= Z0 && z - 3 < Z0 + zc, o4);
+    if constexpr (RES) {
+      // red residual of plane z - 4: black results of planes z - 5 (q4,
+      // two steps ago) and z - 3 (o4), red result and r of plane z - 4
+      const bool vr = z - 4 >= Z0 && z - 4 < Z0 + zc;
+      if (vr) resid(z - 4, B(M4{}), q4[(P + 1) % 3], o4, q3[(P + 1) % 3], q5r[(P + 1) % 3], o5);
+      put(tout, 0, z - 4, vr, o5);
+      q4[P % 3] = o4;
+      if (!FIRST && z <= ze) stage_black(z + 2, hold, holdx);
+    }
     __syncthreads();
   };
   // whole groups of 6 steps (steps past ze only load)
@@ -1780,28 +1856,36 @@ static int sweep4_chunk(int n, int tx) {
 static Box whole_mesh(int n) { return Box{{0, 0, 0}, {n - 1, n - 1, n - 1}}; }
 
 void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
-                    bool first, bool fused, hipStream_t st) {
+                    bool first, bool fused, float* t, float inv_scale, float kappa, hipStream_t st) {
   if (fused) {
     // 128 x 32-cell columns (one 768-thread workgroup per compute unit: 138
-    // KB of LDS); 64 x 32 on a 64^3 mesh
+    // KB of LDS, 160 KB with the residual); 64 x 32 on a 64^3 mesh
     const int tx = n >= 128 ? 128 : 64;
     const int zc = sweep4_chunk(n, tx);
     const dim3 g((unsigned)((n / tx) * (n / 32) * (n / zc)));
+#define SDPM_SWEEP4(F, RS, UXX, NTT)                                                                \
+  hipLaunchKernelGGL((k_sweep4<F, RS, UXX, 32, NTT>), g, dim3(NTT), 0, st, e, e_out, r, n, zc, scale, \
+                     inv_diag, t, inv_scale, kappa)
     if (tx == 128) {
-      if (first)
-        hipLaunchKernelGGL((k_sweep4<true, 16, 32, 768>), g, dim3(768), 0, st, e, e_out, r, n, zc,
-                           scale, inv_diag);
+      if (first && t)
+        SDPM_SWEEP4(true, true, 16, 768);
+      else if (first)
+        SDPM_SWEEP4(true, false, 16, 768);
+      else if (t)
+        SDPM_SWEEP4(false, true, 16, 768);
       else
-        hipLaunchKernelGGL((k_sweep4<false, 16, 32, 768>), g, dim3(768), 0, st, e, e_out, r, n, zc,
-                           scale, inv_diag);
+        SDPM_SWEEP4(false, false, 16, 768);
     } else {
-      if (first)
-        hipLaunchKernelGGL((k_sweep4<true, 8, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc,
-                           scale, inv_diag);
+      if (first && t)
+        SDPM_SWEEP4(true, true, 8, 448);
+      else if (first)
+        SDPM_SWEEP4(true, false, 8, 448);
+      else if (t)
+        SDPM_SWEEP4(false, true, 8, 448);
       else
-        hipLaunchKernelGGL((k_sweep4<false, 8, 32, 448>), g, dim3(448), 0, st, e, e_out, r, n, zc,
-                           scale, inv_diag);
+        SDPM_SWEEP4(false, false, 8, 448);
     }
+#undef SDPM_SWEEP4
     return;
   }
   if (!first && e != e_out)
@@ -1810,6 +1894,9 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
   L.n = n;
   L.box = whole_mesh(n);
   sweep_run<float>(e_out, r, L, 1, 0, 4, first, scale, inv_diag, st);
+  if (t)
+    hipLaunchKernelGGL((k_resid_red_v4<float, 64>), v4_grid(L.box, 64), dim3(64, 4), 0, st, e_out, r,
+                       t, n, L.box, inv_scale, kappa);
 }
 
 // The fused form of pre or post sweeps on level L when it applies (FP32,
@@ -1818,7 +1905,7 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
 // reads e and writes e_alt, and the two swap.  False when it does not apply.
 template <typename T>
 static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, T scale, T inv_diag,
-                    hipStream_t st) {
+                    hipStream_t st, bool resid = false, T inv_scale = 0, T kappa = 0) {
   if constexpr (sizeof(T) != 4) {
     return false;
   } else {
@@ -1829,10 +1916,12 @@ static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, 
     const int id = level > 0 ? K_SWEEP4_COARSE : zero ? K_SWEEP4_FIRST : K_SWEEP4;
     prof_begin(st, id);
     float* out = zero ? (float*)L.e : (float*)L.e_alt;
-    launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true, st);
+    launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true,
+                   resid ? (float*)L.t : nullptr, inv_scale, kappa, st);
     if (!zero) std::swap(L.e, L.e_alt);
     // r read, e written (4 + 4 bytes per cell); without the zero guess the
-    // black half of e read too (2 more)
+    // black half of e read too (2 more); with the residual the red half of t
+    // written instead of the red half of e (the same 2)
     prof_end(st, id, (zero ? 8.0 : 10.0) * (double)box_cells(L.box));
     return true;
   }
@@ -1960,9 +2049,12 @@ const T* vcycle(Level* lv, int nlev_all, double kappa, int pre, int post, int co
     // on the finest level when the cycle continues from the correction
     // already there
     const bool zero = !(l == 0 && fine_start);
-    if (!sweeps4<T>(L, l, periodic, pre, zero, scale, inv_diag, st))
+    const T inv_scale = (T)(1.0 / std::ldexp(1.0, 2 * l));
+    // the fused pre-smoothing forms the red residual itself
+    if (!sweeps4<T>(L, l, periodic, pre, zero, scale, inv_diag, st, true, inv_scale, (T)kappa)) {
       sweep_run<T>((T*)L.e, r, L, l, 0, 2 * pre, zero, scale, inv_diag, st);
-    resid_red<T>((const T*)L.e, r, (T*)L.t, L, (T)(1.0 / std::ldexp(1.0, 2 * l)), (T)kappa, st);
+      resid_red<T>((const T*)L.e, r, (T*)L.t, L, inv_scale, (T)kappa, st);
+    }
     const Level& C = lv[l + 1];
     prof_begin(st, K_RESTRICT);
     restrict_level<T>(L, C, st);

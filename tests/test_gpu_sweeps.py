@@ -2,8 +2,10 @@
 one z-marching pass with its planes in LDS, against four single-colour
 launches on the same inputs (bit-identical over the whole array) and against
 red-black Gauss-Seidel written out here in FP64 from its definition, for the
-zero initial guess and a given one, at 64^3 .. 256^3 (chunks of 16 and 32
-planes, several tiles along every axis, periodic wrap at every face)."""
+zero initial guess and a given one, and in its pre-smoothing form with the
+red residual of the result (against the separate residual kernel, and the
+residual of the FP64 sweeps), at 64^3 .. 256^3 (chunks of 16 planes,
+several columns along every axis, periodic wrap at every face)."""
 import numpy as np
 import pytest
 
@@ -70,6 +72,47 @@ def test_fused_sweeps_match_single_colour_sweeps(n, first):
                     inv_diag, first)
         err = np.abs(_unsplit(a, n).astype(np.float64) - ref).max() / np.abs(ref).max()
         log(f"rb_sweeps n={n} first={first}: max error vs FP64 definition {err:.2e}")
+        assert err < 1e-5
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("first", [True, False])
+def test_fused_sweeps_with_residual(n, first):
+    # the pre-smoothing form: the red residual of the result goes to t (red
+    # half) and the fused pass leaves e's red half unwritten
+    import torch
+    import paper_1709_04703_amd as P
+
+    rng = np.random.Generator(np.random.PCG64(9000 + n))
+    e0 = rng.uniform(-1.0, 1.0, n**3).astype(np.float32)
+    r = rng.uniform(-1.0, 1.0, n**3).astype(np.float32)
+    scale, kappa_h2 = 4.0, 0.113
+    inv_diag = float(np.float32(1.0 / (6.0 + scale * kappa_h2)))
+    e_t = torch.as_tensor(e0).cuda()
+    r_t = torch.as_tensor(r).cuda()
+    fused, t_f = torch.full_like(e_t, float("nan")), torch.full_like(e_t, float("nan"))
+    single, t_s = e_t.clone(), torch.full_like(e_t, float("nan"))
+    P.rb_sweeps(n, e_t, fused, r_t, scale, inv_diag, first, True, t_f, kappa_h2)
+    P.rb_sweeps(n, e_t, single, r_t, scale, inv_diag, first, False, t_s, kappa_h2)
+    torch.cuda.synchronize()
+    h = n**3 // 2
+    a, b = fused.cpu().numpy(), single.cpu().numpy()
+    ta, tb = t_f.cpu().numpy(), t_s.cpu().numpy()
+    nd_e = int(np.count_nonzero(a[h:].view(np.uint32) != b[h:].view(np.uint32)))
+    nd_t = int(np.count_nonzero(ta[:h].view(np.uint32) != tb[:h].view(np.uint32)))
+    log(f"rb_sweeps + residual n={n} first={first}: black e {nd_e}, red t {nd_t} of {h} differ")
+    assert nd_e == 0 and nd_t == 0
+    assert np.isnan(ta[h:]).all()                    # black half of t not written
+    if n <= 128:
+        ref = _rbgs(_unsplit(e0, n).astype(np.float64), _unsplit(r, n).astype(np.float64), scale,
+                    inv_diag, first)
+        k, j, i = np.indices(ref.shape)
+        red = ((i + j + k) & 1) == 0
+        nb = sum(np.roll(ref, sh, axis=ax) for ax in range(3) for sh in (1, -1))
+        tref = _unsplit(r, n).astype(np.float64) - (nb - 6.0 * ref) / scale + kappa_h2 * ref
+        got = _unsplit(np.concatenate([ta[:h], np.zeros(h, np.float32)]), n).astype(np.float64)
+        err = np.abs(got[red] - tref[red]).max() / np.abs(tref[red]).max()
+        log(f"rb_sweeps + residual n={n} first={first}: max t error vs FP64 {err:.2e}")
         assert err < 1e-5
 
 

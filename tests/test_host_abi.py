@@ -139,11 +139,15 @@ def test_defaults(P):
 
 def test_rb_sweeps_argument_checks(P):
     # rejected before any launch: sizes outside [64, 2048] or not powers of
-    # two, NULL arrays, and the fused form writing the array it reads
+    # two, NULL arrays, the fused form writing the array it reads, and a
+    # residual output without a positive scale or aliasing another array
     lib = P.library()
-    buf = ctypes.c_void_p(16)
+    buf, out, t = ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48)
     for n in (32, 96, 4096):
-        assert lib.sdpm_rb_sweeps(n, buf, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, None, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, buf, None, buf, 1.0, 0.1, 1, 1, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, buf, buf, buf, 1.0, 0.1, 0, 1, None) == P.SDPM_EINVAL
+        assert lib.sdpm_rb_sweeps(n, buf, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, None, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, None, buf, 1.0, 0.1, 1, 1, None, 0.0, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, buf, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
+    # the residual needs scale > 0 and an array of its own
+    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 0.0, 0.1, 0, 1, t, 0.1, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 1.0, 0.1, 0, 1, out, 0.1, None) == P.SDPM_EINVAL
