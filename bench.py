@@ -36,8 +36,8 @@ The shrinking phase of the same run (steps 160-164 by default: lightcone
 removal, the frozen-exterior box and the lightcone output all active) is
 timed separately and reported as shrink_phase.
 In the timed steps only the launches of the roofline kernel (the finest level's
-fused four-sweep smoothing passes; the net's layers in the learned modes) carry HIP
-event pairs;
+fused four-sweep post-smoothing passes; the net's layers in the learned modes) carry
+HIP event pairs;
 --profile-steps further untimed steps (3) have every kernel bracketed for the
 per-kernel breakdown (kernel_ms_per_step, roofline.kernels).
 The oracle (FP64 NumPy/SciPy) is timed on a bounded sample as cpu_baseline.
@@ -110,8 +110,8 @@ def kernel_roofline(name, d):
 
 
 # The kernel with the largest share of GPU time in the step (the finest
-# level's fused four-sweep smoothing passes that continue from a correction:
-# 10 bytes per cell); its launches alone carry HIP events in the timed
+# level's fused four-sweep post-smoothing passes: 10 bytes per cell); its
+# launches alone carry HIP events in the timed
 # steps, since an event pair around every launch (~300 per step) would slow
 # the timed step itself.  The full per-kernel profile comes from further,
 # untimed steps, and names its own largest kernel.

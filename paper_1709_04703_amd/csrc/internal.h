@@ -327,6 +327,7 @@ enum KernelId : int {
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
   K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK, K_SWEEP4, K_SWEEP4_FIRST, K_SWEEP4_COARSE,
+  K_SWEEP4_RESID,
   K_NKERNELS
 };
 static_assert(K_NKERNELS <= 64, "the profiler's kernel mask holds 64 kernels");

@@ -1913,7 +1913,10 @@ static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, 
     bool whole = true;
     for (int d = 0; d < 3; ++d) whole = whole && L.box.lo[d] == fb.lo[d] && L.box.hi[d] == fb.hi[d];
     if (nsweeps != 2 || !periodic || !whole || L.n < kSweep4Min || !L.e_alt) return false;
-    const int id = level > 0 ? K_SWEEP4_COARSE : zero ? K_SWEEP4_FIRST : K_SWEEP4;
+    // ids: coarser levels; the finest level's passes from the zero guess
+    // (with the residual), continuing with the residual (pre-smoothing of a
+    // further cycle) and without it (post-smoothing)
+    const int id = level > 0 ? K_SWEEP4_COARSE : zero ? K_SWEEP4_FIRST : resid ? K_SWEEP4_RESID : K_SWEEP4;
     prof_begin(st, id);
     float* out = zero ? (float*)L.e : (float*)L.e_alt;
     launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true,
