@@ -80,9 +80,9 @@ def log(msg):
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
 # Valid only for the kernel source it was measured on: sweep4_fused is the 512^3 level's
-# fused smoothing pass continuing from a correction, 600350.3 KiB fetched (x 1.99992 for the
-# copy's 524307.9 KiB per GiB) and 534547.5 KiB written per dispatch.
-MEASURED_TRAFFIC = {}
+# fused post-smoothing pass, 606995.1 KiB fetched (x 1.99989 for the copy's 524315.8 KiB per
+# GiB) and 534464.6 KiB written per dispatch.
+MEASURED_TRAFFIC = {"sweep4_fused": 1790351936}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
