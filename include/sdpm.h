@@ -365,11 +365,15 @@ int sdpm_ade_sweep(sdpm_ctx* ctx, double lam, int forward);
  * then does not write the red half of e_out (the V-cycle does not read it
  * before the post-smoothing sets it anew), the other writes it and t_out by
  * a separate launch; t_out's red half and e_out's black half are
- * bit-identical between the two.  SDPM_EINVAL also for t_out with
- * scale <= 0 or aliasing another array.                                    */
+ * bit-identical between the two.  box (NULL: the periodic whole mesh):
+ * lo[3], hi[3] of a frozen-exterior box (the shrinking domain's index box,
+ * Sec. 2.4), 1 <= lo <= hi <= n - 2 per axis; e is zero outside it and stays
+ * zero (the correction's homogeneous Dirichlet condition), only its cells
+ * are swept.  SDPM_EINVAL also for t_out with scale <= 0 or aliasing another
+ * array, or a box that reaches a face of the mesh.                         */
 int sdpm_rb_sweeps(int32_t n, const float* e, float* e_out, const float* r, float scale,
                    float inv_diag, int32_t first, int32_t fused, float* t_out, float kappa_h2,
-                   void* stream);
+                   const int32_t* box, void* stream);
 /* Re-sort of the active particles (all SoA arrays permuted together by the
  * key of sort_shift: the Morton code of the cell's block, then its row
  * inside the block; stable LSD radix sort).  Results of the step do not

@@ -161,7 +161,7 @@ def library() -> ctypes.CDLL:
         "sdpm_lightcone_count": [vp, P(i64)],
         "sdpm_ade_sweep": [vp, dbl, i32],
         "sdpm_rb_sweeps": [i32, vp, vp, vp, ctypes.c_float, ctypes.c_float, i32, i32, vp,
-                           ctypes.c_float, vp],
+                           ctypes.c_float, P(i32), vp],
         "sdpm_pk_workspace_bytes": [i32, P(i64)],
         "sdpm_power_spectrum": [P(vp), i64, dbl, i32, i32, vp, i64, vp, P(dbl), P(dbl), P(dbl),
                                 P(i64)],
@@ -244,14 +244,18 @@ def conv3d(n, inp, w, bias, flags, mask, out):
 
 
 def rb_sweeps(n, e, e_out, r, scale: float, inv_diag: float, first: bool, fused: bool,
-              t_out=None, kappa_h2: float = 0.0):
-    """Four red-black half sweeps on a periodic FP32 level in colour-split
-    storage, and with t_out the red residual of the result (see
-    sdpm_rb_sweeps); torch device tensors of n^3 floats (e may be None when
-    first)."""
+              t_out=None, kappa_h2: float = 0.0, box=None):
+    """Four red-black half sweeps on an FP32 level in colour-split storage
+    (periodic, or over the frozen-exterior box (lo, hi)), and with t_out the
+    red residual of the result (see sdpm_rb_sweeps); torch device tensors of
+    n^3 floats (e may be None when first)."""
+    bx = None
+    if box is not None:
+        lo, hi = box
+        bx = (ctypes.c_int32 * 6)(*lo, *hi)
     check(library().sdpm_rb_sweeps(n, _ptr(e), _ptr(e_out), _ptr(r), scale, inv_diag,
                                    1 if first else 0, 1 if fused else 0, _ptr(t_out), kappa_h2,
-                                   _stream()))
+                                   bx, _stream()))
 
 
 def pk_workspace_bytes(ng: int) -> int:

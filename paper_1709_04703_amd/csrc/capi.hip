@@ -365,6 +365,7 @@ void clear_levels(sdpm_ctx* c) {
     const Box fb = full_box(c->lv[l].n);
     launch_fill<T>((T*)c->lv[l].e, c->lv[l].n, fb, (T)0, c->st);
     launch_fill<T>((T*)c->lv[l].t, c->lv[l].n, fb, (T)0, c->st);
+    if (c->lv[l].e_alt) launch_fill<T>((T*)c->lv[l].e_alt, c->lv[l].n, fb, (T)0, c->st);
   }
 }
 
@@ -1478,15 +1479,24 @@ int sdpm_conv3d(int32_t n, const void* in_bf16, const float* w, const float* bia
 
 int sdpm_rb_sweeps(int32_t n, const float* e, float* e_out, const float* r, float scale,
                    float inv_diag, int32_t first, int32_t fused, float* t_out, float kappa_h2,
-                   void* stream) {
+                   const int32_t* box, void* stream) {
   if (n < 64 || n > 2048 || (n & (n - 1)) || !e_out || !r || (!first && !e))
     return fail(nullptr, SDPM_EINVAL, "rb_sweeps: n a power of two in [64, 2048], pointers non-NULL");
   if (fused && !first && e == e_out)
     return fail(nullptr, SDPM_EINVAL, "rb_sweeps: the fused form needs e_out != e");
   if (t_out && (!(scale > 0.0f) || t_out == e_out || t_out == e || t_out == r))
     return fail(nullptr, SDPM_EINVAL, "rb_sweeps: t_out needs scale > 0 and its own array");
+  Box b{};
+  if (box) {
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = box[d];
+      b.hi[d] = box[3 + d];
+      if (b.lo[d] < 1 || b.hi[d] > n - 2 || b.hi[d] < b.lo[d])
+        return fail(nullptr, SDPM_EINVAL, "rb_sweeps: the box must keep a plane from every face");
+    }
+  }
   launch_sweeps4(e, e_out, r, n, scale, inv_diag, first != 0, fused != 0, t_out,
-                 t_out ? 1.0f / scale : 0.0f, kappa_h2, (hipStream_t)stream);
+                 t_out ? 1.0f / scale : 0.0f, kappa_h2, box ? &b : nullptr, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SDPM_OK : fail(nullptr, SDPM_EHIP, "rb_sweeps launch failed");
 }
 

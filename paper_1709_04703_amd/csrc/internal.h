@@ -171,8 +171,8 @@ void launch_ade_sweep(double* phi, const double* f, int n, const Box& b, bool pe
 template <typename T>
 const T* vcycle(Level* lv, int nlev, double kappa, int pre, int post, int coarse_sweeps,
                 bool periodic, bool fine_start, hipStream_t st);
-// Whether a level of n cells a side takes the fused four-sweep kernel when
-// periodic (FP32 only; smaller levels run too few workgroups for it).
+// Whether a level of n cells a side takes the fused four-sweep kernel (FP32
+// only; smaller levels run too few workgroups for it).
 constexpr int kSweep4Min = 256;
 // Four colour sweeps (red, black, red, black) of a periodic FP32 level of
 // n^3 cells, n a power of two >= 64: with fused, one k_sweep4 pass from e
@@ -182,8 +182,12 @@ constexpr int kSweep4Min = 256;
 // red residual of the result goes to t's red half (inv_scale = 1 / scale,
 // kappa = kappa h^2): in the fused pass instead of the red half of e_out,
 // which it then leaves unwritten; otherwise by k_resid_red_v4.
+// With box (may be null: the periodic whole mesh) the sweeps cover a
+// frozen-exterior box that keeps at least one plane from every face of the
+// mesh, e being zero outside it.
 void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
-                    bool first, bool fused, float* t, float inv_scale, float kappa, hipStream_t st);
+                    bool first, bool fused, float* t, float inv_scale, float kappa, const Box* box,
+                    hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Launchers, particle kernels (particles.hip).

@@ -696,10 +696,11 @@ struct StepPhase {
   static constexpr int value = V;
 };
 
-template <bool FIRST, bool RES, int UX, int TY, int NT>
+template <bool FIRST, bool RES, bool BOX, int UX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* __restrict__ r, int n,
-         int zc, float scale, float inv_diag, float* __restrict__ tout, float inv_scale, float kappa) {
+         int zc, float scale, float inv_diag, float* __restrict__ tout, float inv_scale, float kappa,
+         Box b) {
   constexpr int G = RES ? 1 : 0;                 // the residual: one more stage
   constexpr int HY = 4 + G;                      // halo rows per side
   constexpr int U = UX + 2, HW = 4 * U, RY = TY + 2 * HY, PL = RY * HW;   // region: U units x RY rows
@@ -711,12 +712,41 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   __shared__ float ldsx[RES ? NB * 2 * RY : 1];   // black input just outside the region in x
   const int hn = n >> 1, m = n - 1, hm = hn - 1;
   const int64_t oth = (int64_t)n * n * hn, pls = (int64_t)n * hn;
-  const Tile tl = tile_of(n / (8 * UX), n / TY);
-  const int H0 = tl.bx * 4 * UX, Y0 = tl.by * TY, Z0 = tl.bz * zc;
+  // columns over the mesh, or with BOX over the box (from its first
+  // 4-aligned half index, row and plane)
+  const int hb = BOX ? ((b.lo[0] >> 1) & ~3) : 0;
+  const Tile tl = BOX ? tile_of(((b.hi[0] >> 1) - hb + 4 * UX) / (4 * UX), (b.hi[1] - b.lo[1] + TY) / TY)
+                      : tile_of(n / (8 * UX), n / TY);
+  const int H0 = hb + tl.bx * 4 * UX, Y0 = (BOX ? b.lo[1] : 0) + tl.by * TY;
+  const int Z0 = (BOX ? b.lo[2] : 0) + tl.bz * zc;
+  const int zend = BOX ? min(Z0 + zc, b.hi[2] + 1) : Z0 + zc;   // output planes [Z0, zend)
   const int tid = threadIdx.x;
   const bool ok = tid < ITEMS;
   const int y = ok ? tid / U : 0, u = ok ? tid % U : 0;
   const int jj = (Y0 - HY + y) & m;
+  // with BOX every value outside the box is 0 (homogeneous Dirichlet
+  // correction): staged inputs and computed values are masked per cell, by
+  // the unwrapped coordinates (the box keeps one plane from the mesh's
+  // faces, so a wrapped index always lies outside it)
+  const int hu = H0 - 4 + 4 * u, ju = Y0 - HY + y;
+  const bool rowin = !BOX || (ju >= b.lo[1] && ju <= b.hi[1]);
+  auto mask = [&](int c, int z, int h, Vec4<float>& v) {
+    if constexpr (BOX) {
+      const bool in = rowin && z >= b.lo[2] && z <= b.hi[2];
+      const int p = (c + jj + (z & m)) & 1;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int x = 2 * (h + w) + p;
+        if (!(in && x >= b.lo[0] && x <= b.hi[0])) v.v[w] = 0.f;
+      }
+    }
+  };
+  auto mask1 = [&](int c, int z, int h, float& v) {   // one entry at half index h
+    if constexpr (BOX) {
+      const int x = 2 * h + ((c + jj + (z & m)) & 1);
+      if (!(rowin && z >= b.lo[2] && z <= b.hi[2] && x >= b.lo[0] && x <= b.hi[0])) v = 0.f;
+    }
+  };
   const int jh = jj * hn + ((H0 - 4 + 4 * u) & hm);   // row and half index of the unit
   const int base = 4 * tid;                            // its place in an LDS plane
   // the other colour's entry next to the unit (clamped to the region: at
@@ -727,7 +757,10 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
   const int xhi = y * HW + min(4 * u + 4, HW - 1);
   const bool edge_l = u == 0, edge_r = u == U - 1;
   const int jx = jj * hn + (edge_r ? ((H0 - 4 + 4 * U) & hm) : ((H0 - 5) & hm));
-  const bool outp = y >= HY && y < HY + TY && u >= 1 && u <= UX;
+  // output units: the column's, and with BOX only those in the box's rows
+  // and overlapping its x range (others would wrap onto cells of the box)
+  const bool outp = y >= HY && y < HY + TY && u >= 1 && u <= UX &&
+                    (!BOX || (rowin && hu + 3 >= (b.lo[0] >> 1) && hu <= (b.hi[0] >> 1)));
   // plane z of the black ring in slot (z - Z0 + 24) mod 6, with RES
   // (z - Z0 + 28) mod 7 (one more plane: the residual's)
   auto bs = [&](int z) { return ldsb + ((z - Z0 + (RES ? 28 : 24)) % NB) * PL; };
@@ -769,6 +802,7 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
         ov.v[w] = (xc.v[w] + side + ym.v[w] + yp.v[w] + zm.v[w] + zp.v[w] - scale * rv.v[w]) * inv_diag;
       }
     }
+    mask(c, z, hu, ov);
     if (keep) *(Vec4<float>*)(dst + base) = ov;
   };
   // red residual t = r - A e on plane z (rows [HY, RY - HY)) with the
@@ -788,6 +822,7 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
       const float nb = xc.v[w] + side + ym.v[w] + yp.v[w] + bm.v[w] + bp.v[w];
       ov.v[w] = rv.v[w] - (nb - 6.0f * ctr.v[w]) * inv_scale + kappa * ctr.v[w];
     }
+    mask(0, z, hu, ov);
   };
   auto put = [&](float* dst, int c, int z, bool valid, const Vec4<float>& ov) {
     const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(
@@ -798,10 +833,14 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
     const unsigned off = (valid && outp) ? (unsigned)jh * 4u : 0x80000000u;
     __builtin_amdgcn_raw_buffer_store_b128(d, rsc, off, 0, 2 /* non-temporal */);
   };
-  auto stage_black = [&](int z, const Vec4<float>& v, float vx) {
+  auto stage_black = [&](int z, Vec4<float> v, float vx) {
     if (!ok) return;
+    mask(1, z, hu, v);
     *(Vec4<float>*)(bs(z) + base) = v;
-    if (RES && (edge_l || edge_r)) xs_of(z)[(edge_r ? RY : 0) + y] = vx;
+    if (RES && (edge_l || edge_r)) {
+      mask1(1, z, edge_r ? H0 - 4 + 4 * U : H0 - 5, vx);
+      xs_of(z)[(edge_r ? RY : 0) + y] = vx;
+    }
   };
   // input black planes zs - 1 .. zs + 1 into LDS; queues: red r planes
   // zs - 2 .. zs + D - 1, black r planes zs - 3 .. zs + D - 2, black e
@@ -843,7 +882,11 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
     if (!FIRST) {
       hold = qe[(P + 2) % L];
       if constexpr (RES) holdx = qx[(P + 2) % L];
-      if (!RES && ok && z <= ze) *(Vec4<float>*)(B(P2{}) + base) = hold;
+      if (!RES && ok && z <= ze) {
+        Vec4<float> v = hold;
+        mask(1, z + 2, hu, v);
+        *(Vec4<float>*)(B(P2{}) + base) = v;
+      }
       qe[(P + 2) % L] = ld_e(z + 2 + L);
       if constexpr (RES) qx[(P + 2) % L] = ld_x(z + 2 + L);
     }
@@ -864,16 +907,16 @@ k_sweep4(const float* __restrict__ ein, float* __restrict__ eout, const float* _
       sweep(0, z - 2, B(M3{}), B(M2{}), B(M1{}), R(M2{}), 3, false, qr[(P - 2 + L) % L], true, o3,
             nullptr);
     if constexpr (RES) q3[P % 3] = o3;   // red result of plane z - 2, for the residual at step z + 2
-    else put(eout, 0, z - 2, z - 2 >= Z0 && z - 2 < Z0 + zc, o3);
+    else put(eout, 0, z - 2, z - 2 >= Z0 && z - 2 < zend, o3);
     __syncthreads();
     if (z - 3 >= Z0 - G && z - 3 <= ze - 3)
       sweep(1, z - 3, R(M4{}), R(M3{}), R(M2{}), B(M3{}), 4, false, qb[(P - 3 + L) % L], RES, o4,
             nullptr);
-    put(eout, 1, z - 3, z - 3 >= Z0 && z - 3 < Z0 + zc, o4);
+    put(eout, 1, z - 3, z - 3 >= Z0 && z - 3 < zend, o4);
     if constexpr (RES) {
       // red residual of plane z - 4: black results of planes z - 5 (q4,
       // two steps ago) and z - 3 (o4), red result and r of plane z - 4
-      const bool vr = z - 4 >= Z0 && z - 4 < Z0 + zc;
+      const bool vr = z - 4 >= Z0 && z - 4 < zend;
       if (vr) resid(z - 4, B(M4{}), q4[(P + 1) % 3], o4, q3[(P + 1) % 3], q5r[(P + 1) % 3], o5);
       put(tout, 0, z - 4, vr, o5);
       q4[P % 3] = o4;
@@ -1842,49 +1885,60 @@ static void sweep_run(T* e, const T* r, const Level& L, int level, int c0, int n
   if (group) prof_end(st, K_SMOOTH, n * 1.5 * sizeof(T) * (double)box_cells(L.box), n);
 }
 
-// Planes per workgroup of the fused sweeps on columns tx cells wide and 32
-// rows: one workgroup per compute unit (256; each chunk recomputes 6
-// warm-up planes), at least 16 planes (512^3: 128 planes, 0.31 ms against
+// Planes per workgroup of the fused sweeps over `cols` columns and nz
+// planes: about one workgroup per compute unit (256; each chunk recomputes
+// 6 warm-up planes), at least 16 planes (512^3: 128 planes, 0.31 ms against
 // 0.33 ms with 64; 256^3: 16 planes, 48 us against 65 us with 32).
-static int sweep4_chunk(int n, int tx) {
-  const int64_t per = (int64_t)n * n * n / ((int64_t)tx * 32 * 256);
+static int sweep4_chunk(int cols, int nz) {
+  const int per = std::max(1, cols * nz / 256);
   int zc = 16;
-  while (zc < n && zc < per) zc <<= 1;
+  while (zc < nz && zc < per) zc <<= 1;
   return zc;
 }
 
 static Box whole_mesh(int n) { return Box{{0, 0, 0}, {n - 1, n - 1, n - 1}}; }
 
 void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float scale, float inv_diag,
-                    bool first, bool fused, float* t, float inv_scale, float kappa, hipStream_t st) {
+                    bool first, bool fused, float* t, float inv_scale, float kappa, const Box* box,
+                    hipStream_t st) {
+  const Box b = box ? *box : whole_mesh(n);
   if (fused) {
     // 128 x 32-cell columns (one 768-thread workgroup per compute unit: 138
     // KB of LDS, 160 KB with the residual); 64 x 32 on a 64^3 mesh
     const int tx = n >= 128 ? 128 : 64;
-    const int zc = sweep4_chunk(n, tx);
-    const dim3 g((unsigned)((n / tx) * (n / 32) * (n / zc)));
-#define SDPM_SWEEP4(F, RS, UXX, NTT)                                                                \
-  hipLaunchKernelGGL((k_sweep4<F, RS, UXX, 32, NTT>), g, dim3(NTT), 0, st, e, e_out, r, n, zc, scale, \
-                     inv_diag, t, inv_scale, kappa)
+    const int ux = tx / 8;
+    const int hb = box ? ((b.lo[0] >> 1) & ~3) : 0;
+    const int gx = box ? ((b.hi[0] >> 1) - hb + 4 * ux) / (4 * ux) : n / tx;
+    const int gy = box ? (b.hi[1] - b.lo[1] + 32) / 32 : n / 32;
+    const int nz = b.hi[2] - b.lo[2] + 1;
+    const int zc = sweep4_chunk(gx * gy, nz);
+    const dim3 g((unsigned)(gx * gy * ((nz + zc - 1) / zc)));
+#define SDPM_SWEEP4(F, RS, BX, UXX, NTT)                                                              \
+  hipLaunchKernelGGL((k_sweep4<F, RS, BX, UXX, 32, NTT>), g, dim3(NTT), 0, st, e, e_out, r, n, zc,    \
+                     scale, inv_diag, t, inv_scale, kappa, b)
+#define SDPM_SWEEP4_W(BX, UXX, NTT)               \
+  do {                                            \
+    if (first && t)                               \
+      SDPM_SWEEP4(true, true, BX, UXX, NTT);      \
+    else if (first)                               \
+      SDPM_SWEEP4(true, false, BX, UXX, NTT);     \
+    else if (t)                                   \
+      SDPM_SWEEP4(false, true, BX, UXX, NTT);     \
+    else                                          \
+      SDPM_SWEEP4(false, false, BX, UXX, NTT);    \
+  } while (0)
     if (tx == 128) {
-      if (first && t)
-        SDPM_SWEEP4(true, true, 16, 768);
-      else if (first)
-        SDPM_SWEEP4(true, false, 16, 768);
-      else if (t)
-        SDPM_SWEEP4(false, true, 16, 768);
+      if (box)
+        SDPM_SWEEP4_W(true, 16, 768);
       else
-        SDPM_SWEEP4(false, false, 16, 768);
+        SDPM_SWEEP4_W(false, 16, 768);
     } else {
-      if (first && t)
-        SDPM_SWEEP4(true, true, 8, 448);
-      else if (first)
-        SDPM_SWEEP4(true, false, 8, 448);
-      else if (t)
-        SDPM_SWEEP4(false, true, 8, 448);
+      if (box)
+        SDPM_SWEEP4_W(true, 8, 448);
       else
-        SDPM_SWEEP4(false, false, 8, 448);
+        SDPM_SWEEP4_W(false, 8, 448);
     }
+#undef SDPM_SWEEP4_W
 #undef SDPM_SWEEP4
     return;
   }
@@ -1892,11 +1946,21 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
     hipMemcpyAsync(e_out, e, (size_t)n * n * n * sizeof(float), hipMemcpyDeviceToDevice, st);
   Level L{};
   L.n = n;
-  L.box = whole_mesh(n);
+  L.box = b;
   sweep_run<float>(e_out, r, L, 1, 0, 4, first, scale, inv_diag, st);
-  if (t)
-    hipLaunchKernelGGL((k_resid_red_v4<float, 64>), v4_grid(L.box, 64), dim3(64, 4), 0, st, e_out, r,
-                       t, n, L.box, inv_scale, kappa);
+  if (t) {
+    const int txv = v4_threads(b);
+    const dim3 g = v4_grid(b, txv);
+    if (txv == 64)
+      hipLaunchKernelGGL((k_resid_red_v4<float, 64>), g, dim3(64, 4), 0, st, e_out, r, t, n, b,
+                         inv_scale, kappa);
+    else if (txv == 32)
+      hipLaunchKernelGGL((k_resid_red_v4<float, 32>), g, dim3(32, 8), 0, st, e_out, r, t, n, b,
+                         inv_scale, kappa);
+    else
+      hipLaunchKernelGGL((k_resid_red_v4<float, 16>), g, dim3(16, 16), 0, st, e_out, r, t, n, b,
+                         inv_scale, kappa);
+  }
 }
 
 // The fused form of pre or post sweeps on level L when it applies (FP32,
@@ -1912,7 +1976,11 @@ static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, 
     const Box fb = whole_mesh(L.n);
     bool whole = true;
     for (int d = 0; d < 3; ++d) whole = whole && L.box.lo[d] == fb.lo[d] && L.box.hi[d] == fb.hi[d];
-    if (nsweeps != 2 || !periodic || !whole || L.n < kSweep4Min || !L.e_alt) return false;
+    // a frozen-exterior box (which keeps a plane from every face) with at
+    // least 128^3 cells; periodic levels are whole
+    if (nsweeps != 2 || L.n < kSweep4Min || !L.e_alt || (periodic && !whole) ||
+        (!periodic && box_cells(L.box) < (int64_t)1 << 21))
+      return false;
     // ids: coarser levels; the finest level's passes from the zero guess
     // (with the residual), continuing with the residual (pre-smoothing of a
     // further cycle) and without it (post-smoothing)
@@ -1920,7 +1988,7 @@ static bool sweeps4(Level& L, int level, bool periodic, int nsweeps, bool zero, 
     prof_begin(st, id);
     float* out = zero ? (float*)L.e : (float*)L.e_alt;
     launch_sweeps4((const float*)L.e, out, (const float*)L.r, L.n, scale, inv_diag, zero, true,
-                   resid ? (float*)L.t : nullptr, inv_scale, kappa, st);
+                   resid ? (float*)L.t : nullptr, inv_scale, kappa, periodic ? nullptr : &L.box, st);
     if (!zero) std::swap(L.e, L.e_alt);
     // r read, e written (4 + 4 bytes per cell); without the zero guess the
     // black half of e read too (2 more); with the residual the red half of t

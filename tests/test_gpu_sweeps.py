@@ -116,6 +116,67 @@ def test_fused_sweeps_with_residual(n, first):
         assert err < 1e-5
 
 
+def _rbgs_box(e, r, scale, inv_diag, first, lo, hi):
+    """_rbgs with e = 0 outside the box lo..hi (inclusive, (x, y, z)) and
+    only its cells swept."""
+    k, j, i = np.indices(r.shape)
+    inside = ((i >= lo[0]) & (i <= hi[0]) & (j >= lo[1]) & (j <= hi[1]) & (k >= lo[2]) & (k <= hi[2]))
+    e = np.where(inside, 0.0 if first else e, 0.0)
+    red = ((i + j + k) & 1) == 0
+    for colour in (red, ~red, red, ~red):
+        nb = sum(np.roll(e, s_, axis=a) for a in range(3) for s_ in (1, -1))
+        upd = colour & inside
+        e[upd] = ((nb - scale * r) * inv_diag)[upd]
+    return e, inside
+
+
+@pytest.mark.parametrize("n,lo,hi", [(128, (5, 9, 3), (118, 101, 124)),
+                                     (256, (17, 1, 30), (230, 254, 201))])
+@pytest.mark.parametrize("first,resid", [(True, True), (False, True), (False, False)])
+def test_fused_sweeps_on_a_frozen_exterior_box(n, lo, hi, first, resid):
+    # the shrinking domain's levels: e is zero outside the box and stays so
+    import torch
+    import paper_1709_04703_amd as P
+
+    rng = np.random.Generator(np.random.PCG64(7000 + n + 2 * first + resid))
+    k, j, i = np.indices((n, n, n))
+    inside = ((i >= lo[0]) & (i <= hi[0]) & (j >= lo[1]) & (j <= hi[1]) & (k >= lo[2]) & (k <= hi[2]))
+    e_full = np.where(inside, rng.uniform(-1.0, 1.0, (n, n, n)), 0.0).astype(np.float32)
+    e0 = _split(e_full)
+    r = rng.uniform(-1.0, 1.0, n**3).astype(np.float32)
+    scale, kappa_h2 = 1.0, 0.113
+    inv_diag = float(np.float32(1.0 / (6.0 + scale * kappa_h2)))
+    e_t, r_t = torch.as_tensor(e0).cuda(), torch.as_tensor(r).cuda()
+    fused, single = torch.zeros_like(e_t), e_t.clone()
+    t_f = torch.zeros_like(e_t) if resid else None
+    t_s = torch.zeros_like(e_t) if resid else None
+    P.rb_sweeps(n, e_t, fused, r_t, scale, inv_diag, first, True, t_f, kappa_h2, box=(lo, hi))
+    P.rb_sweeps(n, e_t, single, r_t, scale, inv_diag, first, False, t_s, kappa_h2, box=(lo, hi))
+    torch.cuda.synchronize()
+    h = n**3 // 2
+    a, b = fused.cpu().numpy(), single.cpu().numpy()
+    part = slice(h, None) if resid else slice(None)        # with the residual: black e only
+    nd = int(np.count_nonzero(a[part].view(np.uint32) != b[part].view(np.uint32)))
+    msg = f"rb_sweeps box n={n} first={first} resid={resid}: e {nd}"
+    if resid:
+        ta, tb = t_f.cpu().numpy(), t_s.cpu().numpy()
+        ndt = int(np.count_nonzero(ta[:h].view(np.uint32) != tb[:h].view(np.uint32)))
+        msg += f", t {ndt}"
+        nd += ndt
+    log(msg + " entries differ")
+    assert nd == 0
+    out = _unsplit(a, n)
+    if not resid:
+        assert np.all(out[~inside] == 0.0)               # the exterior stays zero
+    if n <= 128:
+        ref, ins = _rbgs_box(_unsplit(e0, n).astype(np.float64), _unsplit(r, n).astype(np.float64),
+                             scale, inv_diag, first, lo, hi)
+        sel = ins if not resid else ins & (((i + j + k) & 1) == 1)
+        err = np.abs(out[sel].astype(np.float64) - ref[sel]).max() / np.abs(ref[sel]).max()
+        log(f"rb_sweeps box n={n}: max error vs FP64 {err:.2e}")
+        assert err < 1e-5
+
+
 def test_fused_sweeps_in_place_first():
     # from the zero guess the fused pass may write the array it was given
     import torch

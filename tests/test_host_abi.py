@@ -144,10 +144,14 @@ def test_rb_sweeps_argument_checks(P):
     lib = P.library()
     buf, out, t = ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48)
     for n in (32, 96, 4096):
-        assert lib.sdpm_rb_sweeps(n, buf, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, None, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, buf, None, buf, 1.0, 0.1, 1, 1, None, 0.0, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, buf, buf, buf, 1.0, 0.1, 0, 1, None, 0.0, None) == P.SDPM_EINVAL
+        assert lib.sdpm_rb_sweeps(n, buf, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, None, out, buf, 1.0, 0.1, 0, 1, None, 0.0, None, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, None, buf, 1.0, 0.1, 1, 1, None, 0.0, None, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, buf, buf, 1.0, 0.1, 0, 1, None, 0.0, None, None) == P.SDPM_EINVAL
     # the residual needs scale > 0 and an array of its own
-    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 0.0, 0.1, 0, 1, t, 0.1, None) == P.SDPM_EINVAL
-    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 1.0, 0.1, 0, 1, out, 0.1, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 0.0, 0.1, 0, 1, t, 0.1, None, None) == P.SDPM_EINVAL
+    assert lib.sdpm_rb_sweeps(64, buf, out, buf, 1.0, 0.1, 0, 1, out, 0.1, None, None) == P.SDPM_EINVAL
+    # a box must keep a plane from every face
+    for bad in ((0, 1, 1, 10, 10, 10), (1, 1, 1, 63, 10, 10), (5, 5, 5, 4, 10, 10)):
+        bx = (ctypes.c_int32 * 6)(*bad)
+        assert lib.sdpm_rb_sweeps(64, buf, out, buf, 1.0, 0.1, 0, 1, None, 0.0, bx, None) == P.SDPM_EINVAL
