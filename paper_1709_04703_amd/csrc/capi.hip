@@ -431,6 +431,32 @@ int sync_norms(sdpm_ctx* c) {
   return sync_scalars(c, 0);
 }
 
+// Copies the four sums of the residual estimate (dscal[kEstSlot ..]) to
+// hpin[kEstSlot ..] and waits.
+int sync_estimate(sdpm_ctx* c) {
+  HIP_TRY(c, hipMemcpyAsync(c->hpin + kEstSlot, c->dscal + kEstSlot, 4 * sizeof(double),
+                            hipMemcpyDeviceToHost, c->st));
+  return sync_scalars(c, 0);
+}
+
+// Bound on the distance, in the 2-norm over the box, between the residual
+// estimate r_old - A e of launch_correct_est and the FP64 residual
+// rhs - A phi of launch_residual after the same correction, from the norms
+// of r_old (no), rhs (nb), the new phi (np) and e (ne): r_old carries the
+// rounding to T of its FP64 value (at most eps_T / 2 of it per cell); the
+// two FP64 residual evaluations, the estimate's own and the FP64 update of
+// phi add rounding of at most 9 unit roundoffs of the magnitudes of their
+// terms (rhs, r_old, and 12 + kappa times phi or e over the cell and its
+// six neighbours, taken as twice the box's norm for the neighbours outside
+// a Dirichlet box), bounded here with a factor of 16.
+template <typename T>
+double estimate_bound(double no, double nb, double np, double ne, double kappa) {
+  const double ut = 0.5 * (double)std::numeric_limits<T>::epsilon();
+  const double u = 0.5 * std::numeric_limits<double>::epsilon();
+  const double g16 = 16.0 * u / (1.0 - 16.0 * u);
+  return ut / (1.0 - ut) * no + g16 * (2.0 * nb + no + (12.0 + kappa) * (4.0 * np + 3.0 * ne));
+}
+
 uint32_t host_flags(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[0]; }
 uint32_t host_removed(sdpm_ctx* c) { return ((uint32_t*)(c->hpin + 16))[1]; }
 
@@ -670,15 +696,44 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
     for (int q = ahead ? 1 : 0; q < ncyc; ++q)
       e0 = vcycle<T>(c->lv, c->nlev, kappa, g.pre, g.post, g.coarse_sweeps, c->periodic != 0,
                      q > 0, c->st);
-    launch_correct<T>(c->fields.phi, e0, chg, pending, g.ng, b, c->st);
+    // Where the host waits after this iteration (the test below), the
+    // correction pass also estimates the new residual as r_old - A e; when
+    // the estimate with its bound is below the threshold, the FP64 residual
+    // would be too and its pass is skipped.
+    const bool wait = time_it || it + 1 >= g.max_outer || it + 1 - it_known >= kMaxAhead ||
+                      !(rn_known * std::pow(c->rho_est, cyc + ncyc - cyc_known) > kAheadMargin * thresh);
+    const bool est = wait && !time_it;
+    if (est) {
+      launch_correct_est<T>(c->fields.phi, e0, (const T*)c->lv[0].r, chg, pending, kappa, g.ng, b,
+                            c->partial, &nb, c->st);
+      launch_reduce_final(c->partial, nb, 4, c->dscal + kEstSlot, c->st);
+    } else {
+      launch_correct<T>(c->fields.phi, e0, chg, pending, g.ng, b, c->st);
+    }
     pending = 0.0;
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
-    launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
-                       &nb, c->st);
-    launch_reduce_final(c->partial, nb, 1, c->dscal + kNormSlot + (it % kNormRing), c->st);
+    bool met = false;
+    if (est) {
+      rc = sync_estimate(c);
+      if (rc) return rc;
+      const double ne = std::sqrt(c->hpin[kEstSlot]);
+      const double bound = estimate_bound<T>(std::sqrt(c->hpin[kEstSlot + 1]), bn,
+                                             std::sqrt(c->hpin[kEstSlot + 2]),
+                                             std::sqrt(c->hpin[kEstSlot + 3]), kappa);
+      if (std::isfinite(ne) && std::isfinite(bound) && (ne + bound) * (1.0 + 1e-9) <= thresh) {
+        met = true;
+        rn = ne;
+      }
+    }
+    if (!met) {
+      launch_residual<T>(c->fields.phi, c->fields.rhs, (T*)c->lv[0].r, g.ng, b, kappa, c->partial,
+                         &nb, c->st);
+      launch_reduce_final(c->partial, nb, 1, c->dscal + kNormSlot + (it % kNormRing), c->st);
+    }
     if (time_it) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
     ++it;
     cyc += ncyc;
+    if (met) break;
     const double pred = rn_known * std::pow(c->rho_est, cyc - cyc_known);
     if (!time_it && it < g.max_outer && it - it_known < kMaxAhead && pred > kAheadMargin * thresh)
       continue;

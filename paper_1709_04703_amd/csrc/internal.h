@@ -17,6 +17,8 @@ constexpr int kGateProbe = 8, kGateProbeMax = 256;   // solves skipped by the ne
 // host scalars: hpin[0..15] reduction results, [16..19] flags, [20] kept
 // count, [kHostNorm ..] the ring of per-iteration residual norms
 constexpr int kNormSlot = 16, kNormRing = 32, kHostNorm = 64, kHostScalars = 128;
+// the four sums of a residual estimate (launch_correct_est), in dscal and hpin
+constexpr int kEstSlot = 4;
 // run-ahead of the outer iterations: at most kMaxAhead without a host wait,
 // and only while the predicted norm exceeds kAheadMargin * threshold
 constexpr int kMaxAhead = 16;
@@ -121,6 +123,14 @@ void launch_residual(const double* phi, const double* rhs, T* r_out, int n, cons
 template <typename T>
 void launch_correct(double* phi, const T* e, float* chg, double pending_scale, int n,
                     const Box& b, hipStream_t st);
+// launch_correct fused with an estimate of the next residual, r_old - A e
+// (r_old: the residual the correction e solved for, colour-split T), in
+// place of the FP64 residual pass; partial sums over *nblocks workgroups of
+// the squares of the estimate, r_old, the new phi and e in slots 0..3.
+template <typename T>
+void launch_correct_est(double* phi, const T* e, const T* r_old, float* chg, double pending_scale,
+                        double kappa, int n, const Box& b, double* partial, int* nblocks,
+                        hipStream_t st);
 // A pending start over the box: d = (float)(chg_scale chg), phi += d, chg = d.
 void launch_apply_start(double* phi, float* chg, double chg_scale, int n, const Box& b,
                         hipStream_t st);
@@ -331,7 +341,7 @@ enum KernelId : int {
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
   K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK, K_SWEEP4, K_SWEEP4_FIRST, K_SWEEP4_COARSE,
-  K_SWEEP4_RESID,
+  K_SWEEP4_RESID, K_CORRECT_EST,
   K_NKERNELS
 };
 static_assert(K_NKERNELS <= 64, "the profiler's kernel mask holds 64 kernels");

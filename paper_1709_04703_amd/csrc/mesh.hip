@@ -486,6 +486,162 @@ k_correct(double* __restrict__ phi, const T* __restrict__ e, float* __restrict__
   }
 }
 
+// k_correct with the next residual estimated in the same pass instead of
+// an FP64 residual pass: the V-cycles solved A e = r_old for the stored
+// residual r_old (type T), so after phi += e the residual of the defect
+// equation is r_old - A e up to the rounding of r_old to T and FP64
+// rounding, A e evaluated here in FP64 from the stored correction (zero
+// outside a Dirichlet box; periodic axes, those the box spans, wrap).  Per
+// workgroup the partial sums of the squares of the estimate, of r_old, of
+// the new phi and of e (slots 0..3), from which the host bounds the
+// distance between the estimate and the FP64 residual.  Tiles as in
+// k_residual_v4: 4 consecutive cells per lane (i0 a multiple of 4), a row
+// segment over the TXV lanes of a wave, kResKz planes walked with e of
+// planes k - 1, k, k + 1 in registers; e and r_old of the lane's cells are
+// two 2-wide loads per colour-split row (cells i0, i0 + 2 and i0 + 1,
+// i0 + 3), its x neighbours the adjacent lanes' end cells.
+template <typename T, int TXV, bool CHG, bool PENDING>
+__global__ void __launch_bounds__(256)
+k_correct_est_v4(double* __restrict__ phi, const T* __restrict__ e, const T* __restrict__ rold,
+                 float* __restrict__ chg, int n, Box b, double chg_scale, double kappa,
+                 double* __restrict__ partial) {
+  __shared__ double sh[4];
+  constexpr int TY = 256 / TXV;
+  const int ib = b.lo[0] & ~3;
+  const Tile tl = tile_of((b.hi[0] - ib + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
+  const int i0 = ib + (tl.bx * TXV + threadIdx.x) * 4;
+  const int j = b.lo[1] + tl.by * TY + threadIdx.y;
+  const int m = n - 1, hn = n >> 1;
+  const int64_t hc = half_cells(n);
+  const bool in = i0 <= b.hi[0] && j <= b.hi[1];
+  const bool px = b.lo[0] == 0 && b.hi[0] == m, py = b.lo[1] == 0 && b.hi[1] == m,
+             pz = b.lo[2] == 0 && b.hi[2] == m;
+  bool cin[4];                                   // the lane's cells inside the box in x
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cin[q] = i0 + q >= b.lo[0] && i0 + q <= b.hi[0];
+  const bool full = cin[0] && cin[3];
+  // the neighbour lane holds cell i0 - 1 (i0 + 4) inside the box without wrapping
+  const bool sh_l = threadIdx.x > 0, sh_r = threadIdx.x + 1 < TXV && i0 + 4 <= b.hi[0];
+  const bool has_l = px || i0 - 1 >= b.lo[0], has_r = px || i0 + 4 <= b.hi[0];
+  const bool has_d = py || j > b.lo[1], has_u = py || j < b.hi[1];
+  const int il = (i0 - 1) & m, ir = (i0 + 4) & m, jm = (j - 1) & m, jp = (j + 1) & m;
+  // colour-split values of cells i0 .. i0 + 3 of row (jj, kk), natural order
+  auto ld4 = [&](const T* a, int jj, int kk) {
+    const int c0 = (i0 + jj + kk) & 1;
+    const int64_t row = ((int64_t)kk * n + jj) * hn + (i0 >> 1);
+    const Vec2<T> u = *(const Vec2<T>*)(a + c0 * hc + row);
+    const Vec2<T> v = *(const Vec2<T>*)(a + (c0 ^ 1) * hc + row);
+    Vec4<T> r;
+    r.v[0] = cin[0] ? u.v[0] : (T)0;
+    r.v[1] = cin[1] ? v.v[0] : (T)0;
+    r.v[2] = cin[2] ? u.v[1] : (T)0;
+    r.v[3] = cin[3] ? v.v[1] : (T)0;
+    return r;
+  };
+  auto zero4 = []() {
+    Vec4<T> r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.v[q] = (T)0;
+    return r;
+  };
+  const int k0 = b.lo[2] + tl.bz * kResKz;
+  const int k1 = min(k0 + kResKz - 1, b.hi[2]);
+  double s_est = 0.0, s_old = 0.0, s_phi = 0.0, s_e = 0.0;
+  Vec4<T> below = zero4(), ctr = zero4();
+  if (in) {
+    if (pz || k0 > b.lo[2]) below = ld4(e, j, (k0 - 1) & m);
+    ctr = ld4(e, j, k0);
+  }
+  for (int k = k0; k <= k1; ++k) {
+    const T from_l = lane_prev<TXV>(ctr.v[3]), from_r = lane_next<TXV>(ctr.v[0]);
+    Vec4<T> above = zero4();
+    if (in) {
+      if (pz || k < b.hi[2]) above = ld4(e, j, (k + 1) & m);
+      const Vec4<T> ym = has_d ? ld4(e, jm, k) : zero4();
+      const Vec4<T> yp = has_u ? ld4(e, jp, k) : zero4();
+      const Vec4<T> rv = ld4(rold, j, k);
+      T xl = from_l, xr = from_r;
+      if (!sh_l) xl = has_l ? e[sidx(il, j, k, n)] : (T)0;
+      if (!sh_r) xr = has_r ? e[sidx(ir, j, k, n)] : (T)0;
+      const int64_t c = lin(i0, j, k, n);
+      double pn[4];
+      float cnew[4];
+      Vec4<double> ph;
+      Vec4<float> cv;
+      if (full) {
+        ph = *(const Vec4<double>*)(phi + c);
+        if (CHG) cv = ld_stream4(chg + c);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ph.v[q] = cin[q] ? phi[c + q] : 0.0;
+          if (CHG) cv.v[q] = cin[q] ? chg[c + q] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T ev = ctr.v[q];
+        if (CHG) {
+          float d = cv.v[q];
+          if (PENDING) {
+            d = (float)(chg_scale * (double)d);
+            pn[q] = (ph.v[q] + (double)d) + (double)ev;
+          } else {
+            pn[q] = ph.v[q] + (double)ev;
+          }
+          cnew[q] = d + (float)ev;
+        } else {
+          pn[q] = ph.v[q] + (double)ev;
+        }
+        const double left = q == 0 ? (double)xl : (double)ctr.v[q - 1];
+        const double right = q == 3 ? (double)xr : (double)ctr.v[q + 1];
+        const double nb = left + right + (double)ym.v[q] + (double)yp.v[q] + (double)above.v[q] +
+                          (double)below.v[q];
+        const double ec = (double)ev;
+        const double est = (double)rv.v[q] - (nb - 6.0 * ec - kappa * ec);
+        if (cin[q]) {
+          s_est += est * est;
+          s_old += (double)rv.v[q] * (double)rv.v[q];
+          s_phi += pn[q] * pn[q];
+          s_e += ec * ec;
+        }
+      }
+      if (full) {
+        Vec4<double> o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o.v[q] = pn[q];
+        *(Vec4<double>*)(phi + c) = o;
+        if (CHG) {
+          Vec4<float> co;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) co.v[q] = cnew[q];
+          st_stream4(chg + c, co);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!cin[q]) continue;
+          phi[c + q] = pn[q];
+          if (CHG) chg[c + q] = cnew[q];
+        }
+      }
+    }
+    below = ctr;
+    ctr = above;
+  }
+  const double a0 = block_sum<256>(s_est, sh);
+  const double a1 = block_sum<256>(s_old, sh);
+  const double a2 = block_sum<256>(s_phi, sh);
+  const double a3 = block_sum<256>(s_e, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int64_t nb = gridDim.x, w = block_linear();
+    partial[w] = a0;
+    partial[nb + w] = a1;
+    partial[2 * nb + w] = a2;
+    partial[3 * nb + w] = a3;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_sum_phi(const double* __restrict__ phi, int n, Box b, double* __restrict__ partial) {
   __shared__ double sh[4];
@@ -1665,6 +1821,49 @@ template void launch_correct<float>(double*, const float*, float*, double, int, 
                                     hipStream_t);
 template void launch_correct<double>(double*, const double*, float*, double, int, const Box&,
                                      hipStream_t);
+
+template <typename T, int TXV>
+static void correct_est_tiles(double* phi, const T* e, const T* r_old, float* chg,
+                              double pending_scale, double kappa, int n, const Box& b,
+                              double* partial, const dim3& g, hipStream_t st) {
+  const dim3 blk(TXV, 256 / TXV);
+  if (chg && pending_scale != 0.0)
+    hipLaunchKernelGGL((k_correct_est_v4<T, TXV, true, true>), g, blk, 0, st, phi, e, r_old, chg, n,
+                       b, pending_scale, kappa, partial);
+  else if (chg)
+    hipLaunchKernelGGL((k_correct_est_v4<T, TXV, true, false>), g, blk, 0, st, phi, e, r_old, chg,
+                       n, b, 0.0, kappa, partial);
+  else
+    hipLaunchKernelGGL((k_correct_est_v4<T, TXV, false, false>), g, blk, 0, st, phi, e, r_old,
+                       nullptr, n, b, 0.0, kappa, partial);
+}
+
+template <typename T>
+void launch_correct_est(double* phi, const T* e, const T* r_old, float* chg, double pending_scale,
+                        double kappa, int n, const Box& b, double* partial, int* nblocks,
+                        hipStream_t st) {
+  // the residual's tiles (4 cells per lane; the host asks for this pass only
+  // on boxes at least 16 cells wide, where the narrowest tile fits)
+  const int ib = b.lo[0] & ~3;
+  const int txv = tile_threads(b.hi[0] - ib + 1);
+  const unsigned gx = (unsigned)((b.hi[0] - ib + 4 * txv) / (4 * txv));
+  const unsigned gy = (unsigned)((b.hi[1] - b.lo[1] + 256 / txv) / (256 / txv));
+  const unsigned gz = (unsigned)((b.hi[2] - b.lo[2] + kResKz) / kResKz);
+  const dim3 g(gx * gy * gz);
+  *nblocks = (int)g.x;
+  prof_begin(st, K_CORRECT_EST);
+  if (txv == 64)
+    correct_est_tiles<T, 64>(phi, e, r_old, chg, pending_scale, kappa, n, b, partial, g, st);
+  else if (txv == 32)
+    correct_est_tiles<T, 32>(phi, e, r_old, chg, pending_scale, kappa, n, b, partial, g, st);
+  else
+    correct_est_tiles<T, 16>(phi, e, r_old, chg, pending_scale, kappa, n, b, partial, g, st);
+  prof_end(st, K_CORRECT_EST, (16.0 + 2.0 * sizeof(T) + (chg ? 8.0 : 0.0)) * box_cells(b));
+}
+template void launch_correct_est<float>(double*, const float*, const float*, float*, double,
+                                        double, int, const Box&, double*, int*, hipStream_t);
+template void launch_correct_est<double>(double*, const double*, const double*, float*, double,
+                                         double, int, const Box&, double*, int*, hipStream_t);
 
 void launch_apply_start(double* phi, float* chg, double chg_scale, int n, const Box& b,
                         hipStream_t st) {

@@ -19,6 +19,21 @@ pytestmark = pytest.mark.gpu
 B = 14
 
 
+def _check_reported_residual(phi, rhs, kappa, reported, tol, sl=None):
+    """The residual rhs - (Lap_h phi - kappa phi) of the returned potential,
+    in FP64 on the host, relative to ||rhs|| over the solved cells: below the
+    tolerance, and the reported figure (an estimate r_old - A e when the last
+    correction pass bounded it below the threshold) close to it."""
+    lap = sum(np.roll(phi, sh, ax) for ax in range(3) for sh in (1, -1)) - 6.0 * phi
+    r = rhs - (lap - kappa * phi)
+    if sl is not None:
+        r, rhs = r[sl], rhs[sl]
+    true = np.linalg.norm(r) / np.linalg.norm(rhs)
+    log(f"  residual: reported {reported:.4e} recomputed {true:.4e}")
+    assert true <= tol * (1.0 + 1e-6)
+    assert abs(reported - true) <= max(0.05 * tol, 1e-3 * true)
+
+
 @pytest.mark.parametrize("ng,kappa,prec,tol", [
     (32, 0.0, 0, 1e-8), (64, 0.0, 0, 1e-8), (64, 0.0, 1, 1e-10), (64, 0.12, 0, 1e-8),
     (128, 0.3, 0, 1e-8), (128, 0.0, 1, 1e-8), (16, 0.0, 0, 1e-10),
@@ -47,6 +62,7 @@ def test_periodic_solve_and_force(ng, kappa, prec, tol):
     err = rel_rms(phi, phi_ref)
     log(f"  iters={st['outer_iters'][0]} res={st['res'][0]:.2e} phi err={err:.2e}")
     assert err <= cond_periodic(ng, kappa) * tol
+    _check_reported_residual(phi, got_rhs, kappa, st["res"][0], tol)
     if kappa == 0.0:
         assert abs(phi.mean()) <= 1e-12 * np.abs(phi).max()
     g = sim.interp_force().cpu().numpy().T
@@ -98,6 +114,7 @@ def test_dirichlet_box_solve_with_frozen_ring(kappa, prec, align, ng):
     sl = (slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
     err = rel_rms(phi[sl], phi_ref[sl])
     log(f"  iters={st['outer_iters'][0]} res={st['res'][0]:.2e} phi err={err:.2e}")
+    _check_reported_residual(phi, sim.rhs.cpu().numpy(), kappa, st["res"][0], cfg.tol, sl)
     nmax = int(max(hi - lo + 1))
     cond = (12.0 + kappa) / (3 * (2 - 2 * np.cos(np.pi / (nmax + 1))) + kappa)
     assert err <= cond * cfg.tol
