@@ -61,9 +61,15 @@ struct sdpm_ctx {
   bool ex_have[2] = {false, false};
   double ex_dtau[2] = {0.0, 0.0};
   double cur_dtau = 0.0;        // conformal step of the sdpm_step in progress (0 otherwise)
-  // residual reduction per V-cycle of the last solve (geometric mean), used
-  // to run ahead of the host without a sync per iteration and to pair cycles
-  double rho_est = 0.1;
+  // residual reduction per V-cycle of the last solve of each kind (geometric
+  // mean; the two half-step solves differ in kappa and converge at different
+  // rates), used to run ahead of the host without a sync per iteration and to
+  // pair cycles
+  double rho_est[2] = {0.1, 0.1};
+  bool rho_measured[2] = {false, false};
+  // ||e|| / ||r_old|| of the last outer iteration whose correction pass
+  // estimated the residual, per kind of solve (0: not measured yet)
+  double e_over_r[2] = {0.0, 0.0};
   // lightcone output
   sdpm_lightcone lc{};
   bool lc_on = false;
@@ -654,8 +660,9 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
   // then the host waits and reads the norms.  A wrong prediction can only add
   // iterations (the residual keeps falling), never stop early.
   // An outer iteration runs further V-cycles on its defect equation (up to
-  // cycles_per_outer) while fewer are predicted, with margin, to leave the
-  // norm above the threshold: a V-cycle is a linear stationary iteration, so
+  // cycles_per_outer) while fewer are predicted to leave the norm above 0.9
+  // times the threshold (twice the threshold while the factor per cycle is
+  // still a guess): a V-cycle is a linear stationary iteration, so
   // each further cycle reduces the error as a further outer iteration would,
   // down to the rounding floor below, and saves that iteration's FP64
   // correction and residual passes.
@@ -664,31 +671,37 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
   // (eps_T / 2) |e| with |e| <= |r| / (kappa h^2 + lambda_min), the extreme
   // eigenvalues of the 7-point operator, lambda_min that of the domain's
   // lowest mode (non-constant when periodic; a lower bound, the Dirichlet
-  // mode of the box's longest side, otherwise).  Further cycles are added
-  // only while their combined factor stays above that worst-case floor: at
-  // kappa h^2 = 0.113 in FP32 (floor 6.4e-6) it allows four cycles of factor
-  // above 0.05, for the 512^3 Poisson solve (kappa = 0, floor 4.8e-3) two of
-  // factor above 0.07.
+  // mode of the box's longest side, otherwise).  The ratio |e| / |r| is
+  // taken as measured in the last solve of the same kind where there is one
+  // (the estimating correction pass sums both), else at that bound.  Further
+  // cycles are added only while their combined factor stays above the floor:
+  // at kappa h^2 = 0.113 in FP32 and the bound's ratio (floor 6.4e-6) it
+  // allows four cycles of factor above 0.05, for the 512^3 Poisson solve
+  // (kappa = 0, floor 4.8e-3) two of factor above 0.07.  Where the floor does
+  // stop the residual, the check after the correction finds it and a further
+  // outer iteration follows.
   double lam_min;
   {
     const int ext = std::max(b.hi[0] - b.lo[0], std::max(b.hi[1] - b.lo[1], b.hi[2] - b.lo[2])) + 1;
     const double sn = c->periodic ? std::sin(M_PI / g.ng) : std::sin(M_PI / (2.0 * (ext + 1)));
     lam_min = 4.0 * sn * sn;
   }
-  const double floor_rel =
-      0.5 * (double)std::numeric_limits<T>::epsilon() * (12.0 + kappa) / (kappa + lam_min);
+  const double q_bound = 1.0 / (kappa + lam_min);
+  const double q = c->e_over_r[slot] > 0.0 ? std::min(c->e_over_r[slot], q_bound) : q_bound;
+  const double floor_rel = 0.5 * (double)std::numeric_limits<T>::epsilon() * (12.0 + kappa) * q;
   double rn_known = rn;
   int it_known = 0, cyc_known = 0;
   while (rn > thresh && it < g.max_outer && std::isfinite(rn)) {
     const bool time_it = gated && it == 0;
-    double pred_next = rn_known * std::pow(c->rho_est, cyc - cyc_known + 1);
-    double factor = c->rho_est;
+    double pred_next = rn_known * std::pow(c->rho_est[slot], cyc - cyc_known + 1);
+    double factor = c->rho_est[slot];
     int ncyc = 1;
-    while (ncyc < g.cycles_per_outer && pred_next > kCycleMargin * thresh &&
-           factor * c->rho_est > kFloorMargin * floor_rel) {
+    const double margin = c->rho_measured[slot] ? kCycleMargin : kCycleMarginGuess;
+    while (ncyc < g.cycles_per_outer && pred_next > margin * thresh &&
+           factor * c->rho_est[slot] > kFloorMargin * floor_rel) {
       ++ncyc;
-      pred_next *= c->rho_est;
-      factor *= c->rho_est;
+      pred_next *= c->rho_est[slot];
+      factor *= c->rho_est[slot];
     }
     const bool ahead = it == 0 && e_spec;   // first cycle already enqueued
     if (time_it && !ahead) HIP_TRY(c, hipEventRecord(c->ev[10], c->st));
@@ -701,7 +714,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
     // the estimate with its bound is below the threshold, the FP64 residual
     // would be too and its pass is skipped.
     const bool wait = time_it || it + 1 >= g.max_outer || it + 1 - it_known >= kMaxAhead ||
-                      !(rn_known * std::pow(c->rho_est, cyc + ncyc - cyc_known) > kAheadMargin * thresh);
+                      !(rn_known * std::pow(c->rho_est[slot], cyc + ncyc - cyc_known) > kAheadMargin * thresh);
     const bool est = wait && !time_it;
     if (est) {
       launch_correct_est<T>(c->fields.phi, e0, (const T*)c->lv[0].r, chg, pending, kappa, g.ng, b,
@@ -720,6 +733,8 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
       const double bound = estimate_bound<T>(std::sqrt(c->hpin[kEstSlot + 1]), bn,
                                              std::sqrt(c->hpin[kEstSlot + 2]),
                                              std::sqrt(c->hpin[kEstSlot + 3]), kappa);
+      const double nr = std::sqrt(c->hpin[kEstSlot + 1]), nc = std::sqrt(c->hpin[kEstSlot + 3]);
+      if (nr > 0.0 && std::isfinite(nc / nr)) c->e_over_r[slot] = nc / nr;
       if (std::isfinite(ne) && std::isfinite(bound) && (ne + bound) * (1.0 + 1e-9) <= thresh) {
         met = true;
         rn = ne;
@@ -734,7 +749,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
     ++it;
     cyc += ncyc;
     if (met) break;
-    const double pred = rn_known * std::pow(c->rho_est, cyc - cyc_known);
+    const double pred = rn_known * std::pow(c->rho_est[slot], cyc - cyc_known);
     if (!time_it && it < g.max_outer && it - it_known < kMaxAhead && pred > kAheadMargin * thresh)
       continue;
     rc = sync_norms(c);
@@ -755,7 +770,10 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
   flush_pending();      // a start already within tol: no correction took it
   if (cyc > 0 && rn > 0.0 && rn_start > 0.0 && std::isfinite(rn)) {
     const double rho = std::pow(rn / rn_start, 1.0 / cyc);
-    if (rho > 0.0 && rho < 1.0) c->rho_est = std::min(std::max(rho, 1e-3), 0.9);
+    if (rho > 0.0 && rho < 1.0) {
+      c->rho_est[slot] = std::min(std::max(rho, 1e-3), 0.9);
+      c->rho_measured[slot] = true;
+    }
   }
   if (gated && net_ran) {
     // V-cycles the guess saved: its residual reduction measured in this

@@ -24,13 +24,20 @@ constexpr int kEstSlot = 4;
 constexpr int kMaxAhead = 16;
 constexpr double kAheadMargin = 10.0;
 // a further V-cycle in an outer iteration only while the cycles so far are
-// predicted to leave the norm above kCycleMargin * threshold (a needless cycle
-// costs about twice what a further outer iteration's FP64 passes do) and
-// their combined factor stays above kFloorMargin times the bound on the
-// rounding floor of the correction; at most kMaxCyclesPerOuter cycles
-constexpr double kCycleMargin = 2.0;
+// predicted, with the factor per cycle measured in the last solve of the
+// same kind, to leave the norm above kCycleMargin * threshold (a cycle too
+// few costs a further outer iteration: its FP64 residual pass, a second
+// estimating correction pass and a host wait, about 1.5 times a 512^3
+// V-cycle, so the cycle is added once failing is about as likely as not)
+// and their combined factor stays above kFloorMargin times the bound on the
+// rounding floor of the correction; at most kMaxCyclesPerOuter cycles.
+// Before any solve of that kind has measured the factor, its guess (0.1)
+// only adds cycles while the prediction stays above kCycleMarginGuess times
+// the threshold.
+constexpr double kCycleMargin = 0.9;
+constexpr double kCycleMarginGuess = 2.0;
 constexpr int kMaxCyclesPerOuter = 4;
-constexpr double kFloorMargin = 1.0;    // the floor is a worst-case bound already
+constexpr double kFloorMargin = 1.0;
 constexpr int kHostLcCount = 120;      // host slot of the fixed-domain lightcone counter
 constexpr int kCoarseMax = 16;        // coarsest multigrid level: at most 16^3 cells
 constexpr int kBoxTx = 64;            // box kernels: 64 x 4 threads, KZ cells in z
