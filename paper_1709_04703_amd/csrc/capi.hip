@@ -715,7 +715,7 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
     // would be too and its pass is skipped.
     const bool wait = time_it || it + 1 >= g.max_outer || it + 1 - it_known >= kMaxAhead ||
                       !(rn_known * std::pow(c->rho_est[slot], cyc + ncyc - cyc_known) > kAheadMargin * thresh);
-    const bool est = wait && !time_it;
+    const bool est = wait;
     if (est) {
       launch_correct_est<T>(c->fields.phi, e0, (const T*)c->lv[0].r, chg, pending, kappa, g.ng, b,
                             c->partial, &nb, c->st);
@@ -725,6 +725,16 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
     }
     pending = 0.0;
     if (rec) launch_record_accum<T>(e0, g.ng, b, rec + 2 * (size_t)g.ng * g.ng * g.ng, c->st);
+    // cost of one V-cycle with its share of the outer iteration's passes
+    // (the learned guess's gate weighs the net's cost against it)
+    auto cycle_cost = [&]() {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess) {
+        const double per = ms / ncyc;
+        c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + per) : per;
+      }
+    };
+    if (time_it && est) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
     bool met = false;
     if (est) {
       rc = sync_estimate(c);
@@ -745,23 +755,19 @@ int solve_impl(sdpm_ctx* c, double kappa, int slot, SolveOut* so, RhsOut rh) {
                          &nb, c->st);
       launch_reduce_final(c->partial, nb, 1, c->dscal + kNormSlot + (it % kNormRing), c->st);
     }
-    if (time_it) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
+    if (time_it && !est) HIP_TRY(c, hipEventRecord(c->ev[11], c->st));
     ++it;
     cyc += ncyc;
-    if (met) break;
+    if (met) {
+      if (time_it) cycle_cost();
+      break;
+    }
     const double pred = rn_known * std::pow(c->rho_est[slot], cyc - cyc_known);
     if (!time_it && it < g.max_outer && it - it_known < kMaxAhead && pred > kAheadMargin * thresh)
       continue;
     rc = sync_norms(c);
     if (rc) return rc;
-    if (time_it) {
-      // cost of one V-cycle with its share of the outer iteration's passes
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev[10], c->ev[11]) == hipSuccess) {
-        const double per = ms / ncyc;
-        c->gate_cycle_ms = c->gate_cycle_ms > 0.0 ? 0.5 * (c->gate_cycle_ms + per) : per;
-      }
-    }
+    if (time_it) cycle_cost();
     rn = std::sqrt(c->hpin[kHostNorm + (it - 1) % kNormRing]);
     rn_known = rn;
     it_known = it;
