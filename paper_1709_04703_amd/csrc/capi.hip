@@ -119,6 +119,11 @@ int fail(sdpm_ctx* c, int code, const char* fmt, ...) {
   } while (0)
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+bool same_box(const Box& a, const Box& b) {
+  for (int d = 0; d < 3; ++d)
+    if (a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d]) return false;
+  return true;
+}
 int ilog2(int64_t v) {
   int l = 0;
   while ((1ll << l) < v) ++l;
@@ -501,8 +506,13 @@ bool extrap_active(const sdpm_ctx* c, int slot) {
 struct RhsOut {
   bool res_ready = false;
   double pending_scale = 0.0;
+  bool force_done = false;      // the force mesh of phi was written as well
 };
-RhsOut assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot, bool mg = false) {
+// With g3 (mixed precision, multigrid), the source pass also writes the FP32
+// force mesh of phi over the solve's box when it runs as the fused vector
+// pass (force_done); the caller takes the force pass otherwise.
+RhsOut assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot, bool mg = false,
+                    float* g3 = nullptr, double inv2h = 0.0) {
   const sdpm_config& g = c->cfg;
   const double h = g.box / g.ng;
   const double nbar = (double)g.n_initial / ((double)g.ng * g.ng * g.ng);
@@ -521,7 +531,7 @@ RhsOut assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot, bool m
             ? launch_rhs_residual<float>(c->fields.counts, c->fields.phi, c->fields.rhs,
                                          (float*)c->lv[0].r, chg, apply, chg_scale, g.ng,
                                          c->lv[0].box, c_scale, c_off, kappa, c->partial, &nb,
-                                         c->st)
+                                         c->st, g3, inv2h)
             : launch_rhs_residual<double>(c->fields.counts, c->fields.phi, c->fields.rhs,
                                           (double*)c->lv[0].r, chg, apply, chg_scale, g.ng,
                                           c->lv[0].box, c_scale, c_off, kappa, c->partial, &nb,
@@ -530,6 +540,7 @@ RhsOut assemble_rhs(sdpm_ctx* c, double s_source, double kappa, int slot, bool m
       launch_reduce_final(c->partial, nb, 2, c->dscal, c->st);
       out.res_ready = true;
       out.pending_scale = apply ? chg_scale : 0.0;
+      out.force_done = g3 != nullptr && g.precision == SDPM_MIXED;
       return out;
     }
   }
@@ -1250,6 +1261,16 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     if (src1 && src1 != SDPM_ENOCONV) return src1;
   }
   HIP_TRY(c, hipEventRecord(c->ev[3], c->st));
+  // The second half sub-step's source pass (row 7: the same density and the
+  // potential just solved for) does not depend on the particle pass; when
+  // its box is the force mesh's, it runs first and writes the force mesh too.
+  RhsOut rh2;
+  bool rh2_done = false;
+  if (!ade && sc.kappa2_h2 > 0.0 && g.precision == SDPM_MIXED && mg_solve(c) &&
+      same_box(mesh_map(c).active, c->lv[0].box)) {
+    rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, true, c->gmesh, 0.5 / h);
+    rh2_done = true;
+  }
   // grad Phi, CIC interpolation, kick with a(t+dt/2), drift with a(t+dt)  (rows 4-6)
   const bool removal = g.shrink && c->n_active > 0 &&
                        sc.r_lc_end < corner_distance(g) * (1.0 + 1e-12);
@@ -1261,7 +1282,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
     const double kick = sc.a_half * sc.dtau, drift = 0.5 * sc.dtau / (a + da);
     if (g.precision == SDPM_MIXED) {
       // FP32 force mesh (FP64 differences), then 12-byte gathers per CIC cell
-      launch_force_mesh(c->fields.phi, c->gmesh, g.ng, mm.active, 0.5 / h, c->st);
+      if (!rh2.force_done) launch_force_mesh(c->fields.phi, c->gmesh, g.ng, mm.active, 0.5 / h, c->st);
       launch_interp_kick_drift<float>(pa, c->fields.phi, c->gmesh, mm, 0.5 / h, drift0, kick, drift,
                                       g.x_obs, sc.r_lc_end * sc.r_lc_end, removal, c->dflags + 1,
                                       c->dflags, c->st);
@@ -1285,7 +1306,7 @@ int sdpm_step(sdpm_ctx* c, double a, double da, sdpm_step_stats* out) {
                      1.0 / sc.kappa2_h2, false, c->st);
   } else if (sc.kappa2_h2 > 0.0) {
     const bool mg = mg_solve(c);
-    const RhsOut rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, mg);
+    if (!rh2_done) rh2 = assemble_rhs(c, sc.s_half, sc.kappa2_h2, 1, mg);
     src2 = solve(c, sc.kappa2_h2, 1, &s2, rh2);
     if (src2 && src2 != SDPM_ENOCONV) return src2;
     flags_read = mg;

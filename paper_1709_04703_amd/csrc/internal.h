@@ -145,13 +145,15 @@ void launch_apply_start(double* phi, float* chg, double chg_scale, int n, const 
 // rhs and r (colour-split T) with phi0 = phi + (float)(chg_scale chg) when
 // apply (the start is then pending: phi and chg unchanged), else phi0 = phi
 // and chg (when given) cleared; partial[0 .. nb) = rhs^2, partial[nb ..
-// 2 nb) = r^2 sums.  Returns false without launching when the box is
-// narrower than the vector tiles.
+// 2 nb) = r^2 sums.  With g3 the pass also writes the FP32 force mesh of
+// phi (as launch_force_mesh with inv2h = 1 / 2h) over the same box.
+// Returns false without launching when the box is narrower than the vector
+// tiles.
 template <typename T>
 bool launch_rhs_residual(const uint64_t* counts, const double* phi, double* rhs, T* r_out,
                          float* chg, bool apply, double chg_scale, int n, const Box& b,
                          double c_scale, double c_off, double kappa, double* partial,
-                         int* nblocks, hipStream_t st);
+                         int* nblocks, hipStream_t st, float* g3 = nullptr, double inv2h = 0.0);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st);
@@ -348,7 +350,7 @@ enum KernelId : int {
   K_INTERP_KICK_DRIFT, K_INTERP_FORCE, K_COUNT_KEPT, K_SCAN, K_SCATTER, K_COPY,
   K_SORT, K_GATHER, K_CONV, K_CONV_WGRAD, K_NET_MISC, K_FORCE_MESH, K_LIGHTCONE,
   K_SMOOTH_COARSE, K_ADE, K_FFT, K_FFT_DIVIDE, K_PK, K_SWEEP4, K_SWEEP4_FIRST, K_SWEEP4_COARSE,
-  K_SWEEP4_RESID, K_CORRECT_EST,
+  K_SWEEP4_RESID, K_CORRECT_EST, K_RHS_FORCE,
   K_NKERNELS
 };
 static_assert(K_NKERNELS <= 64, "the profiler's kernel mask holds 64 kernels");

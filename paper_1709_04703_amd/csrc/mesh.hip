@@ -314,13 +314,19 @@ k_residual_v4(const double* __restrict__ phi, const double* __restrict__ rhs, T*
 // partial[nblocks + block] = sum of r^2.  One pass instead of the rhs pass
 // and the residual pass: phi and rhs are not read a second time (and with
 // the start, phi is not written here).
-template <typename T, int TXV, int MODE>
+// FORCE: the pass also writes the FP32 force mesh of phi (the raw values,
+// before any start), with the arithmetic and the store pattern of
+// k_force_mesh_v4; the second half sub-step's source pass reads the same
+// potential the force is taken from, so one pass serves both.
+template <typename T, int TXV, int MODE, bool FORCE>
 __global__ void __launch_bounds__(256)
 k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict__ phi,
                   double* __restrict__ rhs, T* __restrict__ rout, float* __restrict__ chg, int n,
                   Box b, double c_scale, double c_off, double kappa, double chg_scale,
-                  int nblocks, double* __restrict__ partial) {
+                  int nblocks, double* __restrict__ partial, float* __restrict__ g3,
+                  double inv2h) {
   __shared__ double sh[4];
+  __shared__ __attribute__((aligned(16))) float stage[FORCE ? 12 * 256 : 4];
   constexpr int TY = 256 / TXV;
   const int ib = b.lo[0] & ~3;
   const Tile tl = tile_of((b.hi[0] - ib + 4 * TXV) / (4 * TXV), (b.hi[1] - b.lo[1] + TY) / TY);
@@ -352,9 +358,12 @@ k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict_
     const bool lane_l = threadIdx.x > 0, lane_r = threadIdx.x + 1 < TXV && i0 + 4 <= b.hi[0];
     const int hn = n >> 1;
     const int64_t hc = half_cells(n);
-    Vec4<double> raw, below, ctr, ctr_raw;
+    const int seg0 = ib + tl.bx * TXV * 4;          // first cell of this row segment
+    const bool row_full = seg0 >= b.lo[0] && seg0 + 4 * TXV - 1 <= b.hi[0];
+    Vec4<double> raw, below, ctr, ctr_raw, below_raw;
     Vec4<float> d, ctr_d;
     start4(lin(i0, j, (k0 - 1) & m, n), raw, d);
+    if (FORCE) below_raw = raw;
 #pragma unroll
     for (int q = 0; q < 4; ++q) below.v[q] = raw.v[q] + (double)d.v[q];
     start4(lin(i0, j, k0, n), ctr_raw, ctr_d);
@@ -366,10 +375,13 @@ k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict_
       start4(lin(i0, j, (k + 1) & m, n), above_raw, above_d);
 #pragma unroll
       for (int q = 0; q < 4; ++q) above.v[q] = above_raw.v[q] + (double)above_d.v[q];
+      Vec4<double> ym_raw, yp_raw;
       start4(lin(i0, jm, k, n), raw, d);
+      if (FORCE) ym_raw = raw;
 #pragma unroll
       for (int q = 0; q < 4; ++q) ym.v[q] = raw.v[q] + (double)d.v[q];
       start4(lin(i0, jp, k, n), raw, d);
+      if (FORCE) yp_raw = raw;
 #pragma unroll
       for (int q = 0; q < 4; ++q) yp.v[q] = raw.v[q] + (double)d.v[q];
       double xl = lane_prev<TXV>(ctr.v[3]), xr = lane_next<TXV>(ctr.v[0]);
@@ -420,6 +432,57 @@ k_rhs_residual_v4(const uint64_t* __restrict__ counts, const double* __restrict_
           acc_r += res[q] * res[q];
           acc_b += rv[q] * rv[q];
         }
+      }
+      if constexpr (FORCE) {
+        double fl = lane_prev<TXV>(ctr_raw.v[3]), fr = lane_next<TXV>(ctr_raw.v[0]);
+        if (!lane_l) fl = phi[lin(il, j, k, n)];
+        if (!lane_r) fr = phi[lin(ir, j, k, n)];
+        float out[12];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double left = q == 0 ? fl : ctr_raw.v[q - 1];
+          const double right = q == 3 ? fr : ctr_raw.v[q + 1];
+          out[3 * q + 0] = (float)(-(right - left) * inv2h);
+          out[3 * q + 1] = (float)(-(yp_raw.v[q] - ym_raw.v[q]) * inv2h);
+          out[3 * q + 2] = (float)(-(above_raw.v[q] - below_raw.v[q]) * inv2h);
+        }
+        float* dst = g3 + 3 * c;
+        if (row_full) {
+          // as k_force_mesh_v4: the row segment's 48 TXV contiguous bytes
+          // staged in LDS and stored as 3 coalesced 16-byte stores per lane
+          float* seg = stage + threadIdx.y * (12 * TXV);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            Vec4<float> o;
+            o.v[0] = out[4 * v], o.v[1] = out[4 * v + 1], o.v[2] = out[4 * v + 2], o.v[3] = out[4 * v + 3];
+            *(Vec4<float>*)(seg + 12 * threadIdx.x + 4 * v) = o;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          float* gseg = g3 + 3 * lin(i0 - 4 * (int)threadIdx.x, j, k, n);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            const Vec4<float> o = *(const Vec4<float>*)(seg + 4 * (TXV * v + threadIdx.x));
+            st_stream4(gseg + 4 * (TXV * v + threadIdx.x), o);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else if (full) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            Vec4<float> o;
+            o.v[0] = out[4 * v], o.v[1] = out[4 * v + 1], o.v[2] = out[4 * v + 2], o.v[3] = out[4 * v + 3];
+            st_stream4(dst + 4 * v, o);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (i0 + q >= b.lo[0] && i0 + q <= b.hi[0])
+              for (int dd = 0; dd < 3; ++dd) dst[3 * q + dd] = out[3 * q + dd];
+        }
+        below_raw = ctr_raw;
       }
       below = ctr;
       ctr = above;
@@ -1881,7 +1944,7 @@ template <typename T>
 bool launch_rhs_residual(const uint64_t* counts, const double* phi, double* rhs, T* r_out,
                          float* chg, bool apply, double chg_scale, int n, const Box& b,
                          double c_scale, double c_off, double kappa, double* partial,
-                         int* nblocks, hipStream_t st) {
+                         int* nblocks, hipStream_t st, float* g3, double inv2h) {
   const int ib = b.lo[0] & ~3;
   if (b.hi[0] - ib + 1 < 64) return false;
   const int txv = tile_threads(b.hi[0] - ib + 1);
@@ -1892,32 +1955,42 @@ bool launch_rhs_residual(const uint64_t* counts, const double* phi, double* rhs,
   *nblocks = nb;
   const dim3 g(gx * gy * gz), blk(txv, 256 / txv);
   const int mode = chg ? (apply ? 2 : 1) : 0;
-  prof_begin(st, K_RHS);
-#define SDPM_RR(TX, M)                                                                           \
-  hipLaunchKernelGGL((k_rhs_residual_v4<T, TX, M>), g, blk, 0, st, counts, phi, rhs, r_out, chg, \
-                     n, b, c_scale, c_off, kappa, chg_scale, nb, partial)
-#define SDPM_RR_TX(M)                                                                            \
-  if (txv == 64) SDPM_RR(64, M); else if (txv == 32) SDPM_RR(32, M); else SDPM_RR(16, M)
-  if (mode == 2) {
-    SDPM_RR_TX(2);
+  const bool force = g3 != nullptr;
+  prof_begin(st, force ? K_RHS_FORCE : K_RHS);
+#define SDPM_RR(TX, M, F)                                                                        \
+  hipLaunchKernelGGL((k_rhs_residual_v4<T, TX, M, F>), g, blk, 0, st, counts, phi, rhs, r_out,   \
+                     chg, n, b, c_scale, c_off, kappa, chg_scale, nb, partial, g3, inv2h)
+#define SDPM_RR_TX(M, F)                                                                         \
+  if (txv == 64) SDPM_RR(64, M, F); else if (txv == 32) SDPM_RR(32, M, F); else SDPM_RR(16, M, F)
+  if (force) {
+    if (mode == 2) {
+      SDPM_RR_TX(2, true);
+    } else if (mode == 1) {
+      SDPM_RR_TX(1, true);
+    } else {
+      SDPM_RR_TX(0, true);
+    }
+  } else if (mode == 2) {
+    SDPM_RR_TX(2, false);
   } else if (mode == 1) {
-    SDPM_RR_TX(1);
+    SDPM_RR_TX(1, false);
   } else {
-    SDPM_RR_TX(0);
+    SDPM_RR_TX(0, false);
   }
 #undef SDPM_RR_TX
 #undef SDPM_RR
   // counts, phi and rhs 8 B each, r sizeof(T); the running change 4 B
-  // (read with a start to apply, cleared without)
-  prof_end(st, K_RHS, (24.0 + sizeof(T) + (mode ? 4.0 : 0.0)) * box_cells(b));
+  // (read with a start to apply, cleared without); the force mesh 12 B
+  prof_end(st, force ? K_RHS_FORCE : K_RHS,
+           (24.0 + sizeof(T) + (mode ? 4.0 : 0.0) + (force ? 12.0 : 0.0)) * box_cells(b));
   return true;
 }
 template bool launch_rhs_residual<float>(const uint64_t*, const double*, double*, float*, float*,
                                          bool, double, int, const Box&, double, double, double,
-                                         double*, int*, hipStream_t);
+                                         double*, int*, hipStream_t, float*, double);
 template bool launch_rhs_residual<double>(const uint64_t*, const double*, double*, double*, float*,
                                           bool, double, int, const Box&, double, double, double,
-                                          double*, int*, hipStream_t);
+                                          double*, int*, hipStream_t, float*, double);
 
 void launch_sum_phi(const double* phi, int n, const Box& b, double* partial, int* nblocks,
                     hipStream_t st) {

@@ -9,7 +9,7 @@ const char* const kKernelNames[K_NKERNELS] = {
     "coarse_lds", "interp_kick_drift", "interp_force", "count_kept", "scan_counts", "scatter",
     "copy_back", "morton_radix_sort", "gather", "conv3d_mfma", "conv3d_wgrad_mfma", "net_misc", "force_mesh", "lightcone",
     "smooth_color_coarse", "ade_sweep", "fft_3d", "fft_divide", "power_spectrum", "sweep4_fused",
-    "sweep4_fused_zero_guess", "sweep4_fused_coarse", "sweep4_fused_resid", "correct_est",
+    "sweep4_fused_zero_guess", "sweep4_fused_coarse", "sweep4_fused_resid", "correct_est", "rhs_force",
 };
 
 thread_local Profiler* g_prof = nullptr;
