@@ -80,9 +80,9 @@ def log(msg):
 # scaled by what the counter reads for a 1 GiB device-to-device copy), averaged over the
 # kernel's dispatches in the default 512^3 mixed workload (profiles/ holds the summary).
 # Valid only for the kernel source it was measured on: sweep4_fused is the 512^3 level's
-# fused post-smoothing pass, 605077.8 KiB fetched (x 1.99992 for the copy's 524308.1 KiB per
-# GiB) and 534651.8 KiB written per dispatch.
-MEASURED_TRAFFIC = {"sweep4_fused": 1786635212}
+# fused post-smoothing pass, 607228.6 KiB fetched (x 1.99992 for the copy's 524307.8 KiB per
+# GiB) and 534612.2 KiB written per dispatch.
+MEASURED_TRAFFIC = {"sweep4_fused": 1791000072}
 
 MFMA_KERNELS = ("conv3d_mfma", "conv3d_wgrad_mfma")
 BF16_PEAK_TFLOPS = 2500.0
