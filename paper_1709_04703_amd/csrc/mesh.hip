@@ -2179,8 +2179,8 @@ void launch_sweeps4(const float* e, float* e_out, const float* r, int n, float s
     // KB of LDS, 160 KB with the residual); 64 x 32 on a 64^3 mesh
     // 128-cell columns on periodic levels of 128^3 and up and on boxes in
     // meshes of 512^3 and up; 64-cell columns (two workgroups per CU) on
-    // smaller meshes and on the boxes of the 128^3 and 256^3 levels, where
-    // the chunks of 128-cell columns are short (shrinking phase at 512^3:
+    // smaller meshes and on the boxes of the 256^3 level, where the chunks
+    // of 128-cell columns are short (shrinking phase at 512^3:
     // 11.5 against 11.7 ms per step; on the periodic 256^3 level the wide
     // columns win, 0.72 against 0.86 ms per step)
     const int tx = (n >= 128 && !box) || n >= 512 ? 128 : 64;
