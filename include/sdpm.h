@@ -185,7 +185,11 @@ typedef struct sdpm_step_stats {
   int32_t outer_iters[2];  /* per field sub-step (second is 0 if static)  */
   int32_t vcycles;         /* V-cycles in this call                       */
   int32_t warm_used;       /* 1 if the learned guess was accepted         */
-  double res0[2], res[2];  /* relative residual before / after each solve */
+  double res0[2], res[2];  /* relative residual before / after each solve
+                              (after: the FP64 residual, or where the last
+                              correction's estimate r_old - A e with its
+                              rounding bound settled convergence, that
+                              estimate, within the bound of it) */
   double dtau, a_half, kappa_h2[2], r_lc;
   int32_t lo[3], hi[3], periodic;
   float ms[8];             /* [0] drift+deposit [1] rhs [2] solve 1
