@@ -743,8 +743,20 @@ k_reduce_final(const double* __restrict__ partial, int nblocks, int nslots,
                double* __restrict__ out) {
   __shared__ double sh[16];
   for (int s = 0; s < nslots; ++s) {
+    const double* p = partial + (int64_t)s * nblocks;
+    // the first 8 values of the thread loaded together, then added in the
+    // same order as the loop after them (the sum does not depend on how
+    // the loads are issued)
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = threadIdx.x + 1024 * u;
+      v[u] = t < nblocks ? p[t] : 0.0;
+    }
     double acc = 0.0;
-    for (int t = threadIdx.x; t < nblocks; t += 1024) acc += partial[(int64_t)s * nblocks + t];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+    for (int t = threadIdx.x + 8 * 1024; t < nblocks; t += 1024) acc += p[t];
     const double r = block_sum<1024>(acc, sh);
     if (threadIdx.x == 0) out[s] = r;
   }
