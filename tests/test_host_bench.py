@@ -65,3 +65,19 @@ def test_net_flops_per_voxel():
     assert bench.NET_METHOD_FLOPS_PER_VOXEL == 2 * 27 * (48 + 768 + 16) == 44928
     # kernels: every layer padded to 16 x 16 channels
     assert bench.NET_KERNEL_FLOPS_PER_VOXEL == 5 * 13824 == 69120
+
+
+def test_measured_traffic_matches_the_committed_counters():
+    # the HBM bytes per launch the bench line carries for its roofline kernel
+    # are the committed rocprofv3 summary's figures for the 512^3 level's
+    # post-smoothing pass: FETCH_SIZE scaled by the copy probe, plus WRITE_SIZE
+    import re
+    path = os.path.join(ROOT, "profiles", "pm_step_512_mixed_hbm_traffic.md")
+    text = open(path).read()
+    probe = re.search(r"dispatch 2\): FETCH_SIZE ([0-9.]+) KiB", text)
+    row = re.search(r"^\| k_sweep4<false, false, false, 16, 32, 768> \| \d+ \| \d+ \| ([0-9.]+) \| ([0-9.]+) \|",
+                    text, re.M)
+    assert probe and row
+    fetch, write = float(row.group(1)), float(row.group(2))
+    total = fetch * 1024 * 1048576 / float(probe.group(1)) + write * 1024
+    assert bench.MEASURED_TRAFFIC["sweep4_fused"] == pytest.approx(total, rel=1e-6)
