@@ -86,3 +86,29 @@ def test_acceptance_implies_fp64_check():
                np.linalg.norm(e), kappa, 0.5 * float(np.finfo(np.float32).eps))
     thresh = (est + b) * (1.0 + 1e-9)
     assert true <= thresh
+
+
+@pytest.mark.parametrize("exterior", [1.0, 1e3, 1e5])
+def test_estimate_within_bound_on_a_frozen_exterior_box(exterior):
+    # a Dirichlet box inside the mesh: the correction is zero outside it, the
+    # residuals and the norms are taken over its cells, and the frozen
+    # exterior potential (here up to 1e5 times the interior one) enters the
+    # FP64 residual evaluations at the box's faces
+    rng = np.random.Generator(np.random.PCG64(5))
+    n, kappa, lo, hi = 16, 0.113, 2, 13
+    sl = (slice(lo, hi + 1),) * 3
+    inner = (hi - lo + 1,) * 3
+    rhs = rng.normal(size=(n, n, n))
+    phi_old = rng.normal(size=(n, n, n)) * exterior
+    phi_old[sl] = rng.normal(size=inner)
+    r_old = np.zeros_like(rhs)
+    r_old[sl] = (rhs - _apply(phi_old, kappa))[sl]
+    r32 = r_old.astype(np.float32).astype(np.float64)
+    e = np.zeros_like(rhs)
+    e[sl] = (1e-2 * rng.normal(size=inner)).astype(np.float32)
+    phi_new = phi_old + e
+    true = (rhs - _apply(phi_new, kappa))[sl]
+    est = (r32 - _apply(e, kappa))[sl]
+    b = _bound(np.linalg.norm(r32[sl]), np.linalg.norm(rhs[sl]), np.linalg.norm(phi_new[sl]),
+               np.linalg.norm(e[sl]), kappa, 0.5 * float(np.finfo(np.float32).eps))
+    assert np.linalg.norm(true - est) <= b
